@@ -1,0 +1,216 @@
+"""FP64 CPU oracle of the Gadget3 interaction phase (ctypes front-end).
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It shares no code
+with the HIP library and never loads it; the product path never imports it.
+
+Every array is float64 (positions of the FP32 path are passed as the FP32
+values widened to float64); outputs are written at the active rows of
+caller-ordered arrays, like the product's.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "g3ref.cpp")
+
+GATHER, SYMMETRIC, GRAVITY = 0, 1, 2
+FLAG_FP64_DECISIONS = 1
+OK, EINVAL, ENOCONV = 0, -1, -5
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (FP64, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+               "-o", _SO + ".tmp", _SRC]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_ngb", ctypes.c_double), ("h_tol", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("theta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("G", ctypes.c_double), ("leaf_size", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+    @classmethod
+    def of(cls, p, **over) -> "Params":
+        d = {f: getattr(p, f) for f, _ in cls._fields_}
+        d.update(over)
+        return cls(**d)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.g3ref_kernel.argtypes = [dbl, dbl, P, P, P, P]
+        L.g3ref_kernel.restype = None
+        L.g3ref_key.argtypes = [P, P]
+        L.g3ref_key.restype = ctypes.c_uint64
+        L.g3ref_tree_build.argtypes = [i64, P, P, P, P, i32, i32]
+        L.g3ref_tree_build.restype = P
+        L.g3ref_tree_free.argtypes = [P]
+        L.g3ref_tree_free.restype = None
+        L.g3ref_tree_nnodes.argtypes = [P]
+        L.g3ref_tree_nnodes.restype = i64
+        L.g3ref_tree_nmembers.argtypes = [P]
+        L.g3ref_tree_nmembers.restype = i64
+        L.g3ref_tree_export.argtypes = [P] * 9
+        L.g3ref_tree_export.restype = None
+        L.g3ref_density.argtypes = [P, i64, P, P, i32, P, P, P, P, P, P]
+        L.g3ref_density.restype = ctypes.c_int
+        L.g3ref_hydro.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.g3ref_hydro.restype = ctypes.c_int
+        L.g3ref_gravity.argtypes = [P, i64, P, P, P, P, P, P]
+        L.g3ref_gravity.restype = ctypes.c_int
+        L.g3ref_lists.argtypes = [P, i32, i64, P, P, P, P, P]
+        L.g3ref_lists.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def kernel(r: float, h: float):
+    """(W, dW/dr, dW/dh, F) of the Wendland C6 kernel at (r, h)."""
+    out = [ctypes.c_double() for _ in range(4)]
+    lib().g3ref_kernel(float(r), float(h), *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def key(x, box) -> int:
+    return int(lib().g3ref_key(_ptr(_f64(x, 3)), _ptr(_f64(box, 4))))
+
+
+class Tree:
+    """Octree over all particles (gas_only=False) or over the gas ones."""
+
+    def __init__(self, pos, mass, box, type=None, leaf_size: int = 8, gas_only: bool = False):
+        self.pos = _f64(pos, (-1, 3))
+        self.mass = _f64(mass)
+        self.n = self.pos.shape[0]
+        self.type = None if type is None else np.ascontiguousarray(type, np.uint8)
+        self.box = _f64(box, 4)
+        self._h = lib().g3ref_tree_build(self.n, _ptr(self.pos), _ptr(self.mass),
+                                         _ptr(self.type), _ptr(self.box),
+                                         int(leaf_size), int(gas_only))
+        if not self._h:
+            raise ValueError("g3ref_tree_build rejected its arguments")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().g3ref_tree_free(h)
+            self._h = None
+
+    @property
+    def nnodes(self) -> int:
+        return int(lib().g3ref_tree_nnodes(self._h))
+
+    @property
+    def nmembers(self) -> int:
+        return int(lib().g3ref_tree_nmembers(self._h))
+
+    def export(self) -> dict:
+        m, k = self.nmembers, self.nnodes
+        d = dict(order=np.zeros(m, np.int64), keys=np.zeros(m, np.uint64),
+                 start=np.zeros(k, np.int64), count=np.zeros(k, np.int64),
+                 level=np.zeros(k, np.int32), skip=np.zeros(k, np.int64),
+                 mass=np.zeros(k), com=np.zeros((k, 3)))
+        lib().g3ref_tree_export(self._h, *[_ptr(d[x]) for x in
+                                ("order", "keys", "start", "count", "level", "skip", "mass", "com")])
+        return d
+
+
+def _active(n, active):
+    if active is None:
+        return np.arange(n, dtype=np.int64)
+    return np.ascontiguousarray(active, np.int64)
+
+
+def density(tree: Tree, params, active=None, h=None, solve_h: bool = True) -> dict:
+    act = _active(tree.n, active)
+    hh = np.zeros(tree.n) if h is None else _f64(h).copy()
+    out = dict(h=hh, rho=np.zeros(tree.n), drho_dh=np.zeros(tree.n),
+               omega=np.zeros(tree.n), nngb=np.zeros(tree.n, np.int32))
+    nonconv = ctypes.c_int64(0)
+    p = Params.of(params)
+    st = lib().g3ref_density(tree._h, act.size, _ptr(act), ctypes.byref(p), int(solve_h),
+                             _ptr(hh), _ptr(out["rho"]), _ptr(out["drho_dh"]),
+                             _ptr(out["omega"]), _ptr(out["nngb"]), ctypes.byref(nonconv))
+    if st not in (OK, ENOCONV):
+        raise ValueError(f"g3ref_density status {st}")
+    out["nonconv"] = int(nonconv.value)
+    out["status"] = st
+    return out
+
+
+def hydro(tree: Tree, params, vel, u, h, rho, omega, active=None) -> dict:
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(acc=np.zeros((n, 3)), dudt=np.zeros(n), vsig=np.zeros(n), S=np.zeros(n),
+               npairs=np.zeros(n, np.int32))
+    ins = [_f64(vel, (-1, 3)), _f64(u), _f64(h), _f64(rho), _f64(omega)]
+    p = Params.of(params)
+    st = lib().g3ref_hydro(tree._h, act.size, _ptr(act), ctypes.byref(p),
+                           *[_ptr(a) for a in ins],
+                           *[_ptr(out[k]) for k in ("acc", "dudt", "vsig", "S", "npairs")])
+    if st != OK:
+        raise ValueError(f"g3ref_hydro status {st}")
+    return out
+
+
+def gravity(tree: Tree, params, active=None) -> dict:
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(acc=np.zeros((n, 3)), pot=np.zeros(n), S=np.zeros(n),
+               nterms=np.zeros(n, np.int32))
+    p = Params.of(params)
+    st = lib().g3ref_gravity(tree._h, act.size, _ptr(act), ctypes.byref(p),
+                             *[_ptr(out[k]) for k in ("acc", "pot", "S", "nterms")])
+    if st != OK:
+        raise ValueError(f"g3ref_gravity status {st}")
+    return out
+
+
+def lists(tree: Tree, params, kind: int, active=None, h=None):
+    """CSR (offsets, list) of the interaction lists, each row sorted."""
+    act = _active(tree.n, active)
+    hh = None if h is None else _f64(h)
+    p = Params.of(params)
+    off = np.zeros(act.size + 1, np.int64)
+    st = lib().g3ref_lists(tree._h, int(kind), act.size, _ptr(act), ctypes.byref(p),
+                           _ptr(hh), _ptr(off), None)
+    if st != OK:
+        raise ValueError(f"g3ref_lists status {st}")
+    lst = np.zeros(int(off[-1]), np.int64)
+    lib().g3ref_lists(tree._h, int(kind), act.size, _ptr(act), ctypes.byref(p),
+                      _ptr(hh), _ptr(off), _ptr(lst))
+    return off, lst

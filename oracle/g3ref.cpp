@@ -1,0 +1,628 @@
+/*
+ * g3ref.cpp - FP64 CPU oracle of the Gadget3 interaction phase.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path. It shares no code
+ * with the HIP library. Written for clarity, not speed: every function is the
+ * plain definition (for sums over neighbours) or the algorithm's steps in the
+ * order the method states them (Barnes-Hut walk, bisection for h).
+ *
+ * The paper (arXiv 2003.10850) names the modules but prints no formula; the
+ * published methods used are cited at each function.
+ */
+#include "g3ref.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+/* Wendland C6 normalisation in 3D: 1365 / (64 pi) (Dehnen & Aly 2012, tab. 1) */
+const double kWc6 = 1365.0 / (64.0 * kPi);
+const int kMaxLevel = 21; /* 21 bits per axis, 63-bit Morton keys */
+
+/* ------------------------------------------------------------------ kernel */
+
+/* Wendland C6 with compact support radius h (Gadget convention):
+ *   W(r,h)   = C/h^3 (1-q)^8 (1 + 8q + 25q^2 + 32q^3),  q = r/h < 1
+ *   dW/dr    = -22 C/h^4 q (1-q)^7 (1 + 7q + 16q^2)
+ *   F        = (1/r) dW/dr = -22 C/h^5 (1-q)^7 (1 + 7q + 16q^2)
+ *   dW/dh    = C/h^4 (1-q)^7 (448q^4 + 133q^3 - 29q^2 - 21q - 3)
+ * (the last equals -(3W + r dW/dr)/h; both are pinned by tests). */
+void wc6(double r, double h, double *W, double *dWdr, double *dWdh, double *F) {
+  const double q = r / h;
+  if (!(q < 1.0)) {
+    *W = *dWdr = *dWdh = *F = 0.0;
+    return;
+  }
+  const double t = 1.0 - q;
+  const double t2 = t * t, t4 = t2 * t2, t7 = t4 * t2 * t, t8 = t7 * t;
+  const double h3 = h * h * h, h4 = h3 * h, h5 = h4 * h;
+  const double p8 = 1.0 + q * (8.0 + q * (25.0 + q * 32.0));
+  const double p7 = 1.0 + q * (7.0 + q * 16.0);
+  const double ph = -3.0 + q * (-21.0 + q * (-29.0 + q * (133.0 + q * 448.0)));
+  *W = kWc6 / h3 * t8 * p8;
+  *dWdr = -22.0 * kWc6 / h4 * q * t7 * p7;
+  *F = -22.0 * kWc6 / h5 * t7 * p7;
+  *dWdh = kWc6 / h4 * t7 * ph;
+}
+
+double wc6_W(double r, double h) {
+  double W, a, b, c;
+  wc6(r, h, &W, &a, &b, &c);
+  return W;
+}
+
+/* ------------------------------------------------------------------- keys */
+
+uint32_t cell_of(double x, double lo, double scale) {
+  double f = std::floor((x - lo) * scale);
+  const double top = (double)((1u << kMaxLevel) - 1u);
+  if (!(f >= 0.0)) f = 0.0;
+  if (f > top) f = top;
+  return (uint32_t)f;
+}
+
+/* Interleave three 21-bit integers, x highest within each 3-bit digit, most
+ * significant digit first: digit l (1-based level) selects the child octant
+ * at tree level l. */
+uint64_t interleave(uint32_t ix, uint32_t iy, uint32_t iz) {
+  uint64_t k = 0;
+  for (int b = kMaxLevel - 1; b >= 0; --b)
+    k = (k << 3) | ((uint64_t)((ix >> b) & 1u) << 2) |
+        ((uint64_t)((iy >> b) & 1u) << 1) | (uint64_t)((iz >> b) & 1u);
+  return k;
+}
+
+double key_scale(double L) { return std::ldexp(1.0, kMaxLevel) / L; }
+
+} // namespace
+
+/* ------------------------------------------------------------------- tree */
+
+struct RefNode {
+  int64_t start = 0, count = 0, skip = 0;
+  int32_t level = 0;
+  uint32_t cx = 0, cy = 0, cz = 0; /* integer cube coordinates at level */
+  double l = 0.0;                  /* cube side */
+  double clo[3] = {0, 0, 0};       /* cube lower corner */
+  double M = 0.0, com[3] = {0, 0, 0};
+  std::vector<int64_t> child;      /* preorder indices, Morton order */
+};
+
+struct g3ref_tree {
+  int64_t n = 0;              /* length of the caller arrays */
+  std::vector<double> pos;    /* [n][3] */
+  std::vector<double> mass;   /* [n] */
+  std::vector<uint8_t> type;  /* [n] */
+  std::vector<uint32_t> cell; /* [n][3] integer key coordinates */
+  double box[4] = {0, 0, 0, 1};
+  int32_t leaf = 8;
+  std::vector<int64_t> order; /* sorted member -> caller id */
+  std::vector<uint64_t> keys; /* sorted member keys */
+  std::vector<RefNode> nodes; /* preorder */
+};
+
+namespace {
+
+/* A node is the set of members sharing a 3*level-bit key prefix; it is
+ * subdivided while it holds more than leaf members and level < 21; empty
+ * octants make no node and single-child chains are kept (Barnes & Hut 1986
+ * octree, here over Morton-sorted members). */
+int64_t subdivide(g3ref_tree &t, int64_t s, int64_t e, int32_t level) {
+  const int64_t idx = (int64_t)t.nodes.size();
+  t.nodes.emplace_back();
+  std::vector<int64_t> kids;
+  if (e - s > t.leaf && level < kMaxLevel) {
+    const int shift = 3 * (kMaxLevel - level - 1);
+    int64_t a = s;
+    while (a < e) {
+      const uint64_t d = (t.keys[a] >> shift) & 7u;
+      int64_t b = a;
+      while (b < e && ((t.keys[b] >> shift) & 7u) == d) ++b;
+      kids.push_back(subdivide(t, a, b, level + 1));
+      a = b;
+    }
+  }
+  RefNode &nd = t.nodes[idx];
+  nd.start = s;
+  nd.count = e - s;
+  nd.level = level;
+  nd.child = kids;
+  nd.skip = (int64_t)t.nodes.size();
+  const int64_t first = t.order[s];
+  const int sh = kMaxLevel - level;
+  nd.cx = t.cell[3 * first + 0] >> sh;
+  nd.cy = t.cell[3 * first + 1] >> sh;
+  nd.cz = t.cell[3 * first + 2] >> sh;
+  nd.l = std::ldexp(t.box[3], -level);
+  nd.clo[0] = t.box[0] + nd.cx * nd.l;
+  nd.clo[1] = t.box[1] + nd.cy * nd.l;
+  nd.clo[2] = t.box[2] + nd.cz * nd.l;
+  return idx;
+}
+
+bool inside_cube(const g3ref_tree &t, int64_t i, const RefNode &nd) {
+  const int sh = kMaxLevel - nd.level;
+  return (t.cell[3 * i + 0] >> sh) == nd.cx && (t.cell[3 * i + 1] >> sh) == nd.cy &&
+         (t.cell[3 * i + 2] >> sh) == nd.cz;
+}
+
+/* squared distance from x to the node's cube (0 inside) */
+double cube_dist2(const RefNode &nd, const double *x) {
+  double d2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double lo = nd.clo[a], hi = nd.clo[a] + nd.l, d = 0.0;
+    if (x[a] < lo) d = lo - x[a];
+    else if (x[a] > hi) d = x[a] - hi;
+    d2 += d * d;
+  }
+  return d2;
+}
+
+/* Collect members j of leaves whose cube lies within radius R(node) of x
+ * (R may depend on the node, e.g. the symmetric search). Pruning only. */
+template <class Radius, class Visit>
+void walk_leaves(const g3ref_tree &t, int64_t k, const double *x, Radius R, Visit visit) {
+  const RefNode &nd = t.nodes[k];
+  const double r = R(k);
+  if (cube_dist2(nd, x) > r * r) return;
+  if (nd.child.empty()) {
+    for (int64_t s = nd.start; s < nd.start + nd.count; ++s) visit(t.order[s]);
+    return;
+  }
+  for (int64_t c : nd.child) walk_leaves(t, c, x, R, visit);
+}
+
+const double kPruneMargin = 1.0 + 1e-5; /* FP32 predicate vs FP64 pruning */
+
+/* Neighbour predicate. FP32 (default): dx = fl32(x_j - x_i) per axis,
+ * r2 = fmaf(dz,dz, fmaf(dy,dy, dx*dx)), true iff r2 < fl32(H*H) with H the
+ * FP32 radius. FP64 with G3REF_FLAG_FP64_DECISIONS. */
+bool within(const g3ref_tree &t, int64_t i, int64_t j, double H, int32_t flags) {
+  const double *xi = &t.pos[3 * i], *xj = &t.pos[3 * j];
+  if (flags & G3REF_FLAG_FP64_DECISIONS) {
+    const double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+    return dx * dx + dy * dy + dz * dz < H * H;
+  }
+  const float dx = (float)xj[0] - (float)xi[0];
+  const float dy = (float)xj[1] - (float)xi[1];
+  const float dz = (float)xj[2] - (float)xi[2];
+  const float r2 = std::fmaf(dz, dz, std::fmaf(dy, dy, dx * dx));
+  const float hf = (float)H;
+  const float h2 = hf * hf;
+  return r2 < h2;
+}
+
+double dist(const g3ref_tree &t, int64_t i, int64_t j) {
+  const double *xi = &t.pos[3 * i], *xj = &t.pos[3 * j];
+  const double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
+  return std::sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+bool is_gas(const g3ref_tree &t, int64_t j) { return t.type[j] == 0; }
+
+/* --------------------------------------------------------------- density */
+
+/* rho(h) = sum_j m_j W(r_ij, h) over gas j with r_ij < h (self included),
+ * FP64 membership: the continuous function the root solve works on. */
+double rho_at(const g3ref_tree &t, int64_t i, double h) {
+  const double *xi = &t.pos[3 * i];
+  double rho = 0.0;
+  walk_leaves(t, 0, xi, [&](int64_t) { return h * kPruneMargin; }, [&](int64_t j) {
+    if (!is_gas(t, j)) return;
+    const double r = dist(t, i, j);
+    if (r < h) rho += t.mass[j] * wc6_W(r, h);
+  });
+  return rho;
+}
+
+/* Mass-weighted neighbour number N_eff(h) = (4 pi / 3) h^3 rho(h) / m_i
+ * (Springel & Hernquist 2002, eq. 6). */
+double n_eff(const g3ref_tree &t, int64_t i, double h) {
+  return 4.0 * kPi / 3.0 * h * h * h * rho_at(t, i, h) / t.mass[i];
+}
+
+/* Root of N_eff(h) = N_ngb by bracketing and bisection:
+ *   start at the mean-density estimate h0 = (3 N_ngb m_i / (4 pi rho_bar))^(1/3);
+ *   double (or halve) until N_eff(lo) < N_ngb <= N_eff(hi);
+ *   bisect while hi - lo > tol * hi; return the midpoint.
+ * Returns false if the bracket reaches the cap 2 x box diagonal. */
+bool solve_h(const g3ref_tree &t, int64_t i, const g3ref_params &p, double rho_bar,
+             double *h_out) {
+  const double cap = 2.0 * std::sqrt(3.0) * t.box[3];
+  const double target = p.n_ngb;
+  double h0 = std::cbrt(3.0 * target * t.mass[i] / (4.0 * kPi * rho_bar));
+  if (!(h0 > 0.0) || h0 > cap) h0 = std::min(cap, t.box[3]);
+  double lo, hi;
+  if (n_eff(t, i, h0) < target) {
+    lo = h0;
+    hi = 2.0 * h0;
+    while (n_eff(t, i, hi) < target) {
+      lo = hi;
+      hi = 2.0 * hi;
+      if (hi > cap) {
+        *h_out = cap;
+        return false;
+      }
+    }
+  } else {
+    hi = h0;
+    lo = 0.5 * h0;
+    while (n_eff(t, i, lo) >= target) {
+      hi = lo;
+      lo = 0.5 * lo;
+    }
+  }
+  while (hi - lo > p.h_tol * hi) {
+    const double mid = 0.5 * (lo + hi);
+    if (n_eff(t, i, mid) < target) lo = mid;
+    else hi = mid;
+  }
+  *h_out = 0.5 * (lo + hi);
+  return true;
+}
+
+} // namespace
+
+extern "C" {
+
+void g3ref_kernel(double r, double h, double *W, double *dWdr, double *dWdh, double *F) {
+  wc6(r, h, W, dWdr, dWdh, F);
+}
+
+uint64_t g3ref_key(const double *x, const double *box) {
+  const double s = key_scale(box[3]);
+  return interleave(cell_of(x[0], box[0], s), cell_of(x[1], box[1], s),
+                    cell_of(x[2], box[2], s));
+}
+
+g3ref_tree *g3ref_tree_build(int64_t n, const double *pos, const double *mass,
+                             const uint8_t *type, const double *box, int32_t leaf_size,
+                             int32_t gas_only) {
+  if (n < 0 || (n > 0 && (!pos || !mass)) || !box || !(box[3] > 0.0) || leaf_size < 1)
+    return nullptr;
+  g3ref_tree *t = new g3ref_tree;
+  t->n = n;
+  t->pos.assign(pos, pos + 3 * n);
+  t->mass.assign(mass, mass + n);
+  t->type.assign((size_t)n, 0);
+  if (type) t->type.assign(type, type + n);
+  std::memcpy(t->box, box, sizeof(t->box));
+  t->leaf = leaf_size;
+  t->cell.resize(3 * (size_t)n);
+  const double s = key_scale(box[3]);
+  std::vector<uint64_t> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) t->cell[3 * i + a] = cell_of(pos[3 * i + a], box[a], s);
+    key[i] = interleave(t->cell[3 * i], t->cell[3 * i + 1], t->cell[3 * i + 2]);
+    if (!gas_only || t->type[i] == 0) t->order.push_back(i);
+  }
+  /* Morton order; equal keys keep caller order */
+  std::sort(t->order.begin(), t->order.end(), [&](int64_t a, int64_t b) {
+    return key[a] < key[b] || (key[a] == key[b] && a < b);
+  });
+  for (int64_t i : t->order) t->keys.push_back(key[i]);
+  if (!t->order.empty()) subdivide(*t, 0, (int64_t)t->order.size(), 0);
+  /* monopole moments in FP64: M = sum m, com = sum m x / M */
+  for (RefNode &nd : t->nodes) {
+    double M = 0.0, S[3] = {0, 0, 0};
+    for (int64_t k = nd.start; k < nd.start + nd.count; ++k) {
+      const int64_t j = t->order[k];
+      M += t->mass[j];
+      for (int a = 0; a < 3; ++a) S[a] += t->mass[j] * t->pos[3 * j + a];
+    }
+    nd.M = M;
+    for (int a = 0; a < 3; ++a) nd.com[a] = M > 0.0 ? S[a] / M : nd.clo[a] + 0.5 * nd.l;
+  }
+  return t;
+}
+
+void g3ref_tree_free(g3ref_tree *t) { delete t; }
+int64_t g3ref_tree_nnodes(const g3ref_tree *t) { return t ? (int64_t)t->nodes.size() : 0; }
+int64_t g3ref_tree_nmembers(const g3ref_tree *t) { return t ? (int64_t)t->order.size() : 0; }
+
+void g3ref_tree_export(const g3ref_tree *t, int64_t *order, uint64_t *keys,
+                       int64_t *node_start, int64_t *node_count, int32_t *node_level,
+                       int64_t *node_skip, double *node_mass, double *node_com) {
+  for (size_t k = 0; k < t->order.size(); ++k) {
+    if (order) order[k] = t->order[k];
+    if (keys) keys[k] = t->keys[k];
+  }
+  for (size_t k = 0; k < t->nodes.size(); ++k) {
+    const RefNode &nd = t->nodes[k];
+    if (node_start) node_start[k] = nd.start;
+    if (node_count) node_count[k] = nd.count;
+    if (node_level) node_level[k] = nd.level;
+    if (node_skip) node_skip[k] = nd.skip;
+    if (node_mass) node_mass[k] = nd.M;
+    if (node_com)
+      for (int a = 0; a < 3; ++a) node_com[3 * k + a] = nd.com[a];
+  }
+}
+
+static bool valid_params(const g3ref_params *p) {
+  return p && p->leaf_size >= 1;
+}
+
+/* Density at the active gas particles (Springel & Hernquist 2002):
+ *   rho_i    = sum_j m_j W(r_ij, h_i)            (self included)
+ *   drho/dh  = sum_j m_j dW/dh(r_ij, h_i)
+ *   Omega_i  = 1 + h_i / (3 rho_i) drho/dh
+ *   n_i      = number of gas j meeting the neighbour predicate at h_i.
+ * With solve_h, h_i is first found by solve_h() above. */
+int g3ref_density(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                  const g3ref_params *p, int32_t solve, double *h, double *rho,
+                  double *drho_dh, double *omega, int32_t *nngb, int64_t *nonconv) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !h)
+    return G3REF_EINVAL;
+  if (solve && !(p->n_ngb > 1365.0 / 48.0)) return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+  double gas_mass = 0.0;
+  for (int64_t j : t.order) gas_mass += t.mass[j];
+  const double rho_bar = gas_mass / (t.box[3] * t.box[3] * t.box[3]);
+  int64_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : bad)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    if (solve) {
+      double hs;
+      if (!solve_h(t, i, *p, rho_bar, &hs)) ++bad;
+      h[i] = hs;
+    }
+    const double hi = h[i];
+    const double *xi = &t.pos[3 * i];
+    double r_ = 0.0, dr = 0.0;
+    int32_t cnt = 0;
+    walk_leaves(t, 0, xi, [&](int64_t) { return hi * kPruneMargin; }, [&](int64_t j) {
+      if (!is_gas(t, j) || !within(t, i, j, hi, p->flags)) return;
+      double W, dWdr, dWdh, F;
+      wc6(dist(t, i, j), hi, &W, &dWdr, &dWdh, &F);
+      r_ += t.mass[j] * W;
+      dr += t.mass[j] * dWdh;
+      ++cnt;
+    });
+    if (rho) rho[i] = r_;
+    if (drho_dh) drho_dh[i] = dr;
+    if (omega) omega[i] = 1.0 + hi / (3.0 * r_) * dr;
+    if (nngb) nngb[i] = cnt;
+  }
+  if (nonconv) *nonconv = bad;
+  return bad ? G3REF_ENOCONV : G3REF_OK;
+}
+
+/* Hydro acceleration, du/dt and maximum signal velocity of the active gas
+ * particles: the grad-h SPH equations in energy form (Springel 2005, eqs.
+ * 7 and 13-14) with the signal-velocity viscosity of Monaghan (1997) as used
+ * by Gadget-2. Pairs: gas j != i with r < max(h_i, h_j) (neighbour predicate);
+ * pairs at zero separation add nothing.
+ *   P = (gamma-1) rho u,  c = sqrt(gamma (gamma-1) u),  A = P / (Omega rho^2)
+ *   g_i = F(r, h_i), g_j = F(r, h_j), gbar = (g_i + g_j) / 2
+ *   a_i   -= m_j (A_i g_i + A_j g_j) x_ij
+ *   w = v_ij . x_ij / r;  if w < 0: v_sig = c_i + c_j - 3w,
+ *        Pi = -(alpha/2) v_sig w / ((rho_i + rho_j)/2)    else Pi = 0
+ *   a_i   -= m_j Pi gbar x_ij
+ *   du_i  += m_j A_i g_i v_ij.x_ij + (1/2) m_j Pi gbar v_ij.x_ij
+ *   vsig_i = max_j (c_i + c_j - 3 min(w, 0))   (0 with no pair) */
+int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                const g3ref_params *p, const double *vel, const double *u, const double *h,
+                const double *rho, const double *omega, double *acc, double *dudt,
+                double *vsig, double *S, int32_t *npairs) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !vel || !u ||
+      !h || !rho || !omega)
+    return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+  const double gm = p->gamma;
+  /* node hmax: largest h among the node's gas members (search radius) */
+  std::vector<double> hmax(t.nodes.size(), 0.0);
+  for (size_t k = 0; k < t.nodes.size(); ++k)
+    for (int64_t s = t.nodes[k].start; s < t.nodes[k].start + t.nodes[k].count; ++s)
+      hmax[k] = std::max(hmax[k], h[t.order[s]]);
+  auto A_of = [&](int64_t j) {
+    const double P = (gm - 1.0) * rho[j] * u[j];
+    return P / (omega[j] * rho[j] * rho[j]);
+  };
+  auto c_of = [&](int64_t j) { return std::sqrt(gm * (gm - 1.0) * u[j]); };
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    const double *xi = &t.pos[3 * i];
+    const double Ai = A_of(i), ci = c_of(i), hi = h[i];
+    double ax = 0, ay = 0, az = 0, du = 0, vs = 0, s = 0;
+    int32_t cnt = 0;
+    walk_leaves(t, 0, xi, [&](int64_t k) { return std::max(hi, hmax[k]) * kPruneMargin; },
+                [&](int64_t j) {
+      if (j == i || !is_gas(t, j)) return;
+      const double hm = std::max(hi, h[j]);
+      if (!within(t, i, j, hm, p->flags)) return;
+      ++cnt;
+      const double r = dist(t, i, j);
+      if (!(r > 0.0)) return;
+      const double x[3] = {xi[0] - t.pos[3 * j], xi[1] - t.pos[3 * j + 1],
+                           xi[2] - t.pos[3 * j + 2]};
+      const double v[3] = {vel[3 * i] - vel[3 * j], vel[3 * i + 1] - vel[3 * j + 1],
+                           vel[3 * i + 2] - vel[3 * j + 2]};
+      double W, dWdr, dWdh, gi, gj;
+      wc6(r, hi, &W, &dWdr, &dWdh, &gi);
+      wc6(r, h[j], &W, &dWdr, &dWdh, &gj);
+      const double Aj = A_of(j), cj = c_of(j), mj = t.mass[j];
+      const double vx = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
+      const double w = vx / r;
+      double Pi = 0.0;
+      if (w < 0.0) {
+        const double vsig_ij = ci + cj - 3.0 * w;
+        Pi = -0.5 * p->alpha * vsig_ij * w / (0.5 * (rho[i] + rho[j]));
+      }
+      vs = std::max(vs, ci + cj - 3.0 * std::min(w, 0.0));
+      const double gbar = 0.5 * (gi + gj);
+      const double tp = -mj * (Ai * gi + Aj * gj);
+      const double tv = -mj * Pi * gbar;
+      ax += (tp + tv) * x[0];
+      ay += (tp + tv) * x[1];
+      az += (tp + tv) * x[2];
+      du += mj * Ai * gi * vx + 0.5 * mj * Pi * gbar * vx;
+      s += (std::fabs(tp) + std::fabs(tv)) * r;
+    });
+    if (acc) {
+      acc[3 * i] = ax;
+      acc[3 * i + 1] = ay;
+      acc[3 * i + 2] = az;
+    }
+    if (dudt) dudt[i] = du;
+    if (vsig) vsig[i] = vs;
+    if (S) S[i] = s;
+    if (npairs) npairs[i] = cnt;
+  }
+  return G3REF_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+/* Barnes-Hut opening test for target i and node nd (Barnes & Hut 1986):
+ * accept the monopole iff x_i is outside the node's half-open cube and
+ * l < theta |x_i - c|. FP32 (default): dx = fl32(fl32(c) - x_i),
+ * r2 = fmaf(dz,dz, fmaf(dy,dy, dx*dx)), accept iff fl32(l)^2 < fl32(theta^2) r2
+ * with every product rounded to FP32. */
+bool bh_accept(const g3ref_tree &t, int64_t i, const RefNode &nd, double theta, int32_t flags) {
+  if (inside_cube(t, i, nd)) return false;
+  const double *xi = &t.pos[3 * i];
+  if (flags & G3REF_FLAG_FP64_DECISIONS) {
+    const double dx = nd.com[0] - xi[0], dy = nd.com[1] - xi[1], dz = nd.com[2] - xi[2];
+    return nd.l * nd.l < theta * theta * (dx * dx + dy * dy + dz * dz);
+  }
+  const float dx = (float)nd.com[0] - (float)xi[0];
+  const float dy = (float)nd.com[1] - (float)xi[1];
+  const float dz = (float)nd.com[2] - (float)xi[2];
+  const float r2 = std::fmaf(dz, dz, std::fmaf(dy, dy, dx * dx));
+  const float lf = (float)nd.l;
+  const float lhs = lf * lf;
+  const float th2 = (float)(theta * theta);
+  const float rhs = th2 * r2;
+  return lhs < rhs;
+}
+
+/* Per-particle Barnes-Hut walk: preorder from the root, children in Morton
+ * order; an accepted node contributes its monopole, a leaf that is not
+ * accepted contributes each member j != i, other nodes are opened. */
+template <class Term>
+void bh_walk(const g3ref_tree &t, int64_t k, int64_t i, double theta, int32_t flags, Term term) {
+  const RefNode &nd = t.nodes[k];
+  if (bh_accept(t, i, nd, theta, flags)) {
+    term(nd.M, nd.com, -(k + 1));
+    return;
+  }
+  if (nd.child.empty()) {
+    for (int64_t s = nd.start; s < nd.start + nd.count; ++s) {
+      const int64_t j = t.order[s];
+      if (j != i) term(t.mass[j], &t.pos[3 * j], j);
+    }
+    return;
+  }
+  for (int64_t c : nd.child) bh_walk(t, c, i, theta, flags, term);
+}
+
+} // namespace
+
+extern "C" {
+
+/* Softened gravity of the active particles from every particle:
+ *   a_i   += -G m x_ij / (r^2 + eps^2)^(3/2)
+ *   phi_i += -G m / (r^2 + eps^2)^(1/2)
+ * for each particle term (j != i) and each accepted node (mass M, at its
+ * centre of mass), with x_ij = x_i - x_source. */
+int g3ref_gravity(const g3ref_tree *all, int64_t n_act, const int64_t *active,
+                  const g3ref_params *p, double *acc, double *pot, double *S,
+                  int32_t *nterms) {
+  if (!all || !valid_params(p) || n_act < 0 || (n_act > 0 && !active)) return G3REF_EINVAL;
+  const g3ref_tree &t = *all;
+  const double e2 = p->eps * p->eps, G = p->G;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n) continue;
+    const double *xi = &t.pos[3 * i];
+    double ax = 0, ay = 0, az = 0, ph = 0, s = 0;
+    int32_t cnt = 0;
+    if (!t.nodes.empty())
+      bh_walk(t, 0, i, p->theta, p->flags, [&](double m, const double *c, int64_t) {
+        const double x[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
+        const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const double inv = 1.0 / std::sqrt(r2 + e2);
+        const double inv3 = inv * inv * inv;
+        ax -= G * m * x[0] * inv3;
+        ay -= G * m * x[1] * inv3;
+        az -= G * m * x[2] * inv3;
+        ph -= G * m * inv;
+        s += G * m * std::sqrt(r2) * inv3;
+        ++cnt;
+      });
+    if (acc) {
+      acc[3 * i] = ax;
+      acc[3 * i + 1] = ay;
+      acc[3 * i + 2] = az;
+    }
+    if (pot) pot[i] = ph;
+    if (S) S[i] = s;
+    if (nterms) nterms[i] = cnt;
+  }
+  return G3REF_OK;
+}
+
+int g3ref_lists(const g3ref_tree *tp, int32_t kind, int64_t n_act, const int64_t *active,
+                const g3ref_params *p, const double *h, int64_t *offsets, int64_t *list) {
+  if (!tp || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !offsets)
+    return G3REF_EINVAL;
+  if ((kind == G3REF_GATHER || kind == G3REF_SYMMETRIC) && !h) return G3REF_EINVAL;
+  if (kind < G3REF_GATHER || kind > G3REF_GRAVITY) return G3REF_EINVAL;
+  const g3ref_tree &t = *tp;
+  std::vector<double> hmax;
+  if (kind == G3REF_SYMMETRIC) {
+    hmax.assign(t.nodes.size(), 0.0);
+    for (size_t k = 0; k < t.nodes.size(); ++k)
+      for (int64_t s = t.nodes[k].start; s < t.nodes[k].start + t.nodes[k].count; ++s)
+        hmax[k] = std::max(hmax[k], h[t.order[s]]);
+  }
+  std::vector<std::vector<int64_t>> out((size_t)n_act);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    std::vector<int64_t> &L = out[a];
+    if (i < 0 || i >= t.n || t.nodes.empty()) continue;
+    const double *xi = &t.pos[3 * i];
+    if (kind == G3REF_GRAVITY) {
+      bh_walk(t, 0, i, p->theta, p->flags,
+              [&](double, const double *, int64_t id) { L.push_back(id); });
+    } else {
+      if (!is_gas(t, i)) continue;
+      const double hi = h[i];
+      if (kind == G3REF_GATHER) {
+        walk_leaves(t, 0, xi, [&](int64_t) { return hi * kPruneMargin; }, [&](int64_t j) {
+          if (is_gas(t, j) && within(t, i, j, hi, p->flags)) L.push_back(j);
+        });
+      } else {
+        walk_leaves(t, 0, xi, [&](int64_t k) { return std::max(hi, hmax[k]) * kPruneMargin; },
+                    [&](int64_t j) {
+          if (j != i && is_gas(t, j) && within(t, i, j, std::max(hi, h[j]), p->flags))
+            L.push_back(j);
+        });
+      }
+    }
+    std::sort(L.begin(), L.end());
+  }
+  offsets[0] = 0;
+  for (int64_t a = 0; a < n_act; ++a) offsets[a + 1] = offsets[a] + (int64_t)out[a].size();
+  if (list)
+    for (int64_t a = 0; a < n_act; ++a)
+      std::copy(out[a].begin(), out[a].end(), list + offsets[a]);
+  return G3REF_OK;
+}
+
+} // extern "C"

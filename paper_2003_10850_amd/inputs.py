@@ -1,0 +1,149 @@
+"""Seeded synthetic particle sets for the interaction phase.
+
+This module only draws inputs. It holds none of the method's arithmetic
+(no kernel, no tree, no force); both the HIP path and the CPU oracle read
+what it returns, and neither is imported here.
+
+The paper profiles Magneticum boxes (Box4/hr with 2e7 particles, Box3/hr,
+Box2/hr; sections 1 and 3), which are not available. These generators stand
+in for them with the same scale and the same kind of structure: a clustered
+particle distribution (dense haloes on a smooth background, as in the
+paper's first figure) made of Plummer spheres on a uniform background, with
+gas and collisionless species mixed half and half.
+
+Workloads (all in a unit box, non-periodic, G = 1, equal masses 1/N):
+
+* ``uniform``   - N gas particles uniform in [0,1)^3, zero velocities,
+  u = 1; 64 target neighbours, eps = 0.01 (the 4096-particle case the
+  oracle finishes in seconds).
+* ``plummer``   - N particles, half gas and half collisionless, 80 % drawn
+  from ``n_spheres`` Plummer spheres (scale radius 0.02, masses log-uniform
+  over one decade, centres uniform in [0.1, 0.9]^3) and 20 % uniform,
+  Gaussian velocities sigma = 0.1, u = 1; 295 target neighbours,
+  eps = 1e-3 (the 2^21-particle paper-like case).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+GAS = 0
+COLLISIONLESS = 1
+
+
+@dataclass
+class Params:
+    """Result-defining parameters of one workload (plain numbers, no maths)."""
+    n_ngb: float = 64.0        # target (mass-weighted) neighbour number
+    h_tol: float = 1e-6        # relative bracket width of the h root solve
+    gamma: float = 5.0 / 3.0   # adiabatic index
+    alpha: float = 1.0         # artificial-viscosity strength
+    theta: float = 0.5         # Barnes-Hut opening angle
+    eps: float = 0.01          # Plummer softening length
+    G: float = 1.0             # gravitational constant
+    leaf_size: int = 8         # maximum particles in an octree leaf
+    flags: int = 0
+
+
+@dataclass
+class Workload:
+    name: str
+    pos: np.ndarray            # [N,3] float64 draws (cast per precision)
+    vel: np.ndarray            # [N,3] float64
+    mass: np.ndarray           # [N]   float64
+    u: np.ndarray              # [N]   float64 specific internal energy
+    type: np.ndarray           # [N]   uint8, 0 gas / 1 collisionless
+    box: np.ndarray            # [4]   lo xyz + side
+    params: Params = field(default_factory=Params)
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def as_f32(self):
+        """The FP32 arrays the plain path computes on (pos, vel, mass, u)."""
+        return (self.pos.astype(np.float32), self.vel.astype(np.float32),
+                self.mass.astype(np.float32), self.u.astype(np.float32))
+
+
+def uniform(n: int = 4096, seed: int = 0) -> Workload:
+    """N gas particles uniform in the unit cube, m = 1/N, v = 0, u = 1."""
+    rng = np.random.default_rng(seed)
+    pos = rng.random((n, 3))
+    return Workload(
+        name=f"uniform_n{n}_seed{seed}", pos=pos, vel=np.zeros((n, 3)),
+        mass=np.full(n, 1.0 / n), u=np.ones(n),
+        type=np.zeros(n, np.uint8), box=np.array([0.0, 0.0, 0.0, 1.0]),
+        params=Params(n_ngb=64.0, eps=0.01), seed=seed)
+
+
+def _plummer_radii(rng, a, k):
+    x = rng.random(k)
+    x = np.clip(x, 1e-300, 1.0)
+    return a / np.sqrt(np.maximum(x ** (-2.0 / 3.0) - 1.0, 1e-300))
+
+
+def _directions(rng, k):
+    z = rng.uniform(-1.0, 1.0, k)
+    phi = rng.uniform(0.0, 2.0 * np.pi, k)
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
+def plummer(n: int = 1 << 21, n_spheres: int = 32, seed: int = 1,
+            scale_radius: float = 0.02, background: float = 0.2,
+            n_ngb: float = 295.0, eps: float = 1e-3,
+            sigma_v: float = 0.1) -> Workload:
+    """Clustered set: Plummer spheres on a uniform background, half gas."""
+    rng = np.random.default_rng(seed)
+    n_bg = int(round(background * n))
+    n_cl = n - n_bg
+    centres = rng.uniform(0.1, 0.9, (n_spheres, 3))
+    smass = 10.0 ** rng.random(n_spheres)
+    share = smass / smass.sum() * n_cl
+    counts = np.floor(share).astype(np.int64)
+    rest = n_cl - counts.sum()
+    if rest > 0:  # largest remainders get the leftover particles
+        counts[np.argsort(-(share - counts), kind="stable")[:rest]] += 1
+    pos = np.empty((n, 3))
+    k0 = 0
+    for s in range(n_spheres):
+        need = int(counts[s])
+        got = []
+        while need > 0:
+            r = _plummer_radii(rng, scale_radius, need)
+            p = centres[s] + r[:, None] * _directions(rng, need)
+            ok = np.all((p >= 0.0) & (p < 1.0), axis=1)
+            got.append(p[ok])
+            need -= int(ok.sum())
+        pos[k0:k0 + counts[s]] = np.concatenate(got)[:counts[s]]
+        k0 += int(counts[s])
+    pos[k0:] = rng.random((n_bg, 3))
+    # mix the species: exactly half gas, chosen at random
+    typ = np.full(n, COLLISIONLESS, np.uint8)
+    typ[rng.permutation(n)[: n // 2]] = GAS
+    # shuffle the caller order so that no input order is Morton-like
+    order = rng.permutation(n)
+    pos = pos[order]
+    typ = typ[order]
+    vel = rng.normal(0.0, sigma_v, (n, 3))
+    return Workload(
+        name=f"plummer_n{n}_s{n_spheres}_seed{seed}", pos=pos, vel=vel,
+        mass=np.full(n, 1.0 / n), u=np.ones(n), type=typ,
+        box=np.array([0.0, 0.0, 0.0, 1.0]),
+        params=Params(n_ngb=n_ngb, eps=eps), seed=seed)
+
+
+def lattice(side: int, spacing: float = 1.0) -> np.ndarray:
+    """Integer cubic lattice points (side^3 of them) times ``spacing``."""
+    g = np.arange(side, dtype=np.float64) * spacing
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def active_subset(n: int, fraction: float, seed: int) -> np.ndarray:
+    """A sorted random subset of caller ids (an active set)."""
+    rng = np.random.default_rng(seed)
+    k = max(0, min(n, int(round(fraction * n))))
+    return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)

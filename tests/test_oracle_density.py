@@ -1,0 +1,148 @@
+"""Pins of the oracle's SPH density and smoothing-length solve.
+
+Checked against: direct lattice sums and integer lattice-point counts, the
+root-bracket property of the mass-weighted neighbour number evaluated by
+brute force over all particles, finite differences in h, the neighbour
+predicate by exact brute force, active-subset and permutation invariance."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_10850_amd import inputs
+from brute import neighbour_sets
+
+
+def W_vec(r, h):
+    return np.array([oracle.kernel(float(x), float(h))[0] for x in np.atleast_1d(r)])
+
+
+def brute_rho(pos, mass, i, h, gas=None):
+    d = np.sqrt(((pos - pos[i]) ** 2).sum(1))
+    sel = d < h
+    if gas is not None:
+        sel &= gas
+    return float((mass[sel] * W_vec(d[sel], h)).sum())
+
+
+def lattice_setup(side=13):
+    pos = inputs.lattice(side)
+    c = (side // 2) * (side ** 2 + side + 1)  # centre point index
+    box = [-0.5, -0.5, -0.5, float(side)]
+    return pos, np.ones(len(pos)), c, box
+
+
+@pytest.mark.parametrize("h", [2.481402, 4.129630, 1.5, 3.0])
+def test_lattice_density_at_given_h(h):
+    pos, m, c, box = lattice_setup()
+    t = oracle.Tree(pos, m, box, gas_only=True)
+    hh = np.zeros(len(pos))
+    hh[c] = h
+    d = oracle.density(t, inputs.Params(), active=[c], h=hh, solve_h=False)
+    # integer points with |v|^2 < h^2, counted independently
+    r = int(math.ceil(h))
+    g = np.arange(-r, r + 1)
+    v2 = (g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2).ravel()
+    assert d["nngb"][c] == int((v2 < h * h).sum())
+    assert d["rho"][c] == pytest.approx(brute_rho(pos, m, c, h), rel=1e-13)
+    # the two nominal radii: 81 and 305 lattice points inside (|v|^2 <= 6 and <= 17)
+    if h == 2.481402:
+        assert d["nngb"][c] == 81
+    if h == 4.129630:
+        assert d["nngb"][c] == 305
+
+
+@pytest.mark.parametrize("nngb", [64.0, 295.0])
+def test_lattice_h_solve_brackets_root(nngb):
+    pos, m, c, box = lattice_setup(side=15)
+    t = oracle.Tree(pos, m, box, gas_only=True)
+    p = inputs.Params(n_ngb=nngb, h_tol=1e-10)
+    d = oracle.density(t, p, active=[c])
+    h = d["h"][c]
+
+    def neff(hh):
+        return 4 * math.pi / 3 * hh ** 3 * brute_rho(pos, m, c, hh)
+
+    assert neff(h * (1 - 1e-9)) < nngb <= neff(h * (1 + 1e-9))
+    assert d["nonconv"] == 0
+
+
+def test_c0_solve_brackets_root_by_brute_force():
+    w = inputs.uniform()
+    pos = w.pos.astype(np.float32).astype(np.float64)
+    t = oracle.Tree(pos, w.mass, w.box, gas_only=True)
+    d = oracle.density(t, w.params)
+    assert d["nonconv"] == 0 and d["status"] == 0
+    rng = np.random.default_rng(0)
+    tol = w.params.h_tol
+    for i in rng.choice(w.n, 12, replace=False):
+        h = d["h"][i]
+
+        def neff(hh):
+            return 4 * math.pi / 3 * hh ** 3 * brute_rho(pos, w.mass, i, hh) / w.mass[i]
+
+        # the returned midpoint lies within half a bracket width of the root
+        assert neff(h * (1 - tol)) < w.params.n_ngb <= neff(h * (1 + tol))
+        # outputs at the final h are the plain sums
+        assert d["rho"][i] == pytest.approx(brute_rho(pos, w.mass, i, h), rel=1e-12)
+
+
+def test_drho_dh_matches_finite_difference():
+    w = inputs.plummer(n=3000, n_spheres=3, seed=4)
+    pos = w.pos.astype(np.float32).astype(np.float64)
+    t = oracle.Tree(pos, w.mass, w.box, type=w.type, gas_only=True)
+    gas = np.nonzero(w.type == 0)[0][:40]
+    p = inputs.Params(n_ngb=64.0)
+    d = oracle.density(t, p, active=gas)
+    for i in gas[:10]:
+        h = d["h"][i]
+        dh = 1e-5 * h
+        rp = brute_rho(pos, w.mass, i, h + dh, gas=w.type == 0)
+        rm = brute_rho(pos, w.mass, i, h - dh, gas=w.type == 0)
+        fd = (rp - rm) / (2 * dh)
+        assert d["drho_dh"][i] == pytest.approx(fd, rel=1e-6, abs=1e-8 * d["rho"][i] / h)
+
+
+def test_neighbour_counts_match_exact_predicate():
+    w = inputs.plummer(n=4000, n_spheres=4, seed=11)
+    pos = w.pos.astype(np.float32).astype(np.float64)
+    t = oracle.Tree(pos, w.mass, w.box, type=w.type, gas_only=True)
+    gas = np.nonzero(w.type == 0)[0]
+    p = inputs.Params(n_ngb=64.0)
+    d = oracle.density(t, p, active=gas)
+    h32 = d["h"].astype(np.float32)
+    tg = gas[::37]
+    ref = neighbour_sets(pos, h32, tg, gas)
+    d2 = oracle.density(t, p, active=tg, h=h32.astype(np.float64), solve_h=False)
+    for i in tg:
+        assert d2["nngb"][i] == len(ref[int(i)])
+
+
+def test_active_subset_and_untouched_rows():
+    w = inputs.uniform(n=1500, seed=3)
+    t = oracle.Tree(w.pos, w.mass, w.box, gas_only=True)
+    full = oracle.density(t, w.params)
+    act = inputs.active_subset(w.n, 0.1, seed=1)
+    sub = oracle.density(t, w.params, active=act)
+    np.testing.assert_array_equal(sub["h"][act], full["h"][act])
+    np.testing.assert_array_equal(sub["rho"][act], full["rho"][act])
+    rest = np.setdiff1d(np.arange(w.n), act)
+    assert np.all(sub["rho"][rest] == 0) and np.all(sub["h"][rest] == 0)
+
+
+def test_permutation_invariance():
+    w = inputs.uniform(n=1200, seed=4)
+    perm = np.random.default_rng(2).permutation(w.n)
+    a = oracle.density(oracle.Tree(w.pos, w.mass, w.box, gas_only=True), w.params)
+    b = oracle.density(oracle.Tree(w.pos[perm], w.mass[perm], w.box, gas_only=True), w.params)
+    np.testing.assert_allclose(b["h"], a["h"][perm], rtol=1e-14)
+    np.testing.assert_allclose(b["rho"], a["rho"][perm], rtol=1e-12)
+    np.testing.assert_array_equal(b["nngb"], a["nngb"][perm])
+
+
+def test_invalid_target_number():
+    w = inputs.uniform(n=100)
+    t = oracle.Tree(w.pos, w.mass, w.box, gas_only=True)
+    with pytest.raises(ValueError):
+        oracle.density(t, inputs.Params(n_ngb=20.0))
