@@ -1,0 +1,203 @@
+/*
+ * g3.h - C ABI of libg3.so, the MI355X (gfx950) interaction phase of the
+ * Gadget3 method (Ragagnin et al., "Gadget3 on GPUs with OpenACC",
+ * arXiv 2003.10850).
+ *
+ * The paper's modules all compute, for a list of active particles, a sum over
+ * particles found by a tree walk over groups of active particles
+ * (section 1, fifth paragraph): the SPH density found by iterating the
+ * smoothing length, the SPH hydrodynamic force, and Barnes-Hut gravity whose
+ * node and particle interactions are evaluated inside the walk
+ * (section 2.4). Each module receives only the properties it needs, with
+ * read-only inputs kept apart from the updated outputs (section 2.1); each
+ * entry point below mirrors that: const inputs, separate outputs.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers unless marked (host). Particle arrays are
+ *    in the CALLER's order: row i of every [n] array is particle i.
+ *  - The caller owns every input and output buffer; the library never frees
+ *    or keeps them beyond the call. Outputs must not alias inputs.
+ *  - Outputs are written only at the rows of the active particles; other rows
+ *    are left untouched. active == NULL means every particle is active
+ *    (n_act must then equal n). Active ids must be distinct and in [0, n);
+ *    ids out of range are ignored, SPH calls ignore non-gas ids.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *    and the call returns without waiting, unless its comment says SYNCS.
+ *  - Every call returns a g3_status and never aborts; an asynchronous device
+ *    error surfaces as G3_EHIP on a later call. g3_last_error() gives text.
+ *  - One g3_ctx per host thread. A g3_tree belongs to the ctx that built it.
+ *
+ * Physics (the paper prints no formula; these are the published methods
+ * Gadget builds on): Wendland C6 kernel with support radius h (Dehnen & Aly
+ * 2012); h from the mass-weighted neighbour number
+ * (4 pi/3) h^3 rho / m = n_ngb (Springel & Hernquist 2002); grad-h SPH force
+ * with signal-velocity viscosity (Springel 2005; Monaghan 1997);
+ * Barnes-Hut octree, geometric opening angle, Plummer softening
+ * (Barnes & Hut 1986). Gas particles are SPH sources and targets;
+ * collisionless particles take part in gravity only.
+ */
+#ifndef G3_H
+#define G3_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  G3_OK = 0,
+  G3_EINVAL = -1,    /* bad argument; nothing enqueued */
+  G3_ENOMEM = -2,    /* device allocation failed */
+  G3_EHIP = -3,      /* HIP runtime or earlier asynchronous device error */
+  G3_EOVERFLOW = -4, /* g3_walk: list longer than capacity (total is set) */
+  G3_ENOCONV = -5,   /* h solve did not converge for some particles */
+  G3_ESTATE = -6     /* tree/ctx misuse (e.g. tree of another device) */
+} g3_status;
+
+typedef enum { G3_F32 = 0, G3_F64 = 1 } g3_dtype;
+
+enum { G3_GATHER = 0, G3_SYMMETRIC = 1, G3_GRAVITY = 2 };
+
+typedef struct g3_ctx g3_ctx;   /* scratch pools, counters, last error */
+typedef struct g3_tree g3_tree; /* sorted copies and octrees of one snapshot */
+
+/* Result-defining parameters (host struct, read during the call only). */
+typedef struct {
+  double n_ngb;      /* target mass-weighted neighbour number, > 1365/48 */
+  double h_tol;      /* relative accuracy of the h root (e.g. 1e-6) */
+  double gamma;      /* adiabatic index (5/3) */
+  double alpha;      /* artificial-viscosity strength (1) */
+  double theta;      /* Barnes-Hut opening angle (0.5) */
+  double eps;        /* Plummer softening length */
+  double G;          /* gravitational constant */
+  int32_t leaf_size; /* octree leaf capacity B, 1..64 (8) */
+  int32_t flags;     /* reserved, must be 0 */
+} g3_params;
+
+/* Create a context on HIP device `device`. *out receives the handle. */
+int g3_ctx_create(g3_ctx **out, int device);
+/* Destroy a context and every tree it owns. NULL is ignored. */
+void g3_ctx_destroy(g3_ctx *ctx);
+/* Text of the last error of this ctx ("" if none). Valid until the next call. */
+const char *g3_last_error(const g3_ctx *ctx);
+/* Number of particles whose h solve hit its iteration or bracket cap since
+ * the last reset (reset != 0 clears it). SYNCS the ctx's last stream. */
+int g3_ctx_nonconverged(g3_ctx *ctx, int64_t *count /* host */, int32_t reset);
+
+/*
+ * Build (or rebuild in place) the octrees of one particle set: one over all
+ * particles (gravity) and one over the gas particles (SPH). The octree
+ * follows Barnes & Hut (1986): the root is the cube `box`; a node is the set
+ * of particles sharing a 3l-bit prefix of their 63-bit Morton key
+ * (key = floor((x - lo) * 2^21 / side) per axis, computed in FP64, clamped
+ * to [0, 2^21 - 1]); a node is subdivided while it holds more than
+ * leaf_size particles and l < 21; single-child chains are kept. Nodes are
+ * stored in preorder with children in Morton order. Node monopoles (mass,
+ * centre of mass) are summed in FP64.
+ *   n      particles (0 allowed)
+ *   pos_t  G3_F32 (pos is float[n][3]); G3_F64 is not accepted yet
+ *   pos    [n][3] positions;  mass [n];  type [n] (0 gas, 1 collisionless;
+ *          NULL: all gas)
+ *   box    (host) [4] = lower corner xyz, side > 0
+ *   tree   (host) in/out: *tree == NULL creates a tree owned by ctx; an
+ *          existing tree is rebuilt reusing its buffers.
+ * SYNCS (reads back the node counts). The tree keeps sorted copies, so the
+ * inputs may change after the call returns. */
+int g3_build_tree(g3_ctx *ctx, int64_t n, int32_t pos_t, const void *pos,
+                  const float *mass, const uint8_t *type, const double *box,
+                  const g3_params *p, g3_tree **tree, void *stream);
+/* Release a tree (also released by g3_ctx_destroy). NULL is ignored. */
+void g3_tree_destroy(g3_ctx *ctx, g3_tree *tree);
+/* Sizes of one of the tree's octrees: which = 0 all particles, 1 gas.
+ * Host outputs, nullable. */
+int g3_tree_info(const g3_tree *tree, int32_t which, int64_t *n_members,
+                 int64_t *n_nodes);
+/* Copy one octree out (device outputs, each nullable): order [n_members]
+ * (sorted position -> caller id), keys [n_members], and per node in preorder
+ * [n_nodes]: first member, member count, level, skip (index of the next node
+ * after the subtree; n_nodes past the end), mass, centre of mass [n_nodes][3]
+ * (FP64). */
+int g3_tree_export(g3_ctx *ctx, const g3_tree *tree, int32_t which,
+                   int32_t *order, uint64_t *keys, int32_t *node_start,
+                   int32_t *node_count, int32_t *node_level, int32_t *node_skip,
+                   double *node_mass, double *node_com, void *stream);
+
+/*
+ * Interaction lists of the active particles (the walk step the SPH modules
+ * run before their sums, section 2.4), in CSR form with rows in the order
+ * of `active`:
+ *   G3_GATHER    gas j with |x_j - x_i| < h_i, self included;
+ *   G3_SYMMETRIC gas j != i with |x_j - x_i| < max(h_i, h_j);
+ *   G3_GRAVITY   the Barnes-Hut terms of i: particle j as its caller id,
+ *                accepted node k (preorder index in the all-particle tree)
+ *                as -(k + 1).
+ * Neighbour test (exact, FP32): dx = fl(x_j - x_i) per axis,
+ * r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)), neighbour iff r2 < fl(H * H).
+ *   h        [n] smoothing lengths (GATHER, SYMMETRIC; ignored for GRAVITY)
+ *   offsets  [n_act + 1] int64 output
+ *   list     [capacity] output; entries of a row in walk order
+ *   total    (host) output: offsets[n_act]
+ * SYNCS. Returns G3_EOVERFLOW, with *total and offsets valid and list
+ * untouched, when *total > capacity. */
+int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
+            const int32_t *active, const float *h, const g3_params *p,
+            int64_t capacity, int64_t *offsets, int32_t *list, int64_t *total,
+            void *stream);
+
+/*
+ * SPH density of the active gas particles (section 1: "computes particle
+ * densities by multiple iterations"):
+ *   rho_i   = sum_j m_j W(|x_ij|, h_i)     (gas j, self included)
+ *   drho_dh = sum_j m_j dW/dh(|x_ij|, h_i)
+ *   omega_i = 1 + h_i / (3 rho_i) drho_dh  (grad-h correction)
+ *   nngb_i  = number of gas j meeting the neighbour test at h_i
+ * solve_h = 1: h_i is first solved from (4 pi/3) h^3 rho(h) / m_i = n_ngb to
+ * relative accuracy h_tol (h[i] > 0 on entry is the first guess); h is then
+ * an output. solve_h = 0: h is an input. Output pointers other than h may be
+ * NULL. Non-converged particles are counted (g3_ctx_nonconverged). */
+int g3_density(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
+               const int32_t *active, const g3_params *p, int32_t solve_h,
+               float *h, float *rho, float *drho_dh, float *omega,
+               int32_t *nngb, void *stream);
+
+/*
+ * SPH hydrodynamic force of the active gas particles: grad-h SPH in energy
+ * form (Springel 2005) with signal-velocity viscosity (Monaghan 1997), over
+ * gas pairs j != i with |x_ij| < max(h_i, h_j):
+ *   P = (gamma-1) rho u, c = sqrt(gamma (gamma-1) u), A = P / (omega rho^2)
+ *   F(r,h) = dW/dr / r;  g_i = F(r, h_i);  g_j = F(r, h_j)
+ *   a_i   -= m_j (A_i g_i + A_j g_j) x_ij
+ *   w = v_ij . x_ij / r; if w < 0: Pi = (alpha/2) (c_i + c_j - 3w)(-w) /
+ *        ((rho_i + rho_j)/2), else 0;  a_i -= m_j Pi (g_i + g_j)/2 x_ij
+ *   du_i/dt += m_j A_i g_i v_ij.x_ij + m_j Pi (g_i + g_j)/4 v_ij.x_ij
+ *   vsig_i = max_j (c_i + c_j - 3 min(w, 0))   (0 with no pair)
+ * with x_ij = x_i - x_j, v_ij = v_i - v_j; pairs at r = 0 add nothing.
+ *   vel [n][3], u [n], h [n], rho [n], omega [n]: inputs for every gas
+ *   particle (neighbours need theirs); acc [n][3], dudt, vsig, npairs
+ *   (number of pairs of i) are outputs, each nullable.
+ * Refits the gas octree's per-node maximum h from `h` first. */
+int g3_hydro_force(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                   const int32_t *active, const g3_params *p, const float *vel,
+                   const float *u, const float *h, const float *rho,
+                   const float *omega, float *acc, float *dudt, float *vsig,
+                   int32_t *npairs, void *stream);
+
+/*
+ * Barnes-Hut gravity of the active particles from all particles: walk the
+ * all-particle octree in preorder from the root; a node whose cube does not
+ * contain x_i and whose side l satisfies l < theta |x_i - c| contributes its
+ * monopole (mass M at centre of mass c), an unaccepted leaf contributes each
+ * member j != i, other nodes are opened. Every term is Plummer-softened:
+ *   a_i -= G m x_ij / (r^2 + eps^2)^(3/2),  pot_i -= G m / (r^2 + eps^2)^(1/2).
+ * The opening test is exact in FP32: dx = fl(fl(c) - x_i),
+ * r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)), accept iff
+ * fl(fl(l) * fl(l)) < fl(fl(theta^2) * r2).
+ *   acc [n][3], pot [n], nterms [n] (terms of i): outputs, each nullable. */
+int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
+               const int32_t *active, const g3_params *p, float *acc,
+               float *pot, int32_t *nterms, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

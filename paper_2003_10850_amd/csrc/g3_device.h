@@ -1,0 +1,54 @@
+// Device-side helpers shared by the kernels of libg3.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace g3 {
+
+// Order LDS traffic between the lanes of one wavefront (a compiler barrier
+// with wavefront-scope release/acquire fences; LDS executes a wave's
+// instructions in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Broadcast of a wave-uniform value into a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Exact neighbour test quantity: dx = fl(b - a) per axis,
+// r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)); no contraction beyond that.
+__device__ __forceinline__ float dist2_exact(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  const float xx = dx * dx;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
+}
+
+// fl(b - a) with no contraction into a neighbouring product.
+__device__ __forceinline__ float sub_exact(float b, float a) {
+#pragma clang fp contract(off)
+  return b - a;
+}
+
+// Squared distance from x to the box [lo, hi] evaluated with the same
+// rounding steps as dist2_exact; never larger than dist2_exact of any point
+// inside the box (rounding is monotone), so it prunes exactly.
+__device__ __forceinline__ float box_dist2(float3 x, float4 lo, float4 hi) {
+#pragma clang fp contract(off)
+  const float dx = fmaxf(fmaxf(lo.x - x.x, x.x - hi.x), 0.0f);
+  const float dy = fmaxf(fmaxf(lo.y - x.y, x.y - hi.y), 0.0f);
+  const float dz = fmaxf(fmaxf(lo.z - x.z, x.z - hi.z), 0.0f);
+  return dist2_exact(dx, dy, dz);
+}
+
+// fl(a * a) with no contraction (the squared search radius).
+__device__ __forceinline__ float sq_exact(float a) {
+#pragma clang fp contract(off)
+  return a * a;
+}
+
+}  // namespace g3

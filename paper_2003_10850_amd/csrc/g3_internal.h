@@ -1,0 +1,145 @@
+// Internal declarations of libg3.so: device data layout, the context and
+// tree objects, and the launch wrappers shared by the translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "g3.h"
+
+namespace g3 {
+
+constexpr int kMaxLevel = 21;  // 21 key bits per axis, 63-bit Morton keys
+constexpr int kWave = 64;      // CDNA wavefront width
+
+// One octree node, 64 bytes: a walk reads it with one scalar load.
+struct __align__(16) Node {
+  float4 com_m;  // centre of mass (FP32 copy of the FP64 moment), mass
+  float4 lo_h;   // tight bounding box lower corner, max h of gas members
+  float4 hi_l;   // tight bounding box upper corner, cube side l
+  int4 meta;     // skip, first member, member count, level | leaf << 8
+};
+static_assert(sizeof(Node) == 64, "node must be 64 bytes");
+
+constexpr int kLeafBit = 256;
+
+// One octree over a subset of the particles (all of them, or the gas ones),
+// with the members in Morton order.
+struct Octree {
+  int64_t n = 0;       // members
+  int64_t nnodes = 0;
+  int32_t max_level = 0;
+  int64_t cap_n = 0, cap_nodes = 0;
+  uint64_t *keys = nullptr;  // [n] sorted Morton keys
+  int32_t *perm = nullptr;   // [n] sorted position -> caller id
+  float4 *xm = nullptr;      // [n] sorted (x, y, z, m)
+  Node *nodes = nullptr;     // [nnodes] preorder
+  double4 *mom = nullptr;    // [nnodes] FP64 (M, M x, M y, M z)
+  // SPH member data in sorted order (gas octree only, filled by the calls)
+  float4 *vh = nullptr;   // (vx, vy, vz, h)
+  float4 *aux = nullptr;  // (A, c, rho, 1/h)
+};
+
+}  // namespace g3
+
+struct g3_tree {
+  g3_ctx *owner = nullptr;
+  int device = 0;
+  int64_t n = 0;  // caller particles
+  int64_t cap_n = 0;
+  double box[4] = {0, 0, 0, 1};
+  double scale = 0;  // 2^21 / side
+  int32_t leaf = 8;
+  int32_t *iperm_all = nullptr;  // [n] caller id -> position in `all`
+  int32_t *iperm_gas = nullptr;  // [n] caller id -> position in `gas`, or -1
+  g3::Octree all, gas;
+};
+
+struct g3_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<g3_tree *> trees;
+  struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+  };
+  Buf scratch[16];
+  unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
+  int64_t *pinned = nullptr;               // host pinned readback slots [8]
+  hipStream_t last_stream = nullptr;
+};
+
+namespace g3 {
+
+// scratch slots (grow-only buffers owned by the ctx)
+enum Slot {
+  kSortKeys = 0, kSortVals, kSortTmp, kScanTmp, kCounts, kOffsets,
+  kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
+  kNumSlots
+};
+
+void *scratch(g3_ctx *c, int slot, size_t bytes);  // nullptr on failure
+
+// ---- launch wrappers (each returns hipGetLastError() of its launches) ----
+
+// Exclusive scan with the total: out[i] = sum in[0..i), out[n] = sum in[0..n).
+// tmp must hold scan_tmp_elems(n) elements of the output type.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
+                    hipStream_t s);
+hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp,
+                           hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by key bits [0, 64).
+// tmp must hold radix_tmp_bytes(n) bytes. Result ends in keys/vals.
+size_t radix_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
+                            uint32_t *vals_alt, int64_t n, void *tmp, hipStream_t s);
+
+// Tree build of one octree (members already selected in `ids`/`keys`).
+int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float *mass,
+                 int64_t m, hipStream_t s);
+hipError_t refit_hmax(Octree &o, hipStream_t s);
+
+hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+// Active set -> Morton-ordered target list of one octree. Writes
+// targets[0..cnt) (sorted positions) and rows (index in `active`), with
+// the count at *dcount (device). active == nullptr selects every member.
+int compact_targets(g3_ctx *c, const Octree &o, const int32_t *iperm, int64_t n_caller,
+                    int64_t n_act, const int32_t *active, int32_t **targets,
+                    int32_t **rows, uint32_t **dcount, hipStream_t s);
+
+struct SphParams {
+  float n_ngb, h_tol, gamma, alpha;
+  int max_iter;
+};
+
+hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
+                          int64_t max_targets, const SphParams &sp, int solve_h, float *h,
+                          float *rho, float *drho_dh, float *omega, int32_t *nngb,
+                          unsigned long long *nonconv, hipStream_t s, float hcap);
+hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const float *h,
+                             const float *rho, const float *omega, float gamma,
+                             hipStream_t s);
+hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
+                        int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
+                        float *vsig, int32_t *npairs, hipStream_t s);
+
+struct GravParams {
+  float theta2, eps2, G;
+  int inside_test;  // evaluate the cube-containment test (theta^2 >= 1/3)
+};
+hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint32_t *dcount,
+                          int64_t max_targets, const GravParams &gp, float *acc, float *pot,
+                          int32_t *nterms, hipStream_t s);
+
+// Walk lists: counts pass (list == nullptr) or fill pass.
+hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
+                       const uint32_t *dcount, int64_t max_targets, const float *h_caller,
+                       const GravParams &gp, int32_t *counts, const int64_t *offsets,
+                       int32_t *list, hipStream_t s);
+
+}  // namespace g3

@@ -1,0 +1,168 @@
+// Barnes-Hut gravity with per-particle opening decisions, walked by a whole
+// wavefront at a time.
+//
+// A wave serves 64 Morton-consecutive targets. It visits the all-particle
+// octree in preorder with one scalar node load per step, and every lane
+// takes the per-particle Barnes-Hut decision for that node (Barnes & Hut
+// 1986): accept the monopole, open it, or skip it because an ancestor was
+// already accepted (the lane then resumes at the ancestor's skip index).
+// The wave descends while any lane opens. Accepted monopoles and the members
+// of opened leaves become entries of a 64-entry interaction tile in LDS,
+// each with the 64-bit mask of lanes that use it; the tile is then
+// evaluated by all lanes with the mask folded into the source mass. This
+// keeps the interaction step out of the walk's branches (the limitation the
+// paper names for gravity, section 2.4) and reproduces the per-particle
+// interaction list exactly.
+#include "g3_device.h"
+#include "g3_internal.h"
+
+namespace g3 {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWpb = kBlock / kWave;
+constexpr int kTile = kWave;
+
+struct __align__(16) Entry {
+  float4 p;       // source position, mass
+  int4 meta;      // source sorted index (-1: node), mask low, mask high, unused
+};
+
+// The opening test, exact in FP32: fl(l * l) < fl(theta2 * r2).
+__device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
+#pragma clang fp contract(off)
+  const float lhs = l * l;
+  const float rhs = theta2 * r2;
+  return lhs < rhs;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gravity(
+    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ targets, const uint32_t *__restrict__ dcount, int64_t ntmax,
+    float theta2, float eps2, float G, int inside_test, float *__restrict__ acc,
+    float *__restrict__ pot, int32_t *__restrict__ nterms) {
+  __shared__ Entry tiles[kWpb][kTile];
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
+  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  if (g0 >= ntarg) return;
+  const int64_t t = g0 + lane;
+  const bool valid = t < ntarg;
+  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  const float4 me = xm[s];
+  const float3 xi = make_float3(me.x, me.y, me.z);
+  const uint64_t ki = keys[s];
+  const uint64_t mybit = 1ull << lane;
+  Entry *tile = tiles[w];
+
+  float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+  int nt = 0;
+  int tc = 0;
+
+  auto flush = [&](int nc) {
+    wave_sync();
+    for (int k = 0; k < nc; ++k) {
+      const Entry e = tile[k];
+      const uint64_t mask = (uint64_t)(uint32_t)e.meta.y | ((uint64_t)(uint32_t)e.meta.z << 32);
+      const bool use = (mask & mybit) && e.meta.x != s;
+      const float dx = e.p.x - xi.x, dy = e.p.y - xi.y, dz = e.p.z - xi.z;
+      const float r2 = dx * dx + dy * dy + dz * dz + eps2;
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float mr = use ? e.p.w * rinv : 0.0f;
+      const float mr3 = mr * rinv * rinv;
+      ax += mr3 * dx;
+      ay += mr3 * dy;
+      az += mr3 * dz;
+      ph -= mr;
+      nt += use ? 1 : 0;
+    }
+    wave_sync();
+  };
+
+  int resume = valid ? 0 : INT32_MAX;  // lanes idle while cur < resume
+  int cur = 0;
+  while (cur < nnodes) {
+    const Node nd = nodes[cur];
+    const bool act = cur >= resume;
+    const float r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
+                                 sub_exact(nd.com_m.z, xi.z));
+    bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
+    if (inside_test) {
+      const int level = nd.meta.w & 255;
+      const uint64_t nk = keys[nd.meta.y];
+      const bool inside = ((ki ^ nk) >> (3 * (kMaxLevel - level))) == 0ull;
+      accept = accept && !inside;
+    }
+    const uint64_t amask = __ballot(accept);
+    const uint64_t omask = __ballot(act && !accept);
+    if (accept) resume = nd.meta.x;
+    if (amask) {
+      if (tc == kTile) {
+        flush(kTile);
+        tc = 0;
+      }
+      if (lane == 0) {
+        Entry e;
+        e.p = nd.com_m;
+        e.meta = make_int4(-1, (int)(uint32_t)amask, (int)(uint32_t)(amask >> 32), 0);
+        tile[tc] = e;
+      }
+      ++tc;
+    }
+    if (omask == 0ull) {
+      cur = nd.meta.x;
+      continue;
+    }
+    if (!(nd.meta.w & kLeafBit)) {
+      ++cur;
+      continue;
+    }
+    int st = nd.meta.y, c = nd.meta.z;
+    while (c > 0) {
+      if (tc == kTile) {
+        flush(kTile);
+        tc = 0;
+      }
+      const int take = min(c, kTile - tc);
+      if (lane < take) {
+        Entry e;
+        e.p = xm[st + lane];
+        e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
+        tile[tc + lane] = e;
+      }
+      tc += take;
+      st += take;
+      c -= take;
+    }
+    cur = nd.meta.x;
+  }
+  if (tc > 0) flush(tc);
+
+  if (valid) {
+    const int cid = perm[s];
+    if (acc) {
+      acc[3 * cid] = G * ax;
+      acc[3 * cid + 1] = G * ay;
+      acc[3 * cid + 2] = G * az;
+    }
+    if (pot) pot[cid] = G * ph;
+    if (nterms) nterms[cid] = nt;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint32_t *dcount,
+                          int64_t max_targets, const GravParams &gp, float *acc, float *pot,
+                          int32_t *nterms, hipStream_t s) {
+  if (max_targets <= 0 || all.nnodes == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
+  k_gravity<<<blocks, kBlock, 0, s>>>(all.nodes, (int)all.nnodes, all.xm, all.keys, all.perm,
+                                      targets, dcount, max_targets, gp.theta2, gp.eps2, gp.G,
+                                      gp.inside_test, acc, pot, nterms);
+  return hipGetLastError();
+}
+
+}  // namespace g3

@@ -1,0 +1,352 @@
+// Octree build on the GPU: Morton keys, radix sort, permutation into sorted
+// float4 arrays, preorder topology computed per particle without recursion,
+// and bottom-up FP64 monopoles with tight bounding boxes.
+//
+// Topology (Barnes & Hut 1986 octree over Morton-sorted members): a node is
+// the run of members sharing a 3l-bit key prefix; it is split while it holds
+// more than B members and l < 21. Write cpl(a, b) for the number of leading
+// 3-bit digits two keys share. Member p starts a node at level l exactly
+// when l >= delta_p = cpl(p, p-1) + 1 (delta_0 = 0), and the deepest node
+// holding p (its leaf) is at depth d_p = 1 + the B-th largest of
+// cpl(p, p +- k), k = 1..B (missing neighbours count -1), capped at 21.
+// So p starts the nodes of levels delta_p..d_p, and in preorder (children in
+// Morton order) the nodes sorted by (first member, level) are numbered by an
+// exclusive scan of the per-member counts. The node after the subtree of a
+// node ending before member e is the first node that starts at e.
+#include <utility>
+
+#include "g3_device.h"
+#include "g3_internal.h"
+
+namespace g3 {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t cell_of(float x, double lo, double scale) {
+  double f = floor(((double)x - lo) * scale);
+  if (!(f >= 0.0)) f = 0.0;
+  if (f > (double)((1u << kMaxLevel) - 1u)) f = (double)((1u << kMaxLevel) - 1u);
+  return (uint32_t)f;
+}
+
+__device__ __forceinline__ uint64_t morton_key(const float *p, double lx, double ly,
+                                               double lz, double scale) {
+  return (spread3(cell_of(p[0], lx, scale)) << 2) | (spread3(cell_of(p[1], ly, scale)) << 1) |
+         spread3(cell_of(p[2], lz, scale));
+}
+
+// keys and identity values for the members selected by sel (nullptr: all)
+__global__ void k_keys(const float *__restrict__ pos, const int32_t *__restrict__ sel,
+                       int64_t m, double lx, double ly, double lz, double scale,
+                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t i = sel ? sel[k] : k;
+  keys[k] = morton_key(pos + 3 * i, lx, ly, lz, scale);
+  vals[k] = (uint32_t)i;
+}
+
+__global__ void k_gas_flags(const uint8_t *__restrict__ type, int64_t n,
+                            uint32_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = (type == nullptr || type[i] == 0) ? 1u : 0u;
+}
+
+__global__ void k_gas_compact(const uint32_t *__restrict__ flags,
+                              const uint32_t *__restrict__ slot, int64_t n,
+                              int32_t *__restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flags[i]) ids[slot[i]] = (int32_t)i;
+}
+
+__global__ void k_permute(const uint32_t *__restrict__ perm, int64_t m,
+                          const float *__restrict__ pos, const float *__restrict__ mass,
+                          float4 *__restrict__ xm, int32_t *__restrict__ iperm) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const uint32_t j = perm[s];
+  xm[s] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j]);
+  iperm[j] = (int32_t)s;
+}
+
+__device__ __forceinline__ int cpl(uint64_t a, uint64_t b) {
+  const uint64_t x = a ^ b;
+  if (x == 0) return kMaxLevel;
+  return (__clzll((long long)x) - 1) / 3;  // bit 63 is never used
+}
+
+// nodes started by each member: cnt[p] = max(0, d_p - delta_p + 1)
+__global__ void k_node_counts(const uint64_t *__restrict__ keys, int64_t m, int B,
+                              uint32_t *__restrict__ cnt, uint8_t *__restrict__ lev,
+                              int32_t *__restrict__ maxlev) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const uint64_t kp = keys[p];
+  const int delta = (p == 0) ? 0 : cpl(kp, keys[p - 1]) + 1;
+  // B-th largest of the window prefix lengths: merge two non-increasing runs
+  int64_t i = 1, j = 1;
+  int val = -1;
+  int a = (p - 1 >= 0) ? cpl(kp, keys[p - 1]) : -1;
+  int b = (p + 1 < m) ? cpl(kp, keys[p + 1]) : -1;
+  for (int step = 0; step < B; ++step) {
+    if (a >= b) {
+      val = a;
+      ++i;
+      a = (p - i >= 0) ? cpl(kp, keys[p - i]) : -1;
+    } else {
+      val = b;
+      ++j;
+      b = (p + j < m) ? cpl(kp, keys[p + j]) : -1;
+    }
+  }
+  int d = val + 1;
+  if (d > kMaxLevel) d = kMaxLevel;
+  cnt[p] = (d >= delta) ? (uint32_t)(d - delta + 1) : 0u;
+  lev[2 * p] = (uint8_t)delta;
+  lev[2 * p + 1] = (uint8_t)d;
+  if (d >= delta) atomicMax(maxlev, d);
+}
+
+__global__ void k_nodes(const uint64_t *__restrict__ keys, int64_t m,
+                        const uint32_t *__restrict__ off, const uint8_t *__restrict__ lev,
+                        int64_t nnodes, float side, Node *__restrict__ nodes) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const int delta = lev[2 * p], d = lev[2 * p + 1];
+  if (d < delta) return;
+  const uint64_t kp = keys[p];
+  int64_t end = m;  // members of the level-l node: [p, end)
+  for (int l = delta; l <= d; ++l) {
+    // first q in (p, end] with cpl(p, q) < l (end shrinks as l grows)
+    int64_t lo = p + 1, hi = end;  // answer in [lo, hi]
+    int64_t step = 1;
+    while (lo + step - 1 < hi && cpl(kp, keys[lo + step - 1]) >= l) {
+      lo += step;
+      step <<= 1;
+    }
+    if (lo + step - 1 < hi) hi = lo + step - 1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (cpl(kp, keys[mid]) >= l) lo = mid + 1;
+      else hi = mid;
+    }
+    end = lo;
+    const int64_t idx = (int64_t)off[p] + (l - delta);
+    const int64_t skip = (end >= m) ? nnodes : (int64_t)off[end];
+    Node nd;
+    nd.com_m = make_float4(0.f, 0.f, 0.f, 0.f);
+    nd.lo_h = make_float4(0.f, 0.f, 0.f, 0.f);
+    nd.hi_l = make_float4(0.f, 0.f, 0.f, ldexpf(side, -l));
+    nd.meta = make_int4((int)skip, (int)p, (int)(end - p), l | (l == d ? kLeafBit : 0));
+    nodes[idx] = nd;
+  }
+}
+
+// Bottom-up pass for one level: FP64 mass and first moments, tight box.
+__global__ void k_moments_level(Node *__restrict__ nodes, double4 *__restrict__ mom,
+                                int64_t nnodes, const float4 *__restrict__ xm, int level) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnodes) return;
+  const int4 meta = nodes[k].meta;
+  if ((meta.w & 255) != level) return;
+  double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
+  float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+  float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+  if (meta.w & kLeafBit) {
+    for (int s = meta.y; s < meta.y + meta.z; ++s) {
+      const float4 p = xm[s];
+      const double mm = (double)p.w;
+      M += mm;
+      Sx += mm * (double)p.x;
+      Sy += mm * (double)p.y;
+      Sz += mm * (double)p.z;
+      lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
+      hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
+    }
+  } else {
+    int64_t c = k + 1;
+    while (c < meta.x) {
+      const double4 cm = mom[c];
+      const float4 clo = nodes[c].lo_h, chi = nodes[c].hi_l;
+      M += cm.x;
+      Sx += cm.y;
+      Sy += cm.z;
+      Sz += cm.w;
+      lo.x = fminf(lo.x, clo.x); lo.y = fminf(lo.y, clo.y); lo.z = fminf(lo.z, clo.z);
+      hi.x = fmaxf(hi.x, chi.x); hi.y = fmaxf(hi.y, chi.y); hi.z = fmaxf(hi.z, chi.z);
+      c = nodes[c].meta.x;
+    }
+  }
+  mom[k] = make_double4(M, Sx, Sy, Sz);
+  Node &nd = nodes[k];
+  if (M > 0.0)
+    nd.com_m = make_float4((float)(Sx / M), (float)(Sy / M), (float)(Sz / M), (float)M);
+  else  // massless node: its geometric centre
+    nd.com_m = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z), 0.f);
+  lo.w = nd.lo_h.w;
+  hi.w = nd.hi_l.w;
+  nd.lo_h = lo;
+  nd.hi_l = hi;
+}
+
+// Bottom-up pass for one level: maximum h of the members (vh.w).
+__global__ void k_hmax_level(Node *__restrict__ nodes, int64_t nnodes,
+                             const float4 *__restrict__ vh, int level) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnodes) return;
+  const int4 meta = nodes[k].meta;
+  if ((meta.w & 255) != level) return;
+  float hm = 0.f;
+  if (meta.w & kLeafBit) {
+    for (int s = meta.y; s < meta.y + meta.z; ++s) hm = fmaxf(hm, vh[s].w);
+  } else {
+    int64_t c = k + 1;
+    while (c < meta.x) {
+      hm = fmaxf(hm, nodes[c].lo_h.w);
+      c = nodes[c].meta.x;
+    }
+  }
+  nodes[k].lo_h.w = hm;
+}
+
+template <typename T>
+bool grow(T **p, int64_t *cap, int64_t need) {
+  if (need <= *cap && *p) return true;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const int64_t n = need > 0 ? need : 1;
+  if (hipMalloc((void **)p, (size_t)n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return false;
+  }
+  *cap = n;
+  return true;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// Selects the members (gas only for the gas octree), sorts them and builds
+// the topology and moments. SYNCS once to read the node count.
+int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float *mass,
+                 int64_t m, hipStream_t s) {
+  o.n = m;
+  o.nnodes = 0;
+  o.max_level = 0;
+  if (m == 0) return G3_OK;
+  if (m > o.cap_n) {
+    for (void *p : {(void *)o.keys, (void *)o.perm, (void *)o.xm, (void *)o.vh, (void *)o.aux})
+      if (p) (void)hipFree(p);
+    o.keys = nullptr; o.perm = nullptr; o.xm = nullptr; o.vh = nullptr; o.aux = nullptr;
+    o.cap_n = 0;
+    if (hipMalloc((void **)&o.keys, m * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void **)&o.perm, m * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&o.xm, m * sizeof(float4)) != hipSuccess ||
+        hipMalloc((void **)&o.vh, m * sizeof(float4)) != hipSuccess ||
+        hipMalloc((void **)&o.aux, m * sizeof(float4)) != hipSuccess) {
+      c->err = "device allocation of the sorted particle arrays failed";
+      return G3_ENOMEM;
+    }
+    o.cap_n = m;
+  }
+  uint64_t *kalt = (uint64_t *)scratch(c, kSortKeys, m * sizeof(uint64_t));
+  uint32_t *valt = (uint32_t *)scratch(c, kSortVals, m * sizeof(uint32_t));
+  void *rtmp = scratch(c, kSortTmp, radix_tmp_bytes(m));
+  uint32_t *vals = (uint32_t *)scratch(c, kIds, m * sizeof(uint32_t));
+  uint32_t *cnt = (uint32_t *)scratch(c, kCounts, (m + 1) * sizeof(uint32_t));
+  uint32_t *off = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
+  uint8_t *lev = (uint8_t *)scratch(c, kLevel, 2 * m);
+  uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m) * sizeof(uint32_t));
+  int32_t *maxlev = (int32_t *)scratch(c, kMisc, 64);
+  if (!kalt || !valt || !rtmp || !vals || !cnt || !off || !lev || !stmp || !maxlev) {
+    c->err = "device allocation of build scratch failed";
+    return G3_ENOMEM;
+  }
+  const bool gas = (&o == &t->gas);
+  const int32_t *sel = nullptr;
+  if (gas && m != t->n) sel = (const int32_t *)scratch(c, kFlags, 0);  // filled by caller
+  k_keys<<<nblk(m), kBlock, 0, s>>>(pos, sel, m, t->box[0], t->box[1], t->box[2], t->scale,
+                                    o.keys, vals);
+  hipError_t e = radix_sort_pairs(o.keys, vals, kalt, valt, m, rtmp, s);
+  if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
+  int32_t *iperm = gas ? t->iperm_gas : t->iperm_all;
+  k_permute<<<nblk(m), kBlock, 0, s>>>(vals, m, pos, mass, o.xm, iperm);
+  e = hipMemcpyAsync(o.perm, vals, m * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) { c->err = "perm copy failed"; return G3_EHIP; }
+  e = fill_i32(maxlev, 0, 1, s);
+  if (e != hipSuccess) { c->err = "fill launch failed"; return G3_EHIP; }
+  k_node_counts<<<nblk(m), kBlock, 0, s>>>(o.keys, m, t->leaf, cnt, lev, maxlev);
+  e = scan_u32(cnt, off, m, stmp, s);
+  if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
+  int64_t *pin = c->pinned;
+  e = hipMemcpyAsync(&pin[0], off + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&pin[1], maxlev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { c->err = std::string("node count readback: ") + hipGetErrorString(e); return G3_EHIP; }
+  const int64_t nnodes = (int64_t)(uint32_t)(pin[0] & 0xffffffffll);
+  const int32_t maxl = (int32_t)(pin[1] & 0xffffffffll);
+  if (nnodes <= 0 || nnodes >= (int64_t)INT32_MAX) { c->err = "node count out of range"; return G3_EHIP; }
+  if (nnodes > o.cap_nodes) {
+    if (o.nodes) (void)hipFree(o.nodes);
+    if (o.mom) (void)hipFree(o.mom);
+    o.nodes = nullptr; o.mom = nullptr; o.cap_nodes = 0;
+    const int64_t cap = nnodes + nnodes / 8 + 64;
+    if (hipMalloc((void **)&o.nodes, cap * sizeof(Node)) != hipSuccess ||
+        hipMalloc((void **)&o.mom, cap * sizeof(double4)) != hipSuccess) {
+      c->err = "device allocation of the octree nodes failed";
+      return G3_ENOMEM;
+    }
+    o.cap_nodes = cap;
+  }
+  o.nnodes = nnodes;
+  o.max_level = maxl;
+  k_nodes<<<nblk(m), kBlock, 0, s>>>(o.keys, m, off, lev, nnodes, (float)t->box[3], o.nodes);
+  for (int l = maxl; l >= 0; --l)
+    k_moments_level<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, o.mom, nnodes, o.xm, l);
+  e = hipGetLastError();
+  if (e != hipSuccess) { c->err = std::string("tree build launch: ") + hipGetErrorString(e); return G3_EHIP; }
+  return G3_OK;
+}
+
+hipError_t refit_hmax(Octree &o, hipStream_t s) {
+  for (int l = o.max_level; l >= 0 && o.nnodes > 0; --l)
+    k_hmax_level<<<nblk(o.nnodes), kBlock, 0, s>>>(o.nodes, o.nnodes, o.vh, l);
+  return hipGetLastError();
+}
+
+// Gas member selection for the gas octree: ids of the gas particles in
+// caller order, written to the kFlags scratch slot; returns their number
+// (SYNCS to read it).
+int select_gas(g3_ctx *c, const uint8_t *type, int64_t n, int64_t *m_out, hipStream_t s) {
+  if (!type) { *m_out = n; return G3_OK; }
+  uint32_t *flags = (uint32_t *)scratch(c, kCounts, (n + 1) * sizeof(uint32_t));
+  uint32_t *slot = (uint32_t *)scratch(c, kOffsets, (n + 1) * sizeof(uint32_t));
+  uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(n) * sizeof(uint32_t));
+  int32_t *ids = (int32_t *)scratch(c, kFlags, (n + 1) * sizeof(int32_t));
+  if (!flags || !slot || !stmp || !ids) { c->err = "device allocation failed"; return G3_ENOMEM; }
+  k_gas_flags<<<nblk(n), kBlock, 0, s>>>(type, n, flags);
+  hipError_t e = scan_u32(flags, slot, n, stmp, s);
+  if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
+  k_gas_compact<<<nblk(n), kBlock, 0, s>>>(flags, slot, n, ids);
+  e = hipMemcpyAsync(&c->pinned[2], slot + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { c->err = std::string("gas count readback: ") + hipGetErrorString(e); return G3_EHIP; }
+  *m_out = (int64_t)(uint32_t)(c->pinned[2] & 0xffffffffll);
+  return G3_OK;
+}
+
+}  // namespace g3

@@ -1,0 +1,151 @@
+// Explicit interaction lists (g3_walk): the same wave-coherent walks as the
+// density, hydro and gravity kernels, emitting the accepted entries instead
+// of summing them. A counting pass sizes each row, a scan gives the CSR
+// offsets, a filling pass writes the rows.
+#include "g3_device.h"
+#include "g3_internal.h"
+
+namespace g3 {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWpb = kBlock / kWave;
+
+__global__ __launch_bounds__(kBlock) void k_walk_sph(
+    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const float4 *__restrict__ vh, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ targets, const int32_t *__restrict__ rows,
+    const uint32_t *__restrict__ dcount, int64_t ntmax, int symmetric,
+    int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
+    int32_t *__restrict__ list) {
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
+  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  if (g0 >= ntarg) return;
+  const int64_t t = g0 + lane;
+  const bool valid = t < ntarg;
+  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  const int64_t row = valid ? (rows ? rows[t] : t) : 0;
+  const float4 me = xm[s];
+  const float3 xi = make_float3(me.x, me.y, me.z);
+  const float hi = valid ? vh[s].w : -1.0f;
+  const float h2 = valid ? sq_exact(hi) : -1.0f;
+  int64_t pos = (list && valid) ? offsets[row] : 0;
+  int cnt = 0;
+  int cur = 0;
+  while (cur < nnodes) {
+    const Node nd = nodes[cur];
+    const float d2 = box_dist2(xi, nd.lo_h, nd.hi_l);
+    const bool want = valid && (symmetric ? d2 < sq_exact(fmaxf(hi, nd.lo_h.w)) : d2 < h2);
+    if (__ballot(want) == 0ull) {
+      cur = nd.meta.x;
+      continue;
+    }
+    if (!(nd.meta.w & kLeafBit)) {
+      ++cur;
+      continue;
+    }
+    for (int k = nd.meta.y; k < nd.meta.y + nd.meta.z; ++k) {
+      const float4 q = xm[k];
+      const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                   sub_exact(q.z, xi.z));
+      bool take;
+      if (symmetric) take = valid && k != s && r2 < sq_exact(fmaxf(hi, vh[k].w));
+      else take = valid && r2 < h2;
+      if (take) {
+        if (list) list[pos++] = perm[k];
+        ++cnt;
+      }
+    }
+    cur = nd.meta.x;
+  }
+  if (valid && !list) counts[row] = cnt;
+}
+
+__device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
+#pragma clang fp contract(off)
+  const float lhs = l * l;
+  const float rhs = theta2 * r2;
+  return lhs < rhs;
+}
+
+__global__ __launch_bounds__(kBlock) void k_walk_grav(
+    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ targets, const int32_t *__restrict__ rows,
+    const uint32_t *__restrict__ dcount, int64_t ntmax, float theta2, int inside_test,
+    int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
+    int32_t *__restrict__ list) {
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
+  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  if (g0 >= ntarg) return;
+  const int64_t t = g0 + lane;
+  const bool valid = t < ntarg;
+  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  const int64_t row = valid ? (rows ? rows[t] : t) : 0;
+  const float4 me = xm[s];
+  const float3 xi = make_float3(me.x, me.y, me.z);
+  const uint64_t ki = keys[s];
+  int64_t pos = (list && valid) ? offsets[row] : 0;
+  int cnt = 0;
+  int resume = valid ? 0 : INT32_MAX;
+  int cur = 0;
+  while (cur < nnodes) {
+    const Node nd = nodes[cur];
+    const bool act = cur >= resume;
+    const float r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
+                                 sub_exact(nd.com_m.z, xi.z));
+    bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
+    if (inside_test) {
+      const int level = nd.meta.w & 255;
+      const uint64_t nk = keys[nd.meta.y];
+      accept = accept && (((ki ^ nk) >> (3 * (kMaxLevel - level))) != 0ull);
+    }
+    const bool open = act && !accept;
+    if (accept) {
+      resume = nd.meta.x;
+      if (list) list[pos++] = -(cur + 1);
+      ++cnt;
+    }
+    if (__ballot(open) == 0ull) {
+      cur = nd.meta.x;
+      continue;
+    }
+    if (!(nd.meta.w & kLeafBit)) {
+      ++cur;
+      continue;
+    }
+    for (int k = nd.meta.y; k < nd.meta.y + nd.meta.z; ++k) {
+      if (open && k != s) {
+        if (list) list[pos++] = perm[k];
+        ++cnt;
+      }
+    }
+    cur = nd.meta.x;
+  }
+  if (valid && !list) counts[row] = cnt;
+}
+
+}  // namespace
+
+hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
+                       const uint32_t *dcount, int64_t max_targets, const float *h_caller,
+                       const GravParams &gp, int32_t *counts, const int64_t *offsets,
+                       int32_t *list, hipStream_t s) {
+  (void)h_caller;
+  if (max_targets <= 0 || o.nnodes == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
+  if (kind == G3_GRAVITY)
+    k_walk_grav<<<blocks, kBlock, 0, s>>>(o.nodes, (int)o.nnodes, o.xm, o.keys, o.perm, targets,
+                                          rows, dcount, max_targets, gp.theta2, gp.inside_test,
+                                          counts, offsets, list);
+  else
+    k_walk_sph<<<blocks, kBlock, 0, s>>>(o.nodes, (int)o.nnodes, o.xm, o.vh, o.perm, targets,
+                                         rows, dcount, max_targets, kind == G3_SYMMETRIC,
+                                         counts, offsets, list);
+  return hipGetLastError();
+}
+
+}  // namespace g3

@@ -1,0 +1,168 @@
+"""Thin ctypes binding of libg3.so: the C entry points under the same names.
+
+Argument marshalling only: every pointer argument is an integer address
+(a device pointer from ``tensor.data_ptr()``, or a host address), every
+stream a HIP stream handle. All work happens in the library's kernels. The
+library must have been built (``paper_2003_10850_amd.build``); loading fails
+loudly otherwise: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libg3.so")
+
+G3_OK, G3_EINVAL, G3_ENOMEM, G3_EHIP, G3_EOVERFLOW, G3_ENOCONV, G3_ESTATE = 0, -1, -2, -3, -4, -5, -6
+G3_F32, G3_F64 = 0, 1
+G3_GATHER, G3_SYMMETRIC, G3_GRAVITY = 0, 1, 2
+
+STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
+                -4: "G3_EOVERFLOW", -5: "G3_ENOCONV", -6: "G3_ESTATE"}
+
+# every symbol include/g3.h declares
+EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_nonconverged",
+           "g3_build_tree", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
+           "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity")
+
+
+class g3_params(ctypes.Structure):
+    _fields_ = [("n_ngb", ctypes.c_double), ("h_tol", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("theta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("G", ctypes.c_double), ("leaf_size", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+    @classmethod
+    def of(cls, p, **over) -> "g3_params":
+        d = {f: getattr(p, f) for f, _ in cls._fields_}
+        d.update(over)
+        return cls(**d)
+
+
+class G3Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libg3.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2003_10850_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        sig = {
+            "g3_ctx_create": ([ctypes.POINTER(P), ctypes.c_int], ctypes.c_int),
+            "g3_ctx_destroy": ([P], None),
+            "g3_last_error": ([P], ctypes.c_char_p),
+            "g3_ctx_nonconverged": ([P, P, i32], ctypes.c_int),
+            "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_tree_destroy": ([P, P], None),
+            "g3_tree_info": ([P, i32, P, P], ctypes.c_int),
+            "g3_tree_export": ([P, P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_walk": ([P, P, i32, i64, P, P, P, i64, P, P, P, P], ctypes.c_int),
+            "g3_density": ([P, P, i64, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
+            "g3_hydro_force": ([P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_gravity": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def g3_ctx_create(device: int) -> int:
+    h = ctypes.c_void_p()
+    st = lib().g3_ctx_create(ctypes.byref(h), int(device))
+    if st != G3_OK:
+        raise G3Error(st, f"g3_ctx_create(device={device})")
+    return h.value
+
+
+def g3_ctx_destroy(ctx: int) -> None:
+    lib().g3_ctx_destroy(ctx)
+
+
+def g3_last_error(ctx: int) -> str:
+    return (lib().g3_last_error(ctx) or b"").decode()
+
+
+def _check(ctx, st, name, ok=(G3_OK,)):
+    if st not in ok:
+        raise G3Error(st, f"{name}: {g3_last_error(ctx)}")
+    return st
+
+
+def g3_ctx_nonconverged(ctx: int, reset: bool = False) -> int:
+    c = ctypes.c_int64()
+    _check(ctx, lib().g3_ctx_nonconverged(ctx, ctypes.byref(c), int(reset)), "g3_ctx_nonconverged")
+    return int(c.value)
+
+
+def g3_build_tree(ctx, n, pos_t, pos, mass, type_, box, params, tree, stream) -> int:
+    """box: 4 host doubles; tree: existing handle or 0. Returns the handle."""
+    b = (ctypes.c_double * 4)(*[float(x) for x in box])
+    h = ctypes.c_void_p(tree or None)
+    st = lib().g3_build_tree(ctx, int(n), int(pos_t), pos, mass, type_ or None, b,
+                             ctypes.byref(params), ctypes.byref(h), stream)
+    _check(ctx, st, "g3_build_tree")
+    return h.value
+
+
+def g3_tree_destroy(ctx, tree) -> None:
+    lib().g3_tree_destroy(ctx, tree)
+
+
+def g3_tree_info(tree, which):
+    m, k = ctypes.c_int64(), ctypes.c_int64()
+    st = lib().g3_tree_info(tree, int(which), ctypes.byref(m), ctypes.byref(k))
+    if st != G3_OK:
+        raise G3Error(st, "g3_tree_info")
+    return int(m.value), int(k.value)
+
+
+def g3_tree_export(ctx, tree, which, order, keys, start, count, level, skip, mass, com, stream):
+    st = lib().g3_tree_export(ctx, tree, int(which), order, keys, start, count, level, skip,
+                              mass, com, stream)
+    _check(ctx, st, "g3_tree_export")
+
+
+def g3_walk(ctx, tree, kind, n_act, active, h, params, capacity, offsets, lst, stream):
+    """Returns (status, total); status is G3_OK or G3_EOVERFLOW."""
+    total = ctypes.c_int64()
+    st = lib().g3_walk(ctx, tree, int(kind), int(n_act), active or None, h or None,
+                       ctypes.byref(params), int(capacity), offsets, lst or None,
+                       ctypes.byref(total), stream)
+    _check(ctx, st, "g3_walk", ok=(G3_OK, G3_EOVERFLOW))
+    return st, int(total.value)
+
+
+def g3_density(ctx, tree, n_act, active, params, solve_h, h, rho, drho_dh, omega, nngb, stream):
+    st = lib().g3_density(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                          int(solve_h), h, rho or None, drho_dh or None, omega or None,
+                          nngb or None, stream)
+    _check(ctx, st, "g3_density")
+
+
+def g3_hydro_force(ctx, tree, n_act, active, params, vel, u, h, rho, omega, acc, dudt, vsig,
+                   npairs, stream):
+    st = lib().g3_hydro_force(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                              vel, u, h, rho, omega, acc or None, dudt or None, vsig or None,
+                              npairs or None, stream)
+    _check(ctx, st, "g3_hydro_force")
+
+
+def g3_gravity(ctx, tree, n_act, active, params, acc, pot, nterms, stream):
+    st = lib().g3_gravity(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                          acc or None, pot or None, nterms or None, stream)
+    _check(ctx, st, "g3_gravity")

@@ -128,11 +128,37 @@ def plummer(n: int = 1 << 21, n_spheres: int = 32, seed: int = 1,
     pos = pos[order]
     typ = typ[order]
     vel = rng.normal(0.0, sigma_v, (n, 3))
-    return Workload(
+    w = Workload(
         name=f"plummer_n{n}_s{n_spheres}_seed{seed}", pos=pos, vel=vel,
         mass=np.full(n, 1.0 / n), u=np.ones(n), type=typ,
         box=np.array([0.0, 0.0, 0.0, 1.0]),
         params=Params(n_ngb=n_ngb, eps=eps), seed=seed)
+    w.model = dict(centres=centres, counts=counts, a=scale_radius, n_bg=n_bg)
+    return w
+
+
+def model_gas_density(w: Workload) -> np.ndarray:
+    """Gas mass density of the generating model at every particle: the
+    Plummer profiles 3M/(4 pi a^3) (1 + r^2/a^2)^(-5/2) of the spheres plus
+    the uniform background, times the gas share (1/2). Input synthesis only:
+    it gives smooth, realistic smoothing lengths and densities to feed the
+    hydro force and the fixed-h density without solving anything."""
+    m = getattr(w, "model", None)
+    if m is None:  # uniform gas box
+        return np.full(w.n, w.mass.sum() / w.box[3] ** 3)
+    mp = 1.0 / w.n
+    rho = np.full(w.n, m["n_bg"] * mp)
+    a = m["a"]
+    for c, k in zip(m["centres"], m["counts"]):
+        r2 = ((w.pos - c) ** 2).sum(1)
+        rho += 3.0 * k * mp / (4.0 * np.pi * a ** 3) * (1.0 + r2 / a ** 2) ** -2.5
+    return 0.5 * rho
+
+
+def model_smoothing(w: Workload, n_ngb: float | None = None) -> np.ndarray:
+    """h with (4 pi/3) h^3 rho_model = n_ngb m: a synthetic smoothing field."""
+    n_ngb = w.params.n_ngb if n_ngb is None else n_ngb
+    return (3.0 * n_ngb * w.mass / (4.0 * np.pi * model_gas_density(w))) ** (1.0 / 3.0)
 
 
 def lattice(side: int, spacing: float = 1.0) -> np.ndarray:

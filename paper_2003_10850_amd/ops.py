@@ -1,0 +1,178 @@
+"""torch-facing wrappers of the C entry points.
+
+PyTorch provides device memory and the current stream; each call passes
+``data_ptr()`` addresses and ``torch.cuda.current_stream().cuda_stream`` to
+the library, which does all of the work in its HIP kernels. Output tensors are
+in the caller's particle order; rows of particles that are not active keep
+the values of the ``out`` tensors passed in (zeros when the wrapper
+allocates them).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import g3
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return 0 if t is None else t.data_ptr()
+
+
+def _need(t, dtype, shape, name, device):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device:
+        raise TypeError(f"{name} must be a {dtype} tensor on {device}")
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}")
+    return t
+
+
+class Context:
+    """A library context bound to one GPU."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.handle = g3.g3_ctx_create(self.device.index or 0)
+
+    def nonconverged(self, reset: bool = False) -> int:
+        return g3.g3_ctx_nonconverged(self.handle, reset)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            g3.g3_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """The octrees of one particle set (all particles, and the gas ones)."""
+
+    def __init__(self, ctx: Context, pos, mass, type=None, box=(0.0, 0.0, 0.0, 1.0),
+                 params=None):
+        self.ctx = ctx
+        self.handle = 0
+        self.params = params
+        self.build(pos, mass, type, box)
+
+    def build(self, pos, mass, type=None, box=None):
+        dev = self.ctx.device
+        n = int(pos.shape[0])
+        _need(pos, torch.float32, (n, 3), "pos", dev)
+        _need(mass, torch.float32, (n,), "mass", dev)
+        if type is not None:
+            _need(type, torch.uint8, (n,), "type", dev)
+        if box is not None:
+            self.box = tuple(float(b) for b in box)
+        self.n = n
+        self.handle = g3.g3_build_tree(self.ctx.handle, n, g3.G3_F32, _ptr(pos), _ptr(mass),
+                                       _ptr(type), self.box, g3.g3_params.of(self.params),
+                                       self.handle, _stream(dev))
+        return self
+
+    def info(self, which: int):
+        return g3.g3_tree_info(self.handle, which)
+
+    def export(self, which: int = 0) -> dict:
+        dev = self.ctx.device
+        m, k = self.info(which)
+        i32 = dict(dtype=torch.int32, device=dev)
+        d = dict(order=torch.zeros(m, **i32), keys=torch.zeros(m, dtype=torch.int64, device=dev),
+                 start=torch.zeros(k, **i32), count=torch.zeros(k, **i32),
+                 level=torch.zeros(k, **i32), skip=torch.zeros(k, **i32),
+                 mass=torch.zeros(k, dtype=torch.float64, device=dev),
+                 com=torch.zeros((k, 3), dtype=torch.float64, device=dev))
+        g3.g3_tree_export(self.ctx.handle, self.handle, which,
+                          *[_ptr(d[x]) for x in ("order", "keys", "start", "count", "level",
+                                                 "skip", "mass", "com")], _stream(dev))
+        return d
+
+    def close(self):
+        if self.handle and getattr(self.ctx, "handle", None):
+            g3.g3_tree_destroy(self.ctx.handle, self.handle)
+        self.handle = 0
+
+
+def _active(tree, active):
+    if active is None:
+        return tree.n, 0
+    _need(active, torch.int32, (active.shape[0],), "active", tree.ctx.device)
+    return int(active.shape[0]), active.data_ptr()
+
+
+def _zeros(tree, *shape, dtype=torch.float32):
+    return torch.zeros(*shape, dtype=dtype, device=tree.ctx.device)
+
+
+def density(tree: Tree, params=None, h=None, active=None, solve_h: bool = True, out=None):
+    """SPH density of the active gas particles; returns a dict of tensors."""
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    o = out or {}
+    hh = h.clone() if h is not None else _zeros(tree, n)
+    _need(hh, torch.float32, (n,), "h", tree.ctx.device)
+    res = dict(h=hh, rho=o.get("rho", _zeros(tree, n)), drho_dh=o.get("drho_dh", _zeros(tree, n)),
+               omega=o.get("omega", _zeros(tree, n)),
+               nngb=o.get("nngb", _zeros(tree, n, dtype=torch.int32)))
+    na, ap = _active(tree, active)
+    g3.g3_density(tree.ctx.handle, tree.handle, na, ap, p, int(solve_h), _ptr(hh),
+                  _ptr(res["rho"]), _ptr(res["drho_dh"]), _ptr(res["omega"]), _ptr(res["nngb"]),
+                  _stream(tree.ctx.device))
+    return res
+
+
+def hydro_force(tree: Tree, vel, u, h, rho, omega, params=None, active=None, out=None):
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    dev = tree.ctx.device
+    _need(vel, torch.float32, (n, 3), "vel", dev)
+    for name, t in (("u", u), ("h", h), ("rho", rho), ("omega", omega)):
+        _need(t, torch.float32, (n,), name, dev)
+    o = out or {}
+    res = dict(acc=o.get("acc", _zeros(tree, n, 3)), dudt=o.get("dudt", _zeros(tree, n)),
+               vsig=o.get("vsig", _zeros(tree, n)),
+               npairs=o.get("npairs", _zeros(tree, n, dtype=torch.int32)))
+    na, ap = _active(tree, active)
+    g3.g3_hydro_force(tree.ctx.handle, tree.handle, na, ap, p, _ptr(vel), _ptr(u), _ptr(h),
+                      _ptr(rho), _ptr(omega), _ptr(res["acc"]), _ptr(res["dudt"]),
+                      _ptr(res["vsig"]), _ptr(res["npairs"]), _stream(dev))
+    return res
+
+
+def gravity(tree: Tree, params=None, active=None, out=None):
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    o = out or {}
+    res = dict(acc=o.get("acc", _zeros(tree, n, 3)), pot=o.get("pot", _zeros(tree, n)),
+               nterms=o.get("nterms", _zeros(tree, n, dtype=torch.int32)))
+    na, ap = _active(tree, active)
+    g3.g3_gravity(tree.ctx.handle, tree.handle, na, ap, p, _ptr(res["acc"]), _ptr(res["pot"]),
+                  _ptr(res["nterms"]), _stream(tree.ctx.device))
+    return res
+
+
+def walk(tree: Tree, kind: int, params=None, h=None, active=None, capacity=None):
+    """CSR interaction lists (offsets int64 [n_act+1], list int32)."""
+    p = g3.g3_params.of(params or tree.params)
+    na, ap = _active(tree, active)
+    dev = tree.ctx.device
+    offsets = torch.zeros(na + 1, dtype=torch.int64, device=dev)
+    if h is not None:
+        _need(h, torch.float32, (tree.n,), "h", dev)
+    cap = 0 if capacity is None else int(capacity)
+    lst = torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)
+    st, total = g3.g3_walk(tree.ctx.handle, tree.handle, kind, na, ap, _ptr(h), p, cap,
+                           offsets.data_ptr(), lst.data_ptr() if cap else 0, _stream(dev))
+    if st == g3.G3_EOVERFLOW and capacity is None:
+        lst = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
+        st, total = g3.g3_walk(tree.ctx.handle, tree.handle, kind, na, ap, _ptr(h), p, total,
+                               offsets.data_ptr(), lst.data_ptr(), _stream(dev))
+    return offsets, lst[:total], st
