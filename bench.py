@@ -1,0 +1,259 @@
+"""Benchmark of the interaction phase on one MI355X.
+
+One step = the whole hot path over one synthetic snapshot: octree build (all
+particles and gas), SPH density with the smoothing-length solve from a cold
+start, SPH hydro force, Barnes-Hut gravity, every particle active. The
+workload is the paper-like clustered set: N = 2^21 particles (half gas, half
+collisionless) in 32 Plummer spheres on a 20 % uniform background, FP32,
+Wendland C6 with 295 target neighbours, theta = 0.5, eps = 1e-3.
+
+The metric is particle interactions per second: neighbour pairs of the
+density (self included) + hydro pairs + Barnes-Hut terms (particle and node)
+of every active particle, as counted by the kernels themselves (the parity
+tests check those counts against the oracle exactly).
+
+Prints ONE JSON line. The CPU baseline is the FP64 oracle timed on a bounded
+sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP32 operations per interaction (an FMA counts 2), counted from
+# the formulas each kernel evaluates; sqrt, rsqrt and division count 1
+FLOP_DENSITY = 36   # rho and drho/dh of one pair in the support
+FLOP_HYDRO = 74     # pressure + viscosity acceleration, du/dt, signal speed
+FLOP_GRAVITY = 20   # softened monopole or particle term, acc + potential
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
+HBM_TBS = 8.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_10850_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(w, samples: int, seed: int = 0) -> dict:
+    """The FP64 oracle, as it stands, on this host: octree builds in full,
+    density (with the h bisection), hydro and gravity on random samples of
+    the active particles; each op's time is scaled by its sample fraction."""
+    import oracle
+    from paper_2003_10850_amd import inputs
+
+    pos32, vel32, m32, u32 = w.as_f32()
+    P, M = pos32.astype(np.float64), m32.astype(np.float64)
+    p = w.params
+    rng = np.random.default_rng(seed)
+    gas = np.nonzero(w.type == 0)[0]
+    t0 = time.perf_counter()
+    gt = oracle.Tree(P, M, w.box, type=w.type, gas_only=True)
+    at = oracle.Tree(P, M, w.box, type=w.type)
+    t_build = time.perf_counter() - t0
+
+    sd = rng.choice(gas, min(samples, gas.size), replace=False)
+    t0 = time.perf_counter()
+    d = oracle.density(gt, p, active=sd)
+    t_d = time.perf_counter() - t0
+    i_d = float(d["nngb"][sd].sum())
+
+    # hydro inputs: the generating model's smooth fields (no solve needed)
+    h = inputs.model_smoothing(w).astype(np.float32).astype(np.float64)
+    rho = inputs.model_gas_density(w).astype(np.float32).astype(np.float64)
+    sh = rng.choice(gas, min(samples, gas.size), replace=False)
+    t0 = time.perf_counter()
+    hy = oracle.hydro(gt, p, vel32, u32, h, rho, np.ones(w.n), active=sh)
+    t_h = time.perf_counter() - t0
+    i_h = float(hy["npairs"][sh].sum())
+
+    sg = rng.choice(w.n, min(samples, w.n), replace=False)
+    t0 = time.perf_counter()
+    g = oracle.gravity(at, p, active=sg)
+    t_g = time.perf_counter() - t0
+    i_g = float(g["nterms"][sg].sum())
+
+    fd, fh, fg = sd.size / gas.size, sh.size / gas.size, sg.size / w.n
+    t_full = t_build + t_d / fd + t_h / fh + t_g / fg
+    i_full = i_d / fd + i_h / fh + i_g / fg
+    return {
+        "value": i_full / t_full,
+        "unit": "interactions/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle on the same workload: both octrees built in full "
+                   f"({t_build:.2f} s); density with h bisection on {sd.size}, hydro on "
+                   f"{sh.size} gas and gravity on {sg.size} random particles "
+                   f"({t_d:.2f}/{t_h:.2f}/{t_g:.2f} s), each scaled by its sample "
+                   f"fraction; estimated full step {t_full:.1f} s"),
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+    }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 21)
+    ap.add_argument("--spheres", type=int, default=32)
+    ap.add_argument("--cpu-samples", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(the interaction phase is not sharded across GPUs here)"}))
+        return 2
+
+    import torch
+
+    from paper_2003_10850_amd import inputs, ops, g3
+
+    dev = torch.device("cuda", 0)
+    w = inputs.plummer(n=args.n, n_spheres=args.spheres, seed=1)
+    pos32, vel32, m32, u32 = w.as_f32()
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, vel, mass, u, typ = T(pos32), T(vel32), T(m32), T(u32), T(w.type)
+    ctx = ops.Context(dev)
+    p = w.params
+    tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), p)
+    n = w.n
+    h = torch.zeros(n, dtype=torch.float32, device=dev)
+    outd = dict(rho=torch.zeros(n, device=dev), drho_dh=torch.zeros(n, device=dev),
+                omega=torch.zeros(n, device=dev),
+                nngb=torch.zeros(n, dtype=torch.int32, device=dev))
+    outh = dict(acc=torch.zeros(n, 3, device=dev), dudt=torch.zeros(n, device=dev),
+                vsig=torch.zeros(n, device=dev),
+                npairs=torch.zeros(n, dtype=torch.int32, device=dev))
+    outg = dict(acc=torch.zeros(n, 3, device=dev), pot=torch.zeros(n, device=dev),
+                nterms=torch.zeros(n, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream(dev)
+    ev = {k: [] for k in ("build", "density", "hydro", "gravity")}
+
+    def step(record: bool):
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record:
+            marks[0].record(stream)
+        tree.build(pos, mass, typ)
+        if record:
+            marks[1].record(stream)
+        h.zero_()  # cold start of the h solve every step
+        d = ops.density(tree, h=h, out=outd)
+        hh = d["h"]
+        if record:
+            marks[2].record(stream)
+        ops.hydro_force(tree, vel, u, hh, outd["rho"], outd["omega"], out=outh)
+        if record:
+            marks[3].record(stream)
+        ops.gravity(tree, out=outg)
+        if record:
+            marks[4].record(stream)
+            for k, (a, b) in zip(ev, zip(marks[:-1], marks[1:])):
+                ev[k].append((a, b))
+        return d
+
+    print(f"bench: {w.name} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        print(f"bench: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    nonconv = ctx.nonconverged(reset=True)
+    gas = torch.from_numpy(w.type == 0).to(dev)
+    i_d = int(outd["nngb"][gas].sum())
+    i_h = int(outh["npairs"][gas].sum())
+    i_g = int(outg["nterms"].sum())
+    inter = i_d + i_h + i_g
+    times = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    print(f"bench: {args.steps} steps, {ms:.3f} ms/step; per op ms {times}; "
+          f"interactions dens {i_d} hydro {i_h} grav {i_g}; nonconv {nonconv}",
+          file=sys.stderr, flush=True)
+
+    # the dominant kernel: density and gravity are one kernel launch each
+    # when every particle is active; hydro adds its prep and hmax refit
+    flops = {"density": FLOP_DENSITY * i_d, "hydro": FLOP_HYDRO * i_h,
+             "gravity": FLOP_GRAVITY * i_g}
+    kname = {"density": "k_density", "hydro": "k_hydro", "gravity": "k_gravity"}
+    dom = max(("density", "hydro", "gravity"), key=lambda k: times[k])
+    achieved = flops[dom] / (times[dom] * 1e-3) / 1e12
+    traffic = traffic_for(kname[dom])
+    roofline = {"bound": "alu", "kernel": kname[dom], "achieved": achieved,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                "per_op": {k: {"ms": times[k], "tflops": flops[k] / (times[k] * 1e-3) / 1e12
+                               if k in flops else None} for k in times}}
+    line = {
+        "metric": "particle interactions/sec (density+hydro+gravity), batched-FP32 vs plain at stated err",
+        "value": inter / (ms * 1e-3),
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain GPU path, {w.name}: N={n} (half gas) in "
+                               f"{args.spheres} Plummer spheres + 20% background, FP32, "
+                               "Wendland C6 295 neighbours, theta=0.5, eps=1e-3, all active",
+                   "n": n, "interactions_per_step": {"density": i_d, "hydro": i_h,
+                                                     "gravity": i_g},
+                   "h_nonconverged": nonconv, "path": "plain"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_samples)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -61,6 +61,8 @@ def lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.g3ref_threads.argtypes = []
+        L.g3ref_threads.restype = i32
         L.g3ref_kernel.argtypes = [dbl, dbl, P, P, P, P]
         L.g3ref_kernel.restype = None
         L.g3ref_key.argtypes = [P, P]
@@ -96,6 +98,11 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().g3ref_threads())
 
 
 def kernel(r: float, h: float):

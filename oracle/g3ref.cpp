@@ -18,6 +18,10 @@
 #include <numeric>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 const double kPi = 3.14159265358979323846;
@@ -270,6 +274,14 @@ bool solve_h(const g3ref_tree &t, int64_t i, const g3ref_params &p, double rho_b
 } // namespace
 
 extern "C" {
+
+int32_t g3ref_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void g3ref_kernel(double r, double h, double *W, double *dWdr, double *dWdh, double *F) {
   wc6(r, h, W, dWdr, dWdh, F);

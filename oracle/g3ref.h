@@ -53,6 +53,9 @@ enum { G3REF_GATHER = 0, G3REF_SYMMETRIC = 1, G3REF_GRAVITY = 2 };
 
 typedef struct g3ref_tree g3ref_tree;
 
+/* Number of OpenMP threads the parallel loops use. */
+int32_t g3ref_threads(void);
+
 /* Wendland C6 and its derivatives at (r, h): W, dW/dr, dW/dh, F = dW/dr / r. */
 void g3ref_kernel(double r, double h, double *W, double *dWdr, double *dWdh,
                   double *F);

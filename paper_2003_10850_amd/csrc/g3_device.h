@@ -45,6 +45,16 @@ __device__ __forceinline__ float box_dist2(float3 x, float4 lo, float4 hi) {
   return dist2_exact(dx, dy, dz);
 }
 
+// Neumaier's compensated addition: s + c tracks the sum of every x added
+// with an error of a few ulp of the total, independent of the count. The
+// kernels add plain FP32 per-tile partial sums through it.
+__device__ __forceinline__ void neumaier_add(float &s, float &c, float x) {
+#pragma clang fp contract(off)
+  const float t = s + x;
+  c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
 // fl(a * a) with no contraction (the squared search radius).
 __device__ __forceinline__ float sq_exact(float a) {
 #pragma clang fp contract(off)

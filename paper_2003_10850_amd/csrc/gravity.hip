@@ -57,12 +57,15 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const uint64_t mybit = 1ull << lane;
   Entry *tile = tiles[w];
 
+  // totals with Neumaier compensation terms; per-tile partials are plain
   float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+  float cax = 0.f, cay = 0.f, caz = 0.f, cph = 0.f;
   int nt = 0;
   int tc = 0;
 
   auto flush = [&](int nc) {
     wave_sync();
+    float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
     for (int k = 0; k < nc; ++k) {
       const Entry e = tile[k];
       const uint64_t mask = (uint64_t)(uint32_t)e.meta.y | ((uint64_t)(uint32_t)e.meta.z << 32);
@@ -72,12 +75,16 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       const float rinv = __builtin_amdgcn_rsqf(r2);
       const float mr = use ? e.p.w * rinv : 0.0f;
       const float mr3 = mr * rinv * rinv;
-      ax += mr3 * dx;
-      ay += mr3 * dy;
-      az += mr3 * dz;
-      ph -= mr;
+      px += mr3 * dx;
+      py += mr3 * dy;
+      pz += mr3 * dz;
+      pp -= mr;
       nt += use ? 1 : 0;
     }
+    neumaier_add(ax, cax, px);
+    neumaier_add(ay, cay, py);
+    neumaier_add(az, caz, pz);
+    neumaier_add(ph, cph, pp);
     wave_sync();
   };
 
@@ -139,6 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     cur = nd.meta.x;
   }
   if (tc > 0) flush(tc);
+  ax += cax;
+  ay += cay;
+  az += caz;
+  ph += cph;
 
   if (valid) {
     const int cid = perm[s];

@@ -109,12 +109,14 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const bool live = !done;
     const float h2 = live ? sq_exact(hcur) : -1.0f;
     const float hinv = 1.0f / hcur;
-    float sw = 0.0f, swh = 0.0f;
+    // sums of m w and m wh: plain per tile, compensated across tiles
+    float sw = 0.0f, swh = 0.0f, csw = 0.0f, cswh = 0.0f;
     int cnt = 0;
     int tc = 0, cand = 0;
     auto flush = [&](int nc) {
       tile[lane] = (lane < nc) ? xm[cand] : make_float4(0.f, 0.f, 0.f, 0.f);
       wave_sync();
+      float pw = 0.0f, pwh = 0.0f;
       for (int k = 0; k < nc; ++k) {
         const float4 q = tile[k];
         const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
@@ -123,11 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_density(
           const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
           float wv, whv;
           wc6_w_wh(u, wv, whv);
-          sw += q.w * wv;
-          swh += q.w * whv;
+          pw += q.w * wv;
+          pwh += q.w * whv;
           ++cnt;
         }
       }
+      neumaier_add(sw, csw, pw);
+      neumaier_add(swh, cswh, pwh);
       wave_sync();
     };
     int cur = 0;
@@ -157,6 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
       cur = nd.meta.x;
     }
     if (tc > 0) flush(tc);
+    sw += csw;
+    swh += cswh;
 
     if (live) {
       if (!solve) {
@@ -252,7 +258,9 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
   const float ki = kF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
+  // totals with Neumaier compensation terms; per-tile partials are plain
   float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vs = 0.f;
+  float cax = 0.f, cay = 0.f, caz = 0.f, cdu = 0.f;
   int np = 0, tc = 0, cand = 0;
 
   auto flush = [&](int nc) {
@@ -262,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       T.aux[w][lane] = aux[cand];
     }
     wave_sync();
+    float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
     for (int k = 0; k < nc; ++k) {
       const float4 q = T.xm[w][k];
       const float4 qv = T.vh[w][k];
@@ -290,13 +299,17 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           const float gbar = 0.5f * (gi + gj);
           const float mj = q.w;
           const float coef = mj * (Ai * gi + qa.x * gj + Pi * gbar);  // a_i -= coef x_ij
-          ax += coef * dx;
-          ay += coef * dy;
-          az += coef * dz;
-          du += mj * (Ai * gi + 0.5f * Pi * gbar) * vx;
+          px += coef * dx;
+          py += coef * dy;
+          pz += coef * dz;
+          pu += mj * (Ai * gi + 0.5f * Pi * gbar) * vx;
         }
       }
     }
+    neumaier_add(ax, cax, px);
+    neumaier_add(ay, cay, py);
+    neumaier_add(az, caz, pz);
+    neumaier_add(du, cdu, pu);
     wave_sync();
   };
 
@@ -328,6 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     cur = nd.meta.x;
   }
   if (tc > 0) flush(tc);
+  ax += cax;
+  ay += cay;
+  az += caz;
+  du += cdu;
 
   if (valid) {
     const int cid = perm[s];

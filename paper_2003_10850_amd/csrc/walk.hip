@@ -26,7 +26,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_sph(
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
-  const int64_t row = valid ? (rows ? rows[t] : t) : 0;
+  // rows follow `active`; with every particle active they are caller ids
+  const int64_t row = valid ? (rows ? (int64_t)rows[t] : (int64_t)perm[s]) : 0;
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
   const float hi = valid ? vh[s].w : -1.0f;
@@ -84,7 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_grav(
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
-  const int64_t row = valid ? (rows ? rows[t] : t) : 0;
+  // rows follow `active`; with every particle active they are caller ids
+  const int64_t row = valid ? (rows ? (int64_t)rows[t] : (int64_t)perm[s]) : 0;
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
   const uint64_t ki = keys[s];
