@@ -203,7 +203,10 @@ def main() -> int:
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / args.steps
-    nonconv = ctx.nonconverged(reset=True)
+    ctx.stats(reset=True)
+    step(False)  # one more step to read the h-solve pass counts of one step
+    torch.cuda.synchronize()
+    nonconv, passes, waves = ctx.stats(reset=True)
     gas = torch.from_numpy(w.type == 0).to(dev)
     i_d = int(outd["nngb"][gas].sum())
     i_h = int(outh["npairs"][gas].sum())
@@ -245,7 +248,8 @@ def main() -> int:
                                "Wendland C6 295 neighbours, theta=0.5, eps=1e-3, all active",
                    "n": n, "interactions_per_step": {"density": i_d, "hydro": i_h,
                                                      "gravity": i_g},
-                   "h_nonconverged": nonconv, "path": "plain"},
+                   "h_nonconverged": nonconv,
+                   "h_passes_per_wave": passes / max(waves, 1), "path": "plain"},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

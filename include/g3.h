@@ -80,9 +80,11 @@ int g3_ctx_create(g3_ctx **out, int device);
 void g3_ctx_destroy(g3_ctx *ctx);
 /* Text of the last error of this ctx ("" if none). Valid until the next call. */
 const char *g3_last_error(const g3_ctx *ctx);
-/* Number of particles whose h solve hit its iteration or bracket cap since
- * the last reset (reset != 0 clears it). SYNCS the ctx's last stream. */
-int g3_ctx_nonconverged(g3_ctx *ctx, int64_t *count /* host */, int32_t reset);
+/* Counters of the h solve since the last reset (reset != 0 clears them):
+ * stats (host) [4] = particles whose solve hit its iteration or bracket cap
+ * (non-converged), walk passes summed over wavefronts, wavefronts, 0.
+ * SYNCS the ctx's last stream. */
+int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
 
 /*
  * Build (or rebuild in place) the octrees of one particle set: one over all
@@ -154,7 +156,7 @@ int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
  * solve_h = 1: h_i is first solved from (4 pi/3) h^3 rho(h) / m_i = n_ngb to
  * relative accuracy h_tol (h[i] > 0 on entry is the first guess); h is then
  * an output. solve_h = 0: h is an input. Output pointers other than h may be
- * NULL. Non-converged particles are counted (g3_ctx_nonconverged). */
+ * NULL. Non-converged particles are counted (g3_ctx_stats). */
 int g3_density(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                const int32_t *active, const g3_params *p, int32_t solve_h,
                float *h, float *rho, float *drho_dh, float *omega,

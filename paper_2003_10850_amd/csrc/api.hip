@@ -200,19 +200,19 @@ void g3_ctx_destroy(g3_ctx *c) {
 
 const char *g3_last_error(const g3_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
-int g3_ctx_nonconverged(g3_ctx *c, int64_t *count, int32_t reset) {
-  if (!c || !count) return fail(c, G3_EINVAL, "g3_ctx_nonconverged: null argument");
+int g3_ctx_stats(g3_ctx *c, int64_t *stats, int32_t reset) {
+  if (!c || !stats) return fail(c, G3_EINVAL, "g3_ctx_stats: null argument");
   DeviceGuard g(c->device);
   hipStream_t s = c->last_stream;
-  hipError_t e = hipMemcpyAsync(&c->pinned[7], c->counters, sizeof(unsigned long long),
+  hipError_t e = hipMemcpyAsync(&c->pinned[4], c->counters, 4 * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_ctx_nonconverged");
-  *count = c->pinned[7];
+  if (e != hipSuccess) return hip_fail(c, e, "g3_ctx_stats");
+  for (int k = 0; k < 4; ++k) stats[k] = c->pinned[4 + k];
   if (reset) {
-    e = hipMemsetAsync(c->counters, 0, sizeof(unsigned long long), s);
+    e = hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(c, e, "g3_ctx_nonconverged reset");
+    if (e != hipSuccess) return hip_fail(c, e, "g3_ctx_stats reset");
   }
   return G3_OK;
 }

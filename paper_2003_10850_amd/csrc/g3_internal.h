@@ -120,7 +120,7 @@ struct SphParams {
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
                           int64_t max_targets, const SphParams &sp, int solve_h, float *h,
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
-                          unsigned long long *nonconv, hipStream_t s, float hcap);
+                          unsigned long long *counters, hipStream_t s, float hcap);
 hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const float *h,
                              const float *rho, const float *omega, float gamma,
                              hipStream_t s);

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const uint32_t *__restrict__ dcount, int64_t ntmax, float n_ngb, float tol,
     float hcap, int solve, int max_iter, float *__restrict__ h, float *__restrict__ rho,
     float *__restrict__ drho_dh, float *__restrict__ omega, int32_t *__restrict__ nngb,
-    unsigned long long *__restrict__ nonconv) {
+    unsigned long long *__restrict__ counters) {
   __shared__ float4 tiles[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
@@ -104,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
   float res_h = hcur, res_sw = 0.0f, res_swh = 0.0f;
   int res_n = 0;
   bool failed = false;
+  int passes = 0;
 
   for (int iter = 0;; ++iter) {
     const bool live = !done;
@@ -176,9 +177,12 @@ __global__ __launch_bounds__(kBlock) void k_density(
         if (below) lo = fmaxf(lo, hcur);
         else hi = fminf(hi, hcur);
         const float slope = 3.0f + swh / sw;
+        // Newton step on ln N_eff(ln h); the log of the ratio (not a
+        // difference of logs) keeps the step accurate to a few 1e-8 near
+        // the root, well inside the convergence test below
         float hn;
         if (N == n_ngb) hn = hcur;
-        else if (slope > 0.05f) hn = hcur * __expf((__logf(n_ngb) - __logf(N)) / slope);
+        else if (slope > 0.05f) hn = hcur * expf(logf(n_ngb / N) / slope);
         else hn = below ? 2.0f * hcur : 0.5f * hcur;
         hn = fminf(fmaxf(hn, 0.25f * hcur), 4.0f * hcur);
         if (!(hn > lo && hn < hi)) {
@@ -198,7 +202,15 @@ __global__ __launch_bounds__(kBlock) void k_density(
         }
       }
     }
-    if (__ballot(!done) == 0ull) break;
+    if (__ballot(!done) == 0ull) {
+      passes = iter + 1;
+      break;
+    }
+  }
+  // counters: [0] non-converged particles, [1] walk passes, [2] waves
+  if (lane == 0) {
+    atomicAdd(&counters[1], (unsigned long long)passes);
+    atomicAdd(&counters[2], 1ull);
   }
 
   if (valid) {
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     if (drho_dh) drho_dh[cid] = kC * res_swh * hinv * hinv * hinv * hinv;
     if (omega) omega[cid] = 1.0f + res_swh / (3.0f * res_sw);
     if (nngb) nngb[cid] = res_n;
-    if (failed) atomicAdd(nonconv, 1ull);
+    if (failed) atomicAdd(&counters[0], 1ull);
   }
 }
 
@@ -366,11 +378,11 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
                           int64_t max_targets, const SphParams &sp, int solve_h, float *h,
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
-                          unsigned long long *nonconv, hipStream_t s, float hcap) {
+                          unsigned long long *counters, hipStream_t s, float hcap) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
   k_density<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.perm, targets, dcount, max_targets, sp.n_ngb,
-      sp.h_tol, hcap, solve_h, sp.max_iter, h, rho, drho_dh, omega, nngb, nonconv);
+      sp.h_tol, hcap, solve_h, sp.max_iter, h, rho, drho_dh, omega, nngb, counters);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
                 -4: "G3_EOVERFLOW", -5: "G3_ENOCONV", -6: "G3_ESTATE"}
 
 # every symbol include/g3.h declares
-EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_nonconverged",
+EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
            "g3_build_tree", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity")
 
@@ -63,7 +63,7 @@ def lib():
             "g3_ctx_create": ([ctypes.POINTER(P), ctypes.c_int], ctypes.c_int),
             "g3_ctx_destroy": ([P], None),
             "g3_last_error": ([P], ctypes.c_char_p),
-            "g3_ctx_nonconverged": ([P, P, i32], ctypes.c_int),
+            "g3_ctx_stats": ([P, P, i32], ctypes.c_int),
             "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_tree_destroy": ([P, P], None),
             "g3_tree_info": ([P, i32, P, P], ctypes.c_int),
@@ -103,10 +103,11 @@ def _check(ctx, st, name, ok=(G3_OK,)):
     return st
 
 
-def g3_ctx_nonconverged(ctx: int, reset: bool = False) -> int:
-    c = ctypes.c_int64()
-    _check(ctx, lib().g3_ctx_nonconverged(ctx, ctypes.byref(c), int(reset)), "g3_ctx_nonconverged")
-    return int(c.value)
+def g3_ctx_stats(ctx: int, reset: bool = False):
+    """(non-converged particles, walk passes summed over waves, waves)."""
+    c = (ctypes.c_int64 * 4)()
+    _check(ctx, lib().g3_ctx_stats(ctx, c, int(reset)), "g3_ctx_stats")
+    return int(c[0]), int(c[1]), int(c[2])
 
 
 def g3_build_tree(ctx, n, pos_t, pos, mass, type_, box, params, tree, stream) -> int:

@@ -38,8 +38,12 @@ class Context:
             else torch.device(device)
         self.handle = g3.g3_ctx_create(self.device.index or 0)
 
+    def stats(self, reset: bool = False):
+        """(non-converged h solves, walk passes over all waves, waves)."""
+        return g3.g3_ctx_stats(self.handle, reset)
+
     def nonconverged(self, reset: bool = False) -> int:
-        return g3.g3_ctx_nonconverged(self.handle, reset)
+        return self.stats(reset)[0]
 
     def close(self):
         if getattr(self, "handle", None):
