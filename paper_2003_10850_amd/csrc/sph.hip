@@ -184,14 +184,17 @@ __global__ __launch_bounds__(kBlock) void k_density(
         if (N == n_ngb) hn = hcur;
         else if (slope > 0.05f) hn = hcur * expf(logf(n_ngb / N) / slope);
         else hn = below ? 2.0f * hcur : 0.5f * hcur;
+        // converged when the Newton correction itself is below half the
+        // tolerance (h then lies within it of the root), or the bracket has
+        // closed; tested before any safeguard replaces the step
+        const bool conv = fabsf(hn - hcur) <= 0.5f * tol * hcur ||
+                          (hi < INFINITY && hi - lo <= tol * hi);
         hn = fminf(fmaxf(hn, 0.25f * hcur), 4.0f * hcur);
         if (!(hn > lo && hn < hi)) {
           if (hi < INFINITY && lo > 0.0f) hn = 0.5f * (lo + hi);
           else if (hi < INFINITY) hn = 0.5f * hi;
           else hn = 2.0f * lo;
         }
-        const bool conv = fabsf(hn - hcur) <= 0.5f * tol * hcur ||
-                          (hi < INFINITY && hi - lo <= tol * hi);
         const bool capped = below && hcur >= hcap;
         if (conv || capped || iter + 1 >= max_iter) {
           done = true;
