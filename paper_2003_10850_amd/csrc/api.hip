@@ -1,6 +1,7 @@
 // The C ABI of libg3.so (declared in include/g3.h): argument checks, device
 // selection, scratch management and the order of the launches of each call.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -329,6 +330,17 @@ static GravParams grav_params(const g3_params *p) {
   return gp;
 }
 
+// Tuning knob (never result-defining): SPH walks stop descending at
+// subtrees of at most this many members and scan them whole.
+static int walk_leaf_from_env() {
+  static int v = [] {
+    const char *e = std::getenv("G3_WALK_LEAF");
+    int x = e ? std::atoi(e) : 32;
+    return x < 1 ? 1 : (x > 4096 ? 4096 : x);
+  }();
+  return v;
+}
+
 static SphParams sph_params(const g3_params *p) {
   SphParams sp;
   sp.n_ngb = (float)p->n_ngb;
@@ -336,6 +348,7 @@ static SphParams sph_params(const g3_params *p) {
   sp.gamma = (float)p->gamma;
   sp.alpha = (float)p->alpha;
   sp.max_iter = 64;
+  sp.walk_leaf = walk_leaf_from_env();
   return sp;
 }
 

@@ -17,6 +17,17 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Renumber them so that XCD x runs one contiguous range of logical
+// blocks: spatially adjacent groups then share tree nodes and candidates in
+// the same L2. The map is a bijection of [0, nb).
+__device__ __forceinline__ int64_t xcd_block() {
+  constexpr unsigned kXcd = 8;
+  const unsigned b = blockIdx.x, nb = gridDim.x;
+  const unsigned x = b % kXcd, q = nb / kXcd, r = nb % kXcd;
+  return (int64_t)x * q + (x < r ? x : r) + b / kXcd;
+}
+
 // Broadcast of a wave-uniform value into a scalar register.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

@@ -115,6 +115,7 @@ int compact_targets(g3_ctx *c, const Octree &o, const int32_t *iperm, int64_t n_
 struct SphParams {
   float n_ngb, h_tol, gamma, alpha;
   int max_iter;
+  int walk_leaf;  // SPH walks take subtrees of at most this many members whole
 };
 
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,

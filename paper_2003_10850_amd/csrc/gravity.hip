@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   __shared__ Entry tiles[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
   if (g0 >= ntarg) return;
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;

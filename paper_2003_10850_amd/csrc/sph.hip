@@ -73,13 +73,14 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
     const uint32_t *__restrict__ dcount, int64_t ntmax, float n_ngb, float tol,
-    float hcap, int solve, int max_iter, float *__restrict__ h, float *__restrict__ rho,
+    float hcap, int solve, int max_iter, int walk_leaf, float *__restrict__ h,
+    float *__restrict__ rho,
     float *__restrict__ drho_dh, float *__restrict__ omega, int32_t *__restrict__ nngb,
     unsigned long long *__restrict__ counters) {
   __shared__ float4 tiles[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
   if (g0 >= ntarg) return;
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;
@@ -143,7 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
         cur = nd.meta.x;
         continue;
       }
-      if (!(nd.meta.w & kLeafBit)) {
+      // a small subtree is taken whole: its members are one contiguous run
+      if (!(nd.meta.w & kLeafBit) && nd.meta.z > walk_leaf) {
         ++cur;
         continue;
       }
@@ -257,13 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
-    const uint32_t *__restrict__ dcount, int64_t ntmax, float alpha,
+    const uint32_t *__restrict__ dcount, int64_t ntmax, float alpha, int walk_leaf,
     float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
     int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = ((int64_t)blockIdx.x * kWpb + w) * kWave;
+  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
   if (g0 >= ntarg) return;
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;
@@ -337,7 +339,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       cur = nd.meta.x;
       continue;
     }
-    if (!(nd.meta.w & kLeafBit)) {
+    // a small subtree is taken whole: its members are one contiguous run
+    if (!(nd.meta.w & kLeafBit) && nd.meta.z > walk_leaf) {
       ++cur;
       continue;
     }
@@ -385,7 +388,8 @@ hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint3
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
   k_density<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.perm, targets, dcount, max_targets, sp.n_ngb,
-      sp.h_tol, hcap, solve_h, sp.max_iter, h, rho, drho_dh, omega, nngb, counters);
+      sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, h, rho, drho_dh, omega, nngb,
+      counters);
   return hipGetLastError();
 }
 
@@ -404,7 +408,7 @@ hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
   k_hydro<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.vh, gas.aux, gas.perm, targets, dcount,
-      max_targets, sp.alpha, acc, dudt, vsig, npairs);
+      max_targets, sp.alpha, sp.walk_leaf, acc, dudt, vsig, npairs);
   return hipGetLastError();
 }
 
