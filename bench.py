@@ -118,6 +118,60 @@ def cpu_baseline(w, samples: int, seed: int = 0) -> dict:
     }
 
 
+COPY_BYTES = 256 << 20  # the calibration copy: 256 MiB read + 256 MiB written
+
+
+def copy_calibration(dev) -> None:
+    """A plain device copy of known size, profiled beside the kernels so that
+    the HBM byte counters can be scaled by what they read for it."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
+    """HBM bytes per launch of each g3 kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the same
+    counter's reading for the calibration copy of COPY_BYTES."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
+    scale = {}
+    data = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        acc = per_kernel(path, counter)
+        copies = [v for k, vs in acc.items() if "copy" in k.lower() for v in vs
+                  if v * 1024 > 0.5 * COPY_BYTES]
+        if not copies:
+            raise RuntimeError(f"no calibration copy found in {path}")
+        scale[counter] = float(np.median(copies)) * 1024 / COPY_BYTES
+        data[counter] = acc
+    out["counter_scale"] = scale
+    for name in ("k_density", "k_hydro", "k_gravity"):
+        per = {}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [v for k, vs in data[counter].items() if f"::{name}(" in k for v in vs]
+            per[counter] = float(np.mean(vals)) * 1024 / scale[counter] if vals else None
+        if per["FETCH_SIZE"] is not None and per["WRITE_SIZE"] is not None:
+            out["kernels"][name] = {"fetch_bytes": per["FETCH_SIZE"],
+                                    "write_bytes": per["WRITE_SIZE"],
+                                    "bytes_per_launch": per["FETCH_SIZE"] + per["WRITE_SIZE"]}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -138,7 +192,14 @@ def main() -> int:
     ap.add_argument("--spheres", type=int, default=32)
     ap.add_argument("--cpu-samples", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (for HBM counter scaling)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="write per-kernel HBM bytes from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc), indent=1))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                           "(the interaction phase is not sharded across GPUs here)"}))
@@ -252,6 +313,8 @@ def main() -> int:
                    "h_passes_per_wave": passes / max(waves, 1), "path": "plain"},
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        copy_calibration(dev)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_samples)

@@ -335,7 +335,7 @@ static GravParams grav_params(const g3_params *p) {
 static int walk_leaf_from_env() {
   static int v = [] {
     const char *e = std::getenv("G3_WALK_LEAF");
-    int x = e ? std::atoi(e) : 32;
+    int x = e ? std::atoi(e) : 64;
     return x < 1 ? 1 : (x > 4096 ? 4096 : x);
   }();
   return v;
