@@ -42,6 +42,35 @@ __device__ __forceinline__ float wc6_f(float q) {
   return t4 * t2 * t * (1.0f + q * (7.0f + q * 16.0f));
 }
 
+// Bit k of the result is set iff tile entry k passes this lane's exact
+// neighbour test r2 < h2 (gather) or r2 < max(h_i, h_k)^2 (symmetric, with
+// the entries' h in hs[k].w). The cheap test runs over the whole tile; the
+// kernel sums then visit only the set bits, lane by lane.
+__device__ __forceinline__ uint64_t tile_mask(const float4 *tile, float3 xi, float h2) {
+  uint64_t m = 0ull;
+#pragma unroll 8
+  for (int k = 0; k < kTile; ++k) {
+    const float4 q = tile[k];
+    const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                 sub_exact(q.z, xi.z));
+    m |= (uint64_t)(r2 < h2 ? 1u : 0u) << k;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint64_t tile_mask_sym(const float4 *tile, const float4 *hs,
+                                                  float3 xi, float hi) {
+  uint64_t m = 0ull;
+#pragma unroll 8
+  for (int k = 0; k < kTile; ++k) {
+    const float4 q = tile[k];
+    const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                 sub_exact(q.z, xi.z));
+    m |= (uint64_t)(r2 < sq_exact(fmaxf(hi, hs[k].w)) ? 1u : 0u) << k;
+  }
+  return m;
+}
+
 // First guess of h for a group: descend from the root along the group's
 // first member while the child still holds >= n_ngb members, then take the
 // mean density of that node's bounding box (of its cube if the box is flat).
@@ -116,22 +145,27 @@ __global__ __launch_bounds__(kBlock) void k_density(
     int cnt = 0;
     int tc = 0, cand = 0;
     auto flush = [&](int nc) {
-      tile[lane] = (lane < nc) ? xm[cand] : make_float4(0.f, 0.f, 0.f, 0.f);
+      // unused slots sit at infinity and fail every neighbour test
+      tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       wave_sync();
+      // phase 1: each lane marks the tile entries inside its own sphere
+      const uint64_t mask = tile_mask(tile, xi, h2);
+      // phase 2: each lane sums only its own marked entries
       float pw = 0.0f, pwh = 0.0f;
-      for (int k = 0; k < nc; ++k) {
+      uint64_t m = mask;
+      while (m) {
+        const int k = __builtin_ctzll(m);
+        m &= m - 1;
         const float4 q = tile[k];
         const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
                                      sub_exact(q.z, xi.z));
-        if (r2 < h2) {
-          const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
-          float wv, whv;
-          wc6_w_wh(u, wv, whv);
-          pw += q.w * wv;
-          pwh += q.w * whv;
-          ++cnt;
-        }
+        const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
+        float wv, whv;
+        wc6_w_wh(u, wv, whv);
+        pw += q.w * wv;
+        pwh += q.w * whv;
       }
+      cnt += __popcll(mask);
       neumaier_add(sw, csw, pw);
       neumaier_add(swh, cswh, pwh);
       wave_sync();
@@ -285,20 +319,28 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       T.xm[w][lane] = xm[cand];
       T.vh[w][lane] = vh[cand];
       T.aux[w][lane] = aux[cand];
+    } else {  // unused slots sit at infinity and fail every neighbour test
+      T.xm[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+      T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
+    // phase 1: each lane marks its pairs; invalid lanes (hi < 0) mark none
+    uint64_t m = hi > 0.0f ? tile_mask_sym(T.xm[w], T.vh[w], xi, hi) : 0ull;
+    // the self pair (r = 0) always passes: it is counted here and subtracted
+    // at the end; any pair at r = 0 adds nothing to the sums
+    np += __popcll(m);
+    // phase 2: each lane evaluates only its own pairs
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
-    for (int k = 0; k < nc; ++k) {
+    while (m) {
+      const int k = __builtin_ctzll(m);
+      m &= m - 1;
       const float4 q = T.xm[w][k];
       const float4 qv = T.vh[w][k];
       const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
                   dz = sub_exact(q.z, xi.z);
       const float r2 = dist2_exact(dx, dy, dz);
-      if (r2 < sq_exact(fmaxf(hi, qv.w))) {
+      {
         const float4 qa = T.aux[w][k];
-        // the self pair (r = 0) always passes: it is counted here and
-        // subtracted at the end; any pair at r = 0 adds nothing to the sums
-        ++np;
         if (r2 > 0.0f) {
           const float rinv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * rinv;
