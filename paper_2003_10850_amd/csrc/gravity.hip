@@ -54,7 +54,6 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
   const uint64_t ki = keys[s];
-  const uint64_t mybit = 1ull << lane;
   Entry *tile = tiles[w];
 
   // totals with Neumaier compensation terms; per-tile partials are plain
@@ -63,17 +62,21 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   int nt = 0;
   int tc = 0;
 
+  // this lane's bit in an entry's mask: word (low or high half) and offset
+  const bool hiword = lane >= 32;
+  const uint32_t bitpos = (uint32_t)lane & 31u;
   auto flush = [&](int nc) {
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
     for (int k = 0; k < nc; ++k) {
       const Entry e = tile[k];
-      const uint64_t mask = (uint64_t)(uint32_t)e.meta.y | ((uint64_t)(uint32_t)e.meta.z << 32);
-      const bool use = (mask & mybit) && e.meta.x != s;
+      // branch-free use test: the lane's mask bit, and not the target itself
+      const uint32_t word = (uint32_t)(hiword ? e.meta.z : e.meta.y);
+      const bool use = (__builtin_amdgcn_ubfe(word, bitpos, 1u) != 0u) & (e.meta.x != s);
       const float dx = e.p.x - xi.x, dy = e.p.y - xi.y, dz = e.p.z - xi.z;
-      const float r2 = dx * dx + dy * dy + dz * dz + eps2;
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
       const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float mr = use ? e.p.w * rinv : 0.0f;
+      const float mr = (use ? e.p.w : 0.0f) * rinv;
       const float mr3 = mr * rinv * rinv;
       px += mr3 * dx;
       py += mr3 * dy;

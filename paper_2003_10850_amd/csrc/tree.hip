@@ -88,27 +88,40 @@ __device__ __forceinline__ int cpl(uint64_t a, uint64_t b) {
 }
 
 // nodes started by each member: cnt[p] = max(0, d_p - delta_p + 1)
-__global__ void k_node_counts(const uint64_t *__restrict__ keys, int64_t m, int B,
-                              uint32_t *__restrict__ cnt, uint8_t *__restrict__ lev,
-                              int32_t *__restrict__ maxlev) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kMaxLeaf = 64;
+
+__global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restrict__ keys,
+                                                        int64_t m, int B,
+                                                        uint32_t *__restrict__ cnt,
+                                                        uint8_t *__restrict__ lev,
+                                                        int32_t *__restrict__ maxlev) {
+  // the block's keys with B neighbours on each side, staged in LDS
+  __shared__ uint64_t win[kBlock + 2 * kMaxLeaf];
+  const int64_t b0 = (int64_t)blockIdx.x * kBlock;
+  for (int k = threadIdx.x; k < kBlock + 2 * B; k += kBlock) {
+    const int64_t q = b0 - B + k;
+    win[k] = (q >= 0 && q < m) ? keys[q] : 0ull;
+  }
+  __syncthreads();
+  const int64_t p = b0 + threadIdx.x;
   if (p >= m) return;
-  const uint64_t kp = keys[p];
-  const int delta = (p == 0) ? 0 : cpl(kp, keys[p - 1]) + 1;
+  const uint64_t *kw = win + B + threadIdx.x;  // kw[d] = key of member p + d
+  const uint64_t kp = kw[0];
+  const int delta = (p == 0) ? 0 : cpl(kp, kw[-1]) + 1;
   // B-th largest of the window prefix lengths: merge two non-increasing runs
-  int64_t i = 1, j = 1;
+  int i = 1, j = 1;
   int val = -1;
-  int a = (p - 1 >= 0) ? cpl(kp, keys[p - 1]) : -1;
-  int b = (p + 1 < m) ? cpl(kp, keys[p + 1]) : -1;
+  int a = (p - 1 >= 0) ? cpl(kp, kw[-1]) : -1;
+  int b = (p + 1 < m) ? cpl(kp, kw[1]) : -1;
   for (int step = 0; step < B; ++step) {
     if (a >= b) {
       val = a;
       ++i;
-      a = (p - i >= 0) ? cpl(kp, keys[p - i]) : -1;
+      a = (p - i >= 0 && i <= B) ? cpl(kp, kw[-i]) : -1;
     } else {
       val = b;
       ++j;
-      b = (p + j < m) ? cpl(kp, keys[p + j]) : -1;
+      b = (p + j < m && j <= B) ? cpl(kp, kw[j]) : -1;
     }
   }
   int d = val + 1;
