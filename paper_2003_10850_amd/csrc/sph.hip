@@ -98,6 +98,7 @@ __device__ float group_density_guess(const Node *__restrict__ nodes, int s0, flo
   return nd.com_m.w / V;  // mass density
 }
 
+template <bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
@@ -148,24 +149,42 @@ __global__ __launch_bounds__(kBlock) void k_density(
       // unused slots sit at infinity and fail every neighbour test
       tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       wave_sync();
-      // phase 1: each lane marks the tile entries inside its own sphere
-      const uint64_t mask = tile_mask(tile, xi, h2);
-      // phase 2: each lane sums only its own marked entries
       float pw = 0.0f, pwh = 0.0f;
-      uint64_t m = mask;
-      while (m) {
-        const int k = __builtin_ctzll(m);
-        m &= m - 1;
-        const float4 q = tile[k];
-        const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                     sub_exact(q.z, xi.z));
-        const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
-        float wv, whv;
-        wc6_w_wh(u, wv, whv);
-        pw += q.w * wv;
-        pwh += q.w * whv;
+      if constexpr (kCompact) {
+        // phase 1: each lane marks the tile entries inside its own sphere
+        const uint64_t mask = tile_mask(tile, xi, h2);
+        // phase 2: each lane sums only its own marked entries
+        uint64_t m = mask;
+        while (m) {
+          const int k = __builtin_ctzll(m);
+          m &= m - 1;
+          const float4 q = tile[k];
+          const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                       sub_exact(q.z, xi.z));
+          const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
+          float wv, whv;
+          wc6_w_wh(u, wv, whv);
+          pw += q.w * wv;
+          pwh += q.w * whv;
+        }
+        cnt += __popcll(mask);
+      } else {
+        // every lane tests every entry (read by broadcast); the kernel sum
+        // runs under the lanes that pass
+        for (int k = 0; k < nc; ++k) {
+          const float4 q = tile[k];
+          const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                       sub_exact(q.z, xi.z));
+          if (r2 < h2) {
+            const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
+            float wv, whv;
+            wc6_w_wh(u, wv, whv);
+            pw += q.w * wv;
+            pwh += q.w * whv;
+            ++cnt;
+          }
+        }
       }
-      cnt += __popcll(mask);
       neumaier_add(sw, csw, pw);
       neumaier_add(swh, cswh, pwh);
       wave_sync();
@@ -289,6 +308,7 @@ struct HydroTile {
   float4 aux[kWpb][kTile];
 };
 
+template <bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_hydro(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
@@ -324,21 +344,12 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
-    // phase 1: each lane marks its pairs; invalid lanes (hi < 0) mark none
-    uint64_t m = hi > 0.0f ? tile_mask_sym(T.xm[w], T.vh[w], xi, hi) : 0ull;
-    // the self pair (r = 0) always passes: it is counted here and subtracted
-    // at the end; any pair at r = 0 adds nothing to the sums
-    np += __popcll(m);
-    // phase 2: each lane evaluates only its own pairs
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
-    while (m) {
-      const int k = __builtin_ctzll(m);
-      m &= m - 1;
-      const float4 q = T.xm[w][k];
-      const float4 qv = T.vh[w][k];
-      const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
-                  dz = sub_exact(q.z, xi.z);
-      const float r2 = dist2_exact(dx, dy, dz);
+    // one pair (i, entry k) that passed the symmetric neighbour test; the
+    // self pair (r = 0) passes too: it is counted and subtracted at the end,
+    // and any pair at r = 0 adds nothing to the sums
+    auto pair = [&](int k, const float4 &q, const float4 &qv, float dx, float dy, float dz,
+                    float r2) {
       {
         const float4 qa = T.aux[w][k];
         if (r2 > 0.0f) {
@@ -362,6 +373,34 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           py += coef * dy;
           pz += coef * dz;
           pu += mj * (Ai * gi + 0.5f * Pi * gbar) * vx;
+        }
+      }
+    };
+    if constexpr (kCompact) {
+      // phase 1: each lane marks its pairs; invalid lanes (hi < 0) mark none
+      uint64_t m = hi > 0.0f ? tile_mask_sym(T.xm[w], T.vh[w], xi, hi) : 0ull;
+      np += __popcll(m);
+      // phase 2: each lane evaluates only its own pairs
+      while (m) {
+        const int k = __builtin_ctzll(m);
+        m &= m - 1;
+        const float4 q = T.xm[w][k];
+        const float4 qv = T.vh[w][k];
+        const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
+                    dz = sub_exact(q.z, xi.z);
+        pair(k, q, qv, dx, dy, dz, dist2_exact(dx, dy, dz));
+      }
+    } else {
+      // every lane tests every entry (read by broadcast)
+      for (int k = 0; k < nc; ++k) {
+        const float4 q = T.xm[w][k];
+        const float4 qv = T.vh[w][k];
+        const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
+                    dz = sub_exact(q.z, xi.z);
+        const float r2 = dist2_exact(dx, dy, dz);
+        if (r2 < sq_exact(fmaxf(hi, qv.w))) {
+          ++np;
+          pair(k, q, qv, dx, dy, dz, r2);
         }
       }
     }
@@ -428,7 +467,8 @@ hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint3
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
                           unsigned long long *counters, hipStream_t s, float hcap) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  k_density<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+  auto kern = sp.compact ? k_density<true> : k_density<false>;
+  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.perm, targets, dcount, max_targets, sp.n_ngb,
       sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, h, rho, drho_dh, omega, nngb,
       counters);
@@ -448,7 +488,8 @@ hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_
                         int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
                         float *vsig, int32_t *npairs, hipStream_t s) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  k_hydro<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+  auto kern = sp.compact ? k_hydro<true> : k_hydro<false>;
+  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.vh, gas.aux, gas.perm, targets, dcount,
       max_targets, sp.alpha, sp.walk_leaf, acc, dudt, vsig, npairs);
   return hipGetLastError();
