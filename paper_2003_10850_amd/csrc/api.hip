@@ -341,15 +341,6 @@ static int walk_leaf_from_env() {
   return v;
 }
 
-// Tuning knob: SPH tile evaluation, broadcast (0) or per-lane compacted (1).
-static int compact_from_env() {
-  static int v = [] {
-    const char *e = std::getenv("G3_SPH_COMPACT");
-    return e ? (std::atoi(e) != 0) : 0;
-  }();
-  return v;
-}
-
 static SphParams sph_params(const g3_params *p) {
   SphParams sp;
   sp.n_ngb = (float)p->n_ngb;
@@ -358,7 +349,6 @@ static SphParams sph_params(const g3_params *p) {
   sp.alpha = (float)p->alpha;
   sp.max_iter = 64;
   sp.walk_leaf = walk_leaf_from_env();
-  sp.compact = compact_from_env();
   return sp;
 }
 

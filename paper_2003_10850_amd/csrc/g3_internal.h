@@ -116,7 +116,6 @@ struct SphParams {
   float n_ngb, h_tol, gamma, alpha;
   int max_iter;
   int walk_leaf;  // SPH walks take subtrees of at most this many members whole
-  int compact;    // tiles: 1 = per-lane accept masks then own pairs, 0 = broadcast
 };
 
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,

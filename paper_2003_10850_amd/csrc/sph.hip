@@ -42,35 +42,6 @@ __device__ __forceinline__ float wc6_f(float q) {
   return t4 * t2 * t * (1.0f + q * (7.0f + q * 16.0f));
 }
 
-// Bit k of the result is set iff tile entry k passes this lane's exact
-// neighbour test r2 < h2 (gather) or r2 < max(h_i, h_k)^2 (symmetric, with
-// the entries' h in hs[k].w). The cheap test runs over the whole tile; the
-// kernel sums then visit only the set bits, lane by lane.
-__device__ __forceinline__ uint64_t tile_mask(const float4 *tile, float3 xi, float h2) {
-  uint64_t m = 0ull;
-#pragma unroll 8
-  for (int k = 0; k < kTile; ++k) {
-    const float4 q = tile[k];
-    const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                 sub_exact(q.z, xi.z));
-    m |= (uint64_t)(r2 < h2 ? 1u : 0u) << k;
-  }
-  return m;
-}
-
-__device__ __forceinline__ uint64_t tile_mask_sym(const float4 *tile, const float4 *hs,
-                                                  float3 xi, float hi) {
-  uint64_t m = 0ull;
-#pragma unroll 8
-  for (int k = 0; k < kTile; ++k) {
-    const float4 q = tile[k];
-    const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                 sub_exact(q.z, xi.z));
-    m |= (uint64_t)(r2 < sq_exact(fmaxf(hi, hs[k].w)) ? 1u : 0u) << k;
-  }
-  return m;
-}
-
 // First guess of h for a group: descend from the root along the group's
 // first member while the child still holds >= n_ngb members, then take the
 // mean density of that node's bounding box (of its cube if the box is flat).
@@ -98,7 +69,6 @@ __device__ float group_density_guess(const Node *__restrict__ nodes, int s0, flo
   return nd.com_m.w / V;  // mass density
 }
 
-template <bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
@@ -149,40 +119,22 @@ __global__ __launch_bounds__(kBlock) void k_density(
       // unused slots sit at infinity and fail every neighbour test
       tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       wave_sync();
+      // every lane tests every entry (read by broadcast); the kernel sum runs
+      // under the lanes that pass, and is skipped when none does. (Marking
+      // each lane's entries first and then visiting only its own measured
+      // slower: it costs occupancy and per-lane LDS addressing.)
       float pw = 0.0f, pwh = 0.0f;
-      if constexpr (kCompact) {
-        // phase 1: each lane marks the tile entries inside its own sphere
-        const uint64_t mask = tile_mask(tile, xi, h2);
-        // phase 2: each lane sums only its own marked entries
-        uint64_t m = mask;
-        while (m) {
-          const int k = __builtin_ctzll(m);
-          m &= m - 1;
-          const float4 q = tile[k];
-          const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                       sub_exact(q.z, xi.z));
+      for (int k = 0; k < nc; ++k) {
+        const float4 q = tile[k];
+        const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
+                                     sub_exact(q.z, xi.z));
+        if (r2 < h2) {
           const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
           float wv, whv;
           wc6_w_wh(u, wv, whv);
           pw += q.w * wv;
           pwh += q.w * whv;
-        }
-        cnt += __popcll(mask);
-      } else {
-        // every lane tests every entry (read by broadcast); the kernel sum
-        // runs under the lanes that pass
-        for (int k = 0; k < nc; ++k) {
-          const float4 q = tile[k];
-          const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                       sub_exact(q.z, xi.z));
-          if (r2 < h2) {
-            const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
-            float wv, whv;
-            wc6_w_wh(u, wv, whv);
-            pw += q.w * wv;
-            pwh += q.w * whv;
-            ++cnt;
-          }
+          ++cnt;
         }
       }
       neumaier_add(sw, csw, pw);
@@ -308,7 +260,6 @@ struct HydroTile {
   float4 aux[kWpb][kTile];
 };
 
-template <bool kCompact>
 __global__ __launch_bounds__(kBlock) void k_hydro(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
@@ -376,32 +327,16 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
         }
       }
     };
-    if constexpr (kCompact) {
-      // phase 1: each lane marks its pairs; invalid lanes (hi < 0) mark none
-      uint64_t m = hi > 0.0f ? tile_mask_sym(T.xm[w], T.vh[w], xi, hi) : 0ull;
-      np += __popcll(m);
-      // phase 2: each lane evaluates only its own pairs
-      while (m) {
-        const int k = __builtin_ctzll(m);
-        m &= m - 1;
-        const float4 q = T.xm[w][k];
-        const float4 qv = T.vh[w][k];
-        const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
-                    dz = sub_exact(q.z, xi.z);
-        pair(k, q, qv, dx, dy, dz, dist2_exact(dx, dy, dz));
-      }
-    } else {
-      // every lane tests every entry (read by broadcast)
-      for (int k = 0; k < nc; ++k) {
-        const float4 q = T.xm[w][k];
-        const float4 qv = T.vh[w][k];
-        const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
-                    dz = sub_exact(q.z, xi.z);
-        const float r2 = dist2_exact(dx, dy, dz);
-        if (r2 < sq_exact(fmaxf(hi, qv.w))) {
-          ++np;
-          pair(k, q, qv, dx, dy, dz, r2);
-        }
+    // every lane tests every entry (read by broadcast)
+    for (int k = 0; k < nc; ++k) {
+      const float4 q = T.xm[w][k];
+      const float4 qv = T.vh[w][k];
+      const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
+                  dz = sub_exact(q.z, xi.z);
+      const float r2 = dist2_exact(dx, dy, dz);
+      if (r2 < sq_exact(fmaxf(hi, qv.w))) {
+        ++np;
+        pair(k, q, qv, dx, dy, dz, r2);
       }
     }
     neumaier_add(ax, cax, px);
@@ -467,8 +402,7 @@ hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint3
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
                           unsigned long long *counters, hipStream_t s, float hcap) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  auto kern = sp.compact ? k_density<true> : k_density<false>;
-  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+  k_density<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.perm, targets, dcount, max_targets, sp.n_ngb,
       sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, h, rho, drho_dh, omega, nngb,
       counters);
@@ -488,8 +422,7 @@ hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_
                         int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
                         float *vsig, int32_t *npairs, hipStream_t s) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  auto kern = sp.compact ? k_hydro<true> : k_hydro<false>;
-  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+  k_hydro<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
       gas.nodes, (int)gas.nnodes, gas.xm, gas.vh, gas.aux, gas.perm, targets, dcount,
       max_targets, sp.alpha, sp.walk_leaf, acc, dudt, vsig, npairs);
   return hipGetLastError();
