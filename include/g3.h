@@ -97,7 +97,13 @@ int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
  * stored in preorder with children in Morton order. Node monopoles (mass,
  * centre of mass) are summed in FP64.
  *   n      particles (0 allowed)
- *   pos_t  G3_F32 (pos is float[n][3]); G3_F64 is not accepted yet
+ *   pos_t  G3_F32 (pos is float[n][3]: the plain path) or G3_F64 (pos is
+ *          double[n][3]: the mixed-precision path). With G3_F64 the tree keeps
+ *          the FP64 positions; the kernels work on FP32 offsets from each
+ *          wavefront's group centre with compensated sums, take every
+ *          neighbour and opening decision exactly in FP64 (an FP32 test on
+ *          the offsets, re-tested in FP64 inside its error band), and solve
+ *          h in FP64. The h arrays of that tree's SPH calls are double.
  *   pos    [n][3] positions;  mass [n];  type [n] (0 gas, 1 collisionless;
  *          NULL: all gas)
  *   box    (host) [4] = lower corner xyz, side > 0
@@ -135,14 +141,16 @@ int g3_tree_export(g3_ctx *ctx, const g3_tree *tree, int32_t which,
  *                as -(k + 1).
  * Neighbour test (exact, FP32): dx = fl(x_j - x_i) per axis,
  * r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)), neighbour iff r2 < fl(H * H).
- *   h        [n] smoothing lengths (GATHER, SYMMETRIC; ignored for GRAVITY)
+ *   h        [n] float smoothing lengths (GATHER, SYMMETRIC; ignored for
+ *            GRAVITY)
  *   offsets  [n_act + 1] int64 output
  *   list     [capacity] output; entries of a row in walk order
  *   total    (host) output: offsets[n_act]
  * SYNCS. Returns G3_EOVERFLOW, with *total and offsets valid and list
- * untouched, when *total > capacity. */
+ * untouched, when *total > capacity. Trees built from FP64 positions are
+ * rejected (G3_EINVAL): lists are built for the plain path only. */
 int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
-            const int32_t *active, const float *h, const g3_params *p,
+            const int32_t *active, const void *h, const g3_params *p,
             int64_t capacity, int64_t *offsets, int32_t *list, int64_t *total,
             void *stream);
 
@@ -155,11 +163,13 @@ int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
  *   nngb_i  = number of gas j meeting the neighbour test at h_i
  * solve_h = 1: h_i is first solved from (4 pi/3) h^3 rho(h) / m_i = n_ngb to
  * relative accuracy h_tol (h[i] > 0 on entry is the first guess); h is then
- * an output. solve_h = 0: h is an input. Output pointers other than h may be
- * NULL. Non-converged particles are counted (g3_ctx_stats). */
+ * an output. solve_h = 0: h is an input. h is float for a tree built from
+ * FP32 positions, double for FP64 positions (the h solve then runs in FP64).
+ * Output pointers other than h may be NULL. Non-converged particles are
+ * counted (g3_ctx_stats). */
 int g3_density(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                const int32_t *active, const g3_params *p, int32_t solve_h,
-               float *h, float *rho, float *drho_dh, float *omega,
+               void *h, float *rho, float *drho_dh, float *omega,
                int32_t *nngb, void *stream);
 
 /*
@@ -175,12 +185,13 @@ int g3_density(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
  *   vsig_i = max_j (c_i + c_j - 3 min(w, 0))   (0 with no pair)
  * with x_ij = x_i - x_j, v_ij = v_i - v_j; pairs at r = 0 add nothing.
  *   vel [n][3], u [n], h [n], rho [n], omega [n]: inputs for every gas
- *   particle (neighbours need theirs); acc [n][3], dudt, vsig, npairs
- *   (number of pairs of i) are outputs, each nullable.
+ *   particle (neighbours need theirs); h is float or double like the
+ *   tree's positions; acc [n][3], dudt, vsig, npairs (number of pairs of i)
+ *   are outputs, each nullable.
  * Refits the gas octree's per-node maximum h from `h` first. */
 int g3_hydro_force(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
                    const int32_t *active, const g3_params *p, const float *vel,
-                   const float *u, const float *h, const float *rho,
+                   const float *u, const void *h, const float *rho,
                    const float *omega, float *acc, float *dudt, float *vsig,
                    int32_t *npairs, void *stream);
 

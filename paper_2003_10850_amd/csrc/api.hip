@@ -173,7 +173,7 @@ int g3_ctx_create(g3_ctx **out, int device) {
 
 static void free_octree(Octree &o) {
   for (void *p : {(void *)o.keys, (void *)o.perm, (void *)o.xm, (void *)o.nodes, (void *)o.mom,
-                  (void *)o.vh, (void *)o.aux})
+                  (void *)o.vh, (void *)o.aux, (void *)o.x64, (void *)o.h64, (void *)o.c64})
     if (p) (void)hipFree(p);
   o = Octree();
 }
@@ -223,7 +223,8 @@ int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const fl
                   void *stream) {
   if (!c) return G3_EINVAL;
   if (n < 0 || n >= (int64_t)INT32_MAX) return fail(c, G3_EINVAL, "g3_build_tree: n out of range");
-  if (pos_t != G3_F32) return fail(c, G3_EINVAL, "g3_build_tree: only G3_F32 positions");
+  if (pos_t != G3_F32 && pos_t != G3_F64)
+    return fail(c, G3_EINVAL, "g3_build_tree: pos_t must be G3_F32 or G3_F64");
   if (n > 0 && (!pos || !mass)) return fail(c, G3_EINVAL, "g3_build_tree: null pos/mass");
   if (!box || !(box[3] > 0.0) || !std::isfinite(box[0]) || !std::isfinite(box[1]) ||
       !std::isfinite(box[2]) || !std::isfinite(box[3]))
@@ -259,15 +260,21 @@ int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const fl
   std::memcpy(t->box, box, sizeof(t->box));
   t->scale = std::ldexp(1.0, kMaxLevel) / box[3];
   t->leaf = p->leaf_size;
-  const float *fpos = (const float *)pos;
-  st = build_octree(c, t, t->all, fpos, mass, n, s);
+  t->f64 = pos_t == G3_F64;
+  // FP64 positions are walked through their FP32 copies: pad every pruning
+  // radius by a bound on the rounding of coordinates as large as the box's
+  double amax = 0.0;
+  for (int a = 0; a < 3; ++a)
+    amax = std::max(amax, std::max(std::fabs(box[a]), std::fabs(box[a] + box[3])));
+  t->slack = t->f64 ? (float)std::ldexp(amax, -20) : 0.0f;
+  st = build_octree(c, t, t->all, pos, t->f64, mass, n, s);
   if (st) return st;
   hipError_t e = fill_i32(t->iperm_gas, -1, n, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_build_tree");
   int64_t mgas = 0;
   st = select_gas(c, type, n, &mgas, s);
   if (st) return st;
-  st = build_octree(c, t, t->gas, fpos, mass, mgas, s);
+  st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s);
   if (st) return st;
   c->err.clear();
   return G3_OK;
@@ -319,7 +326,7 @@ int g3_tree_export(g3_ctx *c, const g3_tree *t, int32_t which, int32_t *order, u
   return G3_OK;
 }
 
-static GravParams grav_params(const g3_params *p) {
+static GravParams grav_params(const g3_params *p, const g3_tree *t) {
   GravParams gp;
   gp.theta2 = (float)(p->theta * p->theta);
   gp.eps2 = (float)(p->eps * p->eps);
@@ -327,6 +334,9 @@ static GravParams grav_params(const g3_params *p) {
   // a point inside a node's cube is within sqrt(3) l of its centre of mass,
   // so the containment test can only matter when theta^2 >= 1/3
   gp.inside_test = p->theta * p->theta >= 0.33 ? 1 : 0;
+  gp.f64 = t->f64;
+  gp.theta = p->theta;
+  gp.side = t->box[3];
   return gp;
 }
 
@@ -341,7 +351,7 @@ static int walk_leaf_from_env() {
   return v;
 }
 
-static SphParams sph_params(const g3_params *p) {
+static SphParams sph_params(const g3_params *p, const g3_tree *t) {
   SphParams sp;
   sp.n_ngb = (float)p->n_ngb;
   sp.h_tol = (float)p->h_tol;
@@ -349,6 +359,8 @@ static SphParams sph_params(const g3_params *p) {
   sp.alpha = (float)p->alpha;
   sp.max_iter = 64;
   sp.walk_leaf = walk_leaf_from_env();
+  sp.f64 = t->f64;
+  sp.slack = t->slack;
   return sp;
 }
 
@@ -363,11 +375,13 @@ static int active_args_ok(g3_ctx *c, const g3_tree *t, int64_t n_act, const int3
 }
 
 int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int32_t *active,
-            const float *h, const g3_params *p, int64_t capacity, int64_t *offsets,
+            const void *h, const g3_params *p, int64_t capacity, int64_t *offsets,
             int32_t *list, int64_t *total, void *stream) {
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, tc, n_act, active, "g3_walk");
   if (st) return st;
+  if (tc->f64)
+    return fail(c, G3_EINVAL, "g3_walk: explicit lists are built for FP32 trees only");
   if (kind != G3_GATHER && kind != G3_SYMMETRIC && kind != G3_GRAVITY)
     return fail(c, G3_EINVAL, "g3_walk: unknown kind");
   if (!params_ok(p) || !offsets || !total || capacity < 0 || (capacity > 0 && !list))
@@ -384,7 +398,7 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   const int32_t *iperm = (kind == G3_GRAVITY) ? t->iperm_all : t->iperm_gas;
   hipError_t e;
   if (kind != G3_GRAVITY && o.n > 0) {
-    e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, s);
+    e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
     if (e == hipSuccess && kind == G3_SYMMETRIC) e = refit_hmax(o, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk prep");
   }
@@ -397,9 +411,9 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   int64_t *stmp = (int64_t *)scratch(c, kMisc, scan_tmp_elems(n_act) * sizeof(int64_t) + 64);
   if (!counts || !stmp) return fail(c, G3_ENOMEM, "g3_walk: allocation failed");
   e = fill_i32(counts, 0, n_act, s);
-  GravParams gp = grav_params(p);
+  GravParams gp = grav_params(p, t);
   if (e == hipSuccess)
-    e = launch_walk(o, kind, targets, rows, dcount, maxt, h, gp, counts, nullptr, nullptr, s);
+    e = launch_walk(o, kind, targets, rows, dcount, maxt, gp, counts, nullptr, nullptr, s);
   if (e == hipSuccess) e = scan_i32_to_i64(counts, offsets, n_act, stmp, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&c->pinned[3], offsets + n_act, sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -408,7 +422,7 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   *total = c->pinned[3];
   if (*total > capacity) return fail(c, G3_EOVERFLOW, "g3_walk: list exceeds capacity");
   if (*total > 0) {
-    e = launch_walk(o, kind, targets, rows, dcount, maxt, h, gp, counts, offsets, list, s);
+    e = launch_walk(o, kind, targets, rows, dcount, maxt, gp, counts, offsets, list, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk fill pass");
   }
   c->err.clear();
@@ -416,7 +430,7 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
 }
 
 int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
-               const g3_params *p, int32_t solve_h, float *h, float *rho, float *drho_dh,
+               const g3_params *p, int32_t solve_h, void *h, float *rho, float *drho_dh,
                float *omega, int32_t *nngb, void *stream) {
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_density");
@@ -436,7 +450,7 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   if (st) return st;
   const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
   const float hcap = (float)(2.0 * std::sqrt(3.0) * t->box[3]);
-  hipError_t e = launch_density(o, targets, dcount, maxt, sph_params(p), solve_h ? 1 : 0, h,
+  hipError_t e = launch_density(o, targets, dcount, maxt, sph_params(p, t), solve_h ? 1 : 0, h,
                                 rho, drho_dh, omega, nngb, c->counters, s, hcap);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
@@ -444,7 +458,7 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
 }
 
 int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
-                   const g3_params *p, const float *vel, const float *u, const float *h,
+                   const g3_params *p, const float *vel, const float *u, const void *h,
                    const float *rho, const float *omega, float *acc, float *dudt, float *vsig,
                    int32_t *npairs, void *stream) {
   if (!c) return G3_EINVAL;
@@ -459,8 +473,8 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   Octree &o = t->gas;
-  const SphParams sp = sph_params(p);
-  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, s);
+  const SphParams sp = sph_params(p, t);
+  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
   if (e == hipSuccess) e = refit_hmax(o, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
   int32_t *targets, *rows;
@@ -491,7 +505,8 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   st = compact_targets(c, o, t->iperm_all, t->n, n_act, active, &targets, &rows, &dcount, s);
   if (st) return st;
   const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
-  hipError_t e = launch_gravity(o, targets, dcount, maxt, grav_params(p), acc, pot, nterms, s);
+  hipError_t e =
+      launch_gravity(o, targets, dcount, maxt, grav_params(p, t), acc, pot, nterms, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
   c->err.clear();
   return G3_OK;

@@ -40,6 +40,13 @@ struct Octree {
   // SPH member data in sorted order (gas octree only, filled by the calls)
   float4 *vh = nullptr;   // (vx, vy, vz, h)
   float4 *aux = nullptr;  // (A, c, rho, 1/h)
+  // FP64 positions (x, y, z, m) in sorted order: trees built from FP64 input
+  double4 *x64 = nullptr;
+  int64_t cap_x64 = 0;
+  double *h64 = nullptr;  // FP64 h in sorted order (FP64 trees, SPH calls)
+  int64_t cap_h64 = 0;
+  double4 *c64 = nullptr;  // [nnodes] FP64 centre of mass and mass (FP64 trees)
+  int64_t cap_c64 = 0;
 };
 
 }  // namespace g3
@@ -52,6 +59,8 @@ struct g3_tree {
   double box[4] = {0, 0, 0, 1};
   double scale = 0;  // 2^21 / side
   int32_t leaf = 8;
+  int32_t f64 = 0;   // positions (and h) are FP64: the mixed-precision path
+  float slack = 0;   // bound on the rounding of the FP32 position copies
   int32_t *iperm_all = nullptr;  // [n] caller id -> position in `all`
   int32_t *iperm_gas = nullptr;  // [n] caller id -> position in `gas`, or -1
   g3::Octree all, gas;
@@ -99,8 +108,8 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
                             uint32_t *vals_alt, int64_t n, void *tmp, hipStream_t s);
 
 // Tree build of one octree (members already selected in `ids`/`keys`).
-int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float *mass,
-                 int64_t m, hipStream_t s);
+int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
+                 const float *mass, int64_t m, hipStream_t s);
 hipError_t refit_hmax(Octree &o, hipStream_t s);
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
@@ -116,14 +125,16 @@ struct SphParams {
   float n_ngb, h_tol, gamma, alpha;
   int max_iter;
   int walk_leaf;  // SPH walks take subtrees of at most this many members whole
+  int f64;        // FP64 positions and h: mixed-precision kernels
+  float slack;    // walk pruning pad for FP32 copies of FP64 positions (0 if FP32)
 };
 
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const SphParams &sp, int solve_h, float *h,
+                          int64_t max_targets, const SphParams &sp, int solve_h, void *h,
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
                           unsigned long long *counters, hipStream_t s, float hcap);
-hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const float *h,
-                             const float *rho, const float *omega, float gamma,
+hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const void *h,
+                             const float *rho, const float *omega, float gamma, int f64,
                              hipStream_t s);
 hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
                         int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
@@ -132,6 +143,9 @@ hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_
 struct GravParams {
   float theta2, eps2, G;
   int inside_test;  // evaluate the cube-containment test (theta^2 >= 1/3)
+  int f64;          // FP64 positions: mixed-precision kernels, FP64 decisions
+  double theta;     // opening angle (FP64 decisions)
+  double side;      // root cube side (node sides for FP64 decisions)
 };
 hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint32_t *dcount,
                           int64_t max_targets, const GravParams &gp, float *acc, float *pot,
@@ -139,7 +153,7 @@ hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint3
 
 // Walk lists: counts pass (list == nullptr) or fill pass.
 hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
-                       const uint32_t *dcount, int64_t max_targets, const float *h_caller,
+                       const uint32_t *dcount, int64_t max_targets,
                        const GravParams &gp, int32_t *counts, const int64_t *offsets,
                        int32_t *list, hipStream_t s);
 

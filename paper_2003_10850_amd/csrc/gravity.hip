@@ -37,12 +37,26 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
   return lhs < rhs;
 }
 
+// The opening test in FP64 on the stored FP64 positions and node centres:
+// l l < (theta theta) ((dx dx + dy dy) + dz dz), no contraction.
+__device__ __forceinline__ bool open_accept64(double l, double theta, double4 c, double4 x) {
+#pragma clang fp contract(off)
+  const double dx = c.x - x.x, dy = c.y - x.y, dz = c.z - x.z;
+  return l * l < theta * theta * ((dx * dx + dy * dy) + dz * dz);
+}
+
+// Mixed precision (kF64): positions are stored in FP64 and a wave works on
+// FP32 offsets from a group centre (its first target); the node centres of
+// mass come from FP64 moments. Near the threshold, where the FP32 test on
+// offsets could disagree with the FP64 one, the FP64 test decides.
+template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_gravity(
-    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const Node *__restrict__ nodes, const double4 *__restrict__ c64n, int nnodes,
+    const float4 *__restrict__ xm, const double4 *__restrict__ x64,
     const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
     const int32_t *__restrict__ targets, const uint32_t *__restrict__ dcount, int64_t ntmax,
-    float theta2, float eps2, float G, int inside_test, float *__restrict__ acc,
-    float *__restrict__ pot, int32_t *__restrict__ nterms) {
+    float theta2, float eps2, float G, int inside_test, double theta64, double side,
+    float *__restrict__ acc, float *__restrict__ pot, int32_t *__restrict__ nterms) {
   __shared__ Entry tiles[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
@@ -52,7 +66,15 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
   const float4 me = xm[s];
-  const float3 xi = make_float3(me.x, me.y, me.z);
+  float3 xi = make_float3(me.x, me.y, me.z);
+  double4 p64 = make_double4(0, 0, 0, 0), cg = make_double4(0, 0, 0, 0);
+  float ai = 0.0f;  // |offset| of this lane (mixed precision band)
+  if constexpr (kF64) {
+    cg = x64[uniform(targets ? targets[g0] : (int)g0)];
+    p64 = x64[s];
+    xi = make_float3((float)(p64.x - cg.x), (float)(p64.y - cg.y), (float)(p64.z - cg.z));
+    ai = sqrtf(xi.x * xi.x + xi.y * xi.y + xi.z * xi.z);
+  }
   const uint64_t ki = keys[s];
   Entry *tile = tiles[w];
 
@@ -96,9 +118,26 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   while (cur < nnodes) {
     const Node nd = nodes[cur];
     const bool act = cur >= resume;
-    const float r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
-                                 sub_exact(nd.com_m.z, xi.z));
+    float4 com = nd.com_m;  // centre of mass in the wave's frame, and mass
+    double4 cn = make_double4(0, 0, 0, 0);
+    if constexpr (kF64) {
+      cn = c64n[cur];
+      com = make_float4((float)(cn.x - cg.x), (float)(cn.y - cg.y), (float)(cn.z - cg.z),
+                        com.w);
+    }
+    const float r2 = dist2_exact(sub_exact(com.x, xi.x), sub_exact(com.y, xi.y),
+                                 sub_exact(com.z, xi.z));
     bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
+    if constexpr (kF64) {
+      // |FP32 r2 - FP64 r2| <= 2^-21.5 r (|o_i| + |o_c| + r) + 2^-23 r2 for
+      // offsets o; the FP64 test decides inside 4x that band
+      const float lhs = nd.hi_l.w * nd.hi_l.w, rhs = theta2 * r2;
+      const float r = sqrtf(r2);
+      const float ac = sqrtf(com.x * com.x + com.y * com.y + com.z * com.z);
+      const float band = rhs * 1.9073486e-6f * ((ai + ac) / fmaxf(r, 1e-30f) + 4.0f);
+      if (act && fabsf(lhs - rhs) <= band)
+        accept = open_accept64(ldexp(side, -(nd.meta.w & 255)), theta64, cn, p64);
+    }
     if (inside_test) {
       const int level = nd.meta.w & 255;
       const uint64_t nk = keys[nd.meta.y];
@@ -115,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       }
       if (lane == 0) {
         Entry e;
-        e.p = nd.com_m;
+        e.p = com;
         e.meta = make_int4(-1, (int)(uint32_t)amask, (int)(uint32_t)(amask >> 32), 0);
         tile[tc] = e;
       }
@@ -138,7 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       const int take = min(c, kTile - tc);
       if (lane < take) {
         Entry e;
-        e.p = xm[st + lane];
+        if constexpr (kF64) {
+          const double4 pj = x64[st + lane];
+          e.p = make_float4((float)(pj.x - cg.x), (float)(pj.y - cg.y), (float)(pj.z - cg.z),
+                            (float)pj.w);
+        } else {
+          e.p = xm[st + lane];
+        }
         e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
         tile[tc + lane] = e;
       }
@@ -173,9 +218,10 @@ hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint3
                           int32_t *nterms, hipStream_t s) {
   if (max_targets <= 0 || all.nnodes == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
-  k_gravity<<<blocks, kBlock, 0, s>>>(all.nodes, (int)all.nnodes, all.xm, all.keys, all.perm,
-                                      targets, dcount, max_targets, gp.theta2, gp.eps2, gp.G,
-                                      gp.inside_test, acc, pot, nterms);
+  auto kern = gp.f64 ? k_gravity<true> : k_gravity<false>;
+  kern<<<blocks, kBlock, 0, s>>>(all.nodes, all.c64, (int)all.nnodes, all.xm, all.x64, all.keys,
+                                 all.perm, targets, dcount, max_targets, gp.theta2, gp.eps2,
+                                 gp.G, gp.inside_test, gp.theta, gp.side, acc, pot, nterms);
   return hipGetLastError();
 }
 

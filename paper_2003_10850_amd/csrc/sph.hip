@@ -9,6 +9,8 @@
 // wave wide); every lane then scans the tile against its own target with the
 // exact neighbour test, so walk and interaction sums are decoupled without a
 // per-particle list in memory.
+#include <type_traits>
+
 #include "g3_device.h"
 #include "g3_internal.h"
 
@@ -69,15 +71,38 @@ __device__ float group_density_guess(const Node *__restrict__ nodes, int s0, flo
   return nd.com_m.w / V;  // mass density
 }
 
+// FP64 neighbour test on the stored FP64 positions, the same expression as
+// the mixed-precision definition: ((dx dx + dy dy) + dz dz) < H H.
+__device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
+#pragma clang fp contract(off)
+  const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+  return (dx * dx + dy * dy) + dz * dz < H * H;
+}
+
+// Mixed precision: a wave works on FP32 offsets o = fl32(x - c) from a group
+// centre c (its first target), so their rounding scales with the group's
+// extent. The FP32 test r2 < fl32(H^2) on offsets differs from the exact
+// FP64 test by at most about 2^-21.5 (|o_i|/H + 3.4) H^2 for candidates
+// within reach; inside the band 2^-19 (|o_i|/H + 4) H^2 around the
+// threshold the FP64 test decides. This keeps every decision exact.
+__device__ __forceinline__ float band64(float3 o, float H2, float H) {
+  const float a = sqrtf(o.x * o.x + o.y * o.y + o.z * o.z);
+  return H2 * 1.9073486e-6f * (a / H + 4.0f);  // 2^-19
+}
+
+template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
-    const uint32_t *__restrict__ dcount, int64_t ntmax, float n_ngb, float tol,
-    float hcap, int solve, int max_iter, int walk_leaf, float *__restrict__ h,
-    float *__restrict__ rho,
-    float *__restrict__ drho_dh, float *__restrict__ omega, int32_t *__restrict__ nngb,
+    const double4 *__restrict__ x64, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ targets, const uint32_t *__restrict__ dcount, int64_t ntmax,
+    float n_ngb, float tol, float hcap, int solve, int max_iter, int walk_leaf, float slack,
+    void *__restrict__ hptr, float *__restrict__ rho, float *__restrict__ drho_dh,
+    float *__restrict__ omega, int32_t *__restrict__ nngb,
     unsigned long long *__restrict__ counters) {
+  using HT = typename std::conditional<kF64, double, float>::type;
+  HT *h = (HT *)hptr;
   __shared__ float4 tiles[kWpb][kTile];
+  __shared__ int tidx[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
   const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
@@ -85,39 +110,65 @@ __global__ __launch_bounds__(kBlock) void k_density(
   const int64_t t = g0 + lane;
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  const int s0 = uniform(targets ? targets[g0] : (int)g0);
   const float4 me = xm[s];
-  const float3 xi = make_float3(me.x, me.y, me.z);
+  const float3 xa = make_float3(me.x, me.y, me.z);  // FP32 position: box tests
   const int cid = perm[s];
   float4 *tile = tiles[w];
+  // this lane's position in the wave's frame
+  float3 xi = xa;
+  double4 p64 = make_double4(0, 0, 0, 0), c64 = make_double4(0, 0, 0, 0);
+  if constexpr (kF64) {
+    c64 = x64[s0];
+    p64 = x64[s];
+    xi = make_float3((float)(p64.x - c64.x), (float)(p64.y - c64.y), (float)(p64.z - c64.z));
+  }
 
-  float hcur = valid ? h[cid] : 1.0f;
+  HT hcur = valid ? h[cid] : HT(1);
   if (solve) {
-    const int s0 = uniform(targets ? targets[g0] : (int)g0);
-    if (__ballot(valid && !(hcur > 0.0f))) {
+    if (__ballot(valid && !(hcur > HT(0)))) {
       const float rho_g = group_density_guess(nodes, s0, n_ngb);
       const float guess = cbrtf(3.0f * n_ngb * me.w / (4.0f * 3.14159265f * rho_g));
-      if (!(hcur > 0.0f)) hcur = fminf(guess, hcap);
+      if (!(hcur > HT(0))) hcur = (HT)fminf(guess, hcap);
     }
   }
-  float lo = 0.0f, hi = INFINITY;
+  HT lo = HT(0), hi = HT(INFINITY);
   bool done = !valid;
   // results of the accepted evaluation
-  float res_h = hcur, res_sw = 0.0f, res_swh = 0.0f;
+  HT res_h = hcur;
+  float res_sw = 0.0f, res_swh = 0.0f;
   int res_n = 0;
   bool failed = false;
   int passes = 0;
 
   for (int iter = 0;; ++iter) {
     const bool live = !done;
-    const float h2 = live ? sq_exact(hcur) : -1.0f;
-    const float hinv = 1.0f / hcur;
+    const float hf = (float)hcur;
+    // squared radius of the FP32 test: fl32(h^2) (of the FP64 h when mixed)
+    const float h2 = !live ? -1.0f : (kF64 ? (float)((double)hcur * (double)hcur) : sq_exact(hf));
+    // walk pruning radius: exact for FP32 positions, padded by the rounding
+    // of FP32 absolute coordinates when the positions are FP64
+    const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(hf + slack) : h2);
+    const float band = kF64 ? band64(xi, h2, hf) : 0.0f;
+    const float hinv = 1.0f / hf;
     // sums of m w and m wh: plain per tile, compensated across tiles
     float sw = 0.0f, swh = 0.0f, csw = 0.0f, cswh = 0.0f;
     int cnt = 0;
     int tc = 0, cand = 0;
     auto flush = [&](int nc) {
       // unused slots sit at infinity and fail every neighbour test
-      tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+      if constexpr (kF64) {
+        float4 q = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        if (lane < nc) {
+          const double4 pj = x64[cand];
+          q = make_float4((float)(pj.x - c64.x), (float)(pj.y - c64.y), (float)(pj.z - c64.z),
+                          (float)pj.w);
+        }
+        tile[lane] = q;
+        tidx[w][lane] = cand;
+      } else {
+        tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+      }
       wave_sync();
       // every lane tests every entry (read by broadcast); the kernel sum runs
       // under the lanes that pass, and is skipped when none does. (Marking
@@ -128,7 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_density(
         const float4 q = tile[k];
         const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
                                      sub_exact(q.z, xi.z));
-        if (r2 < h2) {
+        bool in = r2 < h2;
+        if constexpr (kF64) {
+          if (fabsf(r2 - h2) <= band) in = within64(p64, x64[tidx[w][k]], (double)hcur);
+        }
+        if (in) {
           const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
           float wv, whv;
           wc6_w_wh(u, wv, whv);
@@ -144,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     int cur = 0;
     while (cur < nnodes) {
       const Node nd = nodes[cur];
-      const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < h2;
+      const bool want = box_dist2(xa, nd.lo_h, nd.hi_l) < hw2;
       if (__ballot(want) == 0ull) {
         cur = nd.meta.x;
         continue;
@@ -181,34 +236,35 @@ __global__ __launch_bounds__(kBlock) void k_density(
         // its log-slope is 3 + h rho'/rho = 3 + sum m wh / sum m w.
         const float N = kNeffSelf * sw / me.w;
         const bool below = N < n_ngb;
-        if (below) lo = fmaxf(lo, hcur);
-        else hi = fminf(hi, hcur);
+        if (below) lo = lo > hcur ? lo : hcur;
+        else hi = hi < hcur ? hi : hcur;
         const float slope = 3.0f + swh / sw;
-        // Newton step on ln N_eff(ln h); the log of the ratio (not a
-        // difference of logs) keeps the step accurate to a few 1e-8 near
-        // the root, well inside the convergence test below
-        float hn;
+        // Newton step on ln N_eff(ln h), in the precision of h; the log of
+        // the ratio (not a difference of logs) keeps the step accurate to a
+        // few 1e-8 near the root, well inside the convergence test below
+        HT hn;
         if (N == n_ngb) hn = hcur;
-        else if (slope > 0.05f) hn = hcur * expf(logf(n_ngb / N) / slope);
-        else hn = below ? 2.0f * hcur : 0.5f * hcur;
+        else if (slope > 0.05f)
+          hn = hcur * (HT)exp((HT)log((HT)n_ngb / (HT)N) / (HT)slope);
+        else hn = below ? HT(2) * hcur : HT(0.5) * hcur;
         // converged when the Newton correction itself is below half the
         // tolerance (h then lies within it of the root), or the bracket has
         // closed; tested before any safeguard replaces the step
-        const bool conv = fabsf(hn - hcur) <= 0.5f * tol * hcur ||
-                          (hi < INFINITY && hi - lo <= tol * hi);
-        hn = fminf(fmaxf(hn, 0.25f * hcur), 4.0f * hcur);
+        const bool conv = fabs(hn - hcur) <= HT(0.5) * (HT)tol * hcur ||
+                          (hi < HT(INFINITY) && hi - lo <= (HT)tol * hi);
+        hn = hn < HT(0.25) * hcur ? HT(0.25) * hcur : (hn > HT(4) * hcur ? HT(4) * hcur : hn);
         if (!(hn > lo && hn < hi)) {
-          if (hi < INFINITY && lo > 0.0f) hn = 0.5f * (lo + hi);
-          else if (hi < INFINITY) hn = 0.5f * hi;
-          else hn = 2.0f * lo;
+          if (hi < HT(INFINITY) && lo > HT(0)) hn = HT(0.5) * (lo + hi);
+          else if (hi < HT(INFINITY)) hn = HT(0.5) * hi;
+          else hn = HT(2) * lo;
         }
-        const bool capped = below && hcur >= hcap;
+        const bool capped = below && hcur >= (HT)hcap;
         if (conv || capped || iter + 1 >= max_iter) {
           done = true;
           failed = !conv;
           res_h = hcur; res_sw = sw; res_swh = swh; res_n = cnt;
         } else {
-          hcur = fminf(hn, hcap);
+          hcur = hn < (HT)hcap ? hn : (HT)hcap;
         }
       }
     }
@@ -224,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
   }
 
   if (valid) {
-    const float hinv = 1.0f / res_h;
+    const float hinv = 1.0f / (float)res_h;
     const float r = kC * res_sw * hinv * hinv * hinv;
     if (solve) h[cid] = res_h;
     if (rho) rho[cid] = r;
@@ -235,15 +291,18 @@ __global__ __launch_bounds__(kBlock) void k_density(
   }
 }
 
+template <typename HT>
 __global__ void k_hydro_prep(const int32_t *__restrict__ perm, int64_t m,
                              const float *__restrict__ vel, const float *__restrict__ u,
-                             const float *__restrict__ h, const float *__restrict__ rho,
+                             const HT *__restrict__ h, const float *__restrict__ rho,
                              const float *__restrict__ omega, float gamma,
-                             float4 *__restrict__ vh, float4 *__restrict__ aux) {
+                             float4 *__restrict__ vh, float4 *__restrict__ aux,
+                             double *__restrict__ h64) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= m) return;
   const int j = perm[s];
-  const float hj = h[j];
+  const float hj = (float)h[j];
+  if (h64) h64[s] = (double)h[j];
   vh[s] = make_float4(vel ? vel[3 * j] : 0.f, vel ? vel[3 * j + 1] : 0.f,
                       vel ? vel[3 * j + 2] : 0.f, hj);
   if (aux) {
@@ -260,14 +319,17 @@ struct HydroTile {
   float4 aux[kWpb][kTile];
 };
 
+template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_hydro(
     const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const double4 *__restrict__ x64, const double *__restrict__ h64,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
     const uint32_t *__restrict__ dcount, int64_t ntmax, float alpha, int walk_leaf,
-    float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
+    float slack, float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
     int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
+  __shared__ int tidx[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
   const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
@@ -276,7 +338,16 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
   const float4 me = xm[s], mv = vh[s], ma = aux[s];
-  const float3 xi = make_float3(me.x, me.y, me.z);
+  const float3 xa = make_float3(me.x, me.y, me.z);  // FP32 position: box tests
+  float3 xi = xa;  // this lane's position in the wave's frame
+  double4 p64 = make_double4(0, 0, 0, 0), c64 = make_double4(0, 0, 0, 0);
+  double hi64 = 0.0;
+  if constexpr (kF64) {
+    c64 = x64[uniform(targets ? targets[g0] : (int)g0)];
+    p64 = x64[s];
+    hi64 = h64[s];
+    xi = make_float3((float)(p64.x - c64.x), (float)(p64.y - c64.y), (float)(p64.z - c64.z));
+  }
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
   const float ki = kF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
@@ -287,12 +358,20 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
 
   auto flush = [&](int nc) {
     if (lane < nc) {
-      T.xm[w][lane] = xm[cand];
+      if constexpr (kF64) {
+        const double4 pj = x64[cand];
+        T.xm[w][lane] = make_float4((float)(pj.x - c64.x), (float)(pj.y - c64.y),
+                                    (float)(pj.z - c64.z), (float)pj.w);
+        tidx[w][lane] = cand;
+      } else {
+        T.xm[w][lane] = xm[cand];
+      }
       T.vh[w][lane] = vh[cand];
       T.aux[w][lane] = aux[cand];
     } else {  // unused slots sit at infinity and fail every neighbour test
       T.xm[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (kF64) tidx[w][lane] = 0;
     }
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
@@ -334,7 +413,16 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
                   dz = sub_exact(q.z, xi.z);
       const float r2 = dist2_exact(dx, dy, dz);
-      if (r2 < sq_exact(fmaxf(hi, qv.w))) {
+      const float H = fmaxf(hi, qv.w);
+      const float H2 = sq_exact(H);
+      bool in = r2 < H2;
+      if constexpr (kF64) {
+        if (valid && fabsf(r2 - H2) <= band64(xi, H2, H)) {
+          const int j = tidx[w][k];
+          in = within64(p64, x64[j], fmax(hi64, h64[j]));
+        }
+      }
+      if (in) {
         ++np;
         pair(k, q, qv, dx, dy, dz, r2);
       }
@@ -349,8 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   int cur = 0;
   while (cur < nnodes) {
     const Node nd = nodes[cur];
-    const float hm = fmaxf(hi, nd.lo_h.w);
-    const bool want = hi > 0.0f && box_dist2(xi, nd.lo_h, nd.hi_l) < sq_exact(hm);
+    const float hm = fmaxf(hi, nd.lo_h.w) + slack;
+    const bool want = hi > 0.0f && box_dist2(xa, nd.lo_h, nd.hi_l) < sq_exact(hm);
     if (__ballot(want) == 0ull) {
       cur = nd.meta.x;
       continue;
@@ -398,23 +486,39 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 }  // namespace
 
 hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const SphParams &sp, int solve_h, float *h,
+                          int64_t max_targets, const SphParams &sp, int solve_h, void *h,
                           float *rho, float *drho_dh, float *omega, int32_t *nngb,
                           unsigned long long *counters, hipStream_t s, float hcap) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  k_density<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
-      gas.nodes, (int)gas.nnodes, gas.xm, gas.perm, targets, dcount, max_targets, sp.n_ngb,
-      sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, h, rho, drho_dh, omega, nngb,
-      counters);
+  auto kern = sp.f64 ? k_density<true> : k_density<false>;
+  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+      gas.nodes, (int)gas.nnodes, gas.xm, gas.x64, gas.perm, targets, dcount, max_targets,
+      sp.n_ngb, sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, sp.slack, h, rho, drho_dh,
+      omega, nngb, counters);
   return hipGetLastError();
 }
 
-hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const float *h,
-                             const float *rho, const float *omega, float gamma,
+hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const void *h,
+                             const float *rho, const float *omega, float gamma, int f64,
                              hipStream_t s) {
   if (gas.n == 0) return hipSuccess;
-  k_hydro_prep<<<nblk(gas.n, 256), 256, 0, s>>>(gas.perm, gas.n, vel, u, h, rho, omega,
-                                                 gamma, gas.vh, rho ? gas.aux : nullptr);
+  if (f64) {
+    if (!gas.h64 || gas.cap_h64 < gas.n) {
+      if (gas.h64) (void)hipFree(gas.h64);
+      gas.h64 = nullptr;
+      gas.cap_h64 = 0;
+      if (hipMalloc((void **)&gas.h64, gas.n * sizeof(double)) != hipSuccess)
+        return hipErrorOutOfMemory;
+      gas.cap_h64 = gas.n;
+    }
+    k_hydro_prep<double><<<nblk(gas.n, 256), 256, 0, s>>>(
+        gas.perm, gas.n, vel, u, (const double *)h, rho, omega, gamma, gas.vh,
+        rho ? gas.aux : nullptr, gas.h64);
+  } else {
+    k_hydro_prep<float><<<nblk(gas.n, 256), 256, 0, s>>>(
+        gas.perm, gas.n, vel, u, (const float *)h, rho, omega, gamma, gas.vh,
+        rho ? gas.aux : nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -422,9 +526,10 @@ hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_
                         int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
                         float *vsig, int32_t *npairs, hipStream_t s) {
   if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
-  k_hydro<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
-      gas.nodes, (int)gas.nnodes, gas.xm, gas.vh, gas.aux, gas.perm, targets, dcount,
-      max_targets, sp.alpha, sp.walk_leaf, acc, dudt, vsig, npairs);
+  auto kern = sp.f64 ? k_hydro<true> : k_hydro<false>;
+  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
+      gas.nodes, (int)gas.nnodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, gas.perm, targets,
+      dcount, max_targets, sp.alpha, sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
   return hipGetLastError();
 }
 

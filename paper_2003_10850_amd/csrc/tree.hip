@@ -34,21 +34,25 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
-__device__ __forceinline__ uint32_t cell_of(float x, double lo, double scale) {
+// key cell in FP64 for FP32 and FP64 positions alike
+template <typename T>
+__device__ __forceinline__ uint32_t cell_of(T x, double lo, double scale) {
   double f = floor(((double)x - lo) * scale);
   if (!(f >= 0.0)) f = 0.0;
   if (f > (double)((1u << kMaxLevel) - 1u)) f = (double)((1u << kMaxLevel) - 1u);
   return (uint32_t)f;
 }
 
-__device__ __forceinline__ uint64_t morton_key(const float *p, double lx, double ly,
-                                               double lz, double scale) {
+template <typename T>
+__device__ __forceinline__ uint64_t morton_key(const T *p, double lx, double ly, double lz,
+                                               double scale) {
   return (spread3(cell_of(p[0], lx, scale)) << 2) | (spread3(cell_of(p[1], ly, scale)) << 1) |
          spread3(cell_of(p[2], lz, scale));
 }
 
 // keys and identity values for the members selected by sel (nullptr: all)
-__global__ void k_keys(const float *__restrict__ pos, const int32_t *__restrict__ sel,
+template <typename T>
+__global__ void k_keys(const T *__restrict__ pos, const int32_t *__restrict__ sel,
                        int64_t m, double lx, double ly, double lz, double scale,
                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,13 +75,20 @@ __global__ void k_gas_compact(const uint32_t *__restrict__ flags,
   if (i < n && flags[i]) ids[slot[i]] = (int32_t)i;
 }
 
+// Sorted copies: FP32 (x, y, z, m) always; for FP64 positions also the
+// exact (x, y, z, m) in FP64.
+template <typename T>
 __global__ void k_permute(const uint32_t *__restrict__ perm, int64_t m,
-                          const float *__restrict__ pos, const float *__restrict__ mass,
-                          float4 *__restrict__ xm, int32_t *__restrict__ iperm) {
+                          const T *__restrict__ pos, const float *__restrict__ mass,
+                          float4 *__restrict__ xm, double4 *__restrict__ x64,
+                          int32_t *__restrict__ iperm) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= m) return;
   const uint32_t j = perm[s];
-  xm[s] = make_float4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j]);
+  xm[s] = make_float4((float)pos[3 * j], (float)pos[3 * j + 1], (float)pos[3 * j + 2], mass[j]);
+  if (x64)
+    x64[s] = make_double4((double)pos[3 * j], (double)pos[3 * j + 1], (double)pos[3 * j + 2],
+                          (double)mass[j]);
   iperm[j] = (int32_t)s;
 }
 
@@ -169,7 +180,9 @@ __global__ void k_nodes(const uint64_t *__restrict__ keys, int64_t m,
 
 // Bottom-up pass for one level: FP64 mass and first moments, tight box.
 __global__ void k_moments_level(Node *__restrict__ nodes, double4 *__restrict__ mom,
-                                int64_t nnodes, const float4 *__restrict__ xm, int level) {
+                                double4 *__restrict__ c64, int64_t nnodes,
+                                const float4 *__restrict__ xm,
+                                const double4 *__restrict__ x64, int level) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nnodes) return;
   const int4 meta = nodes[k].meta;
@@ -180,11 +193,12 @@ __global__ void k_moments_level(Node *__restrict__ nodes, double4 *__restrict__ 
   if (meta.w & kLeafBit) {
     for (int s = meta.y; s < meta.y + meta.z; ++s) {
       const float4 p = xm[s];
-      const double mm = (double)p.w;
-      M += mm;
-      Sx += mm * (double)p.x;
-      Sy += mm * (double)p.y;
-      Sz += mm * (double)p.z;
+      // moments from the exact positions (FP64 ones when the tree has them)
+      const double4 q = x64 ? x64[s] : make_double4(p.x, p.y, p.z, p.w);
+      M += q.w;
+      Sx += q.w * q.x;
+      Sy += q.w * q.y;
+      Sz += q.w * q.z;
       lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
       hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
     }
@@ -208,6 +222,9 @@ __global__ void k_moments_level(Node *__restrict__ nodes, double4 *__restrict__ 
     nd.com_m = make_float4((float)(Sx / M), (float)(Sy / M), (float)(Sz / M), (float)M);
   else  // massless node: its geometric centre
     nd.com_m = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z), 0.f);
+  if (c64)
+    c64[k] = M > 0.0 ? make_double4(Sx / M, Sy / M, Sz / M, M)
+                     : make_double4(nd.com_m.x, nd.com_m.y, nd.com_m.z, 0.0);
   lo.w = nd.lo_h.w;
   hi.w = nd.hi_l.w;
   nd.lo_h = lo;
@@ -255,12 +272,23 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 // Selects the members (gas only for the gas octree), sorts them and builds
 // the topology and moments. SYNCS once to read the node count.
-int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float *mass,
-                 int64_t m, hipStream_t s) {
+int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
+                 const float *mass, int64_t m, hipStream_t s) {
   o.n = m;
   o.nnodes = 0;
   o.max_level = 0;
   if (m == 0) return G3_OK;
+  if (f64 && (!o.x64 || o.cap_x64 < m)) {
+    if (o.x64) (void)hipFree(o.x64);
+    o.x64 = nullptr;
+    o.cap_x64 = 0;
+    if (hipMalloc((void **)&o.x64, m * sizeof(double4)) != hipSuccess) {
+      c->err = "device allocation of the FP64 positions failed";
+      return G3_ENOMEM;
+    }
+    o.cap_x64 = m;
+  }
+  double4 *x64 = f64 ? o.x64 : nullptr;
   if (m > o.cap_n) {
     for (void *p : {(void *)o.keys, (void *)o.perm, (void *)o.xm, (void *)o.vh, (void *)o.aux})
       if (p) (void)hipFree(p);
@@ -292,12 +320,21 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float
   const bool gas = (&o == &t->gas);
   const int32_t *sel = nullptr;
   if (gas && m != t->n) sel = (const int32_t *)scratch(c, kFlags, 0);  // filled by caller
-  k_keys<<<nblk(m), kBlock, 0, s>>>(pos, sel, m, t->box[0], t->box[1], t->box[2], t->scale,
-                                    o.keys, vals);
+  if (f64)
+    k_keys<double><<<nblk(m), kBlock, 0, s>>>((const double *)pos, sel, m, t->box[0], t->box[1],
+                                              t->box[2], t->scale, o.keys, vals);
+  else
+    k_keys<float><<<nblk(m), kBlock, 0, s>>>((const float *)pos, sel, m, t->box[0], t->box[1],
+                                             t->box[2], t->scale, o.keys, vals);
   hipError_t e = radix_sort_pairs(o.keys, vals, kalt, valt, m, rtmp, s);
   if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
   int32_t *iperm = gas ? t->iperm_gas : t->iperm_all;
-  k_permute<<<nblk(m), kBlock, 0, s>>>(vals, m, pos, mass, o.xm, iperm);
+  if (f64)
+    k_permute<double><<<nblk(m), kBlock, 0, s>>>(vals, m, (const double *)pos, mass, o.xm, x64,
+                                                 iperm);
+  else
+    k_permute<float><<<nblk(m), kBlock, 0, s>>>(vals, m, (const float *)pos, mass, o.xm, nullptr,
+                                                iperm);
   e = hipMemcpyAsync(o.perm, vals, m * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) { c->err = "perm copy failed"; return G3_EHIP; }
   e = fill_i32(maxlev, 0, 1, s);
@@ -325,11 +362,23 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const float *pos, const float
     }
     o.cap_nodes = cap;
   }
+  if (f64 && (!o.c64 || o.cap_c64 < nnodes)) {
+    if (o.c64) (void)hipFree(o.c64);
+    o.c64 = nullptr;
+    o.cap_c64 = 0;
+    const int64_t cap = nnodes + nnodes / 8 + 64;
+    if (hipMalloc((void **)&o.c64, cap * sizeof(double4)) != hipSuccess) {
+      c->err = "device allocation of the FP64 node centres failed";
+      return G3_ENOMEM;
+    }
+    o.cap_c64 = cap;
+  }
   o.nnodes = nnodes;
   o.max_level = maxl;
   k_nodes<<<nblk(m), kBlock, 0, s>>>(o.keys, m, off, lev, nnodes, (float)t->box[3], o.nodes);
   for (int l = maxl; l >= 0; --l)
-    k_moments_level<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, o.mom, nnodes, o.xm, l);
+    k_moments_level<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, o.mom, f64 ? o.c64 : nullptr,
+                                                     nnodes, o.xm, x64, l);
   e = hipGetLastError();
   if (e != hipSuccess) { c->err = std::string("tree build launch: ") + hipGetErrorString(e); return G3_EHIP; }
   return G3_OK;

@@ -133,10 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_walk_grav(
 }  // namespace
 
 hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
-                       const uint32_t *dcount, int64_t max_targets, const float *h_caller,
+                       const uint32_t *dcount, int64_t max_targets,
                        const GravParams &gp, int32_t *counts, const int64_t *offsets,
                        int32_t *list, hipStream_t s) {
-  (void)h_caller;
   if (max_targets <= 0 || o.nnodes == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
   if (kind == G3_GRAVITY)

@@ -68,16 +68,21 @@ class Tree:
         self.build(pos, mass, type, box)
 
     def build(self, pos, mass, type=None, box=None):
+        """pos float32 (plain path) or float64 (mixed-precision path)."""
         dev = self.ctx.device
         n = int(pos.shape[0])
-        _need(pos, torch.float32, (n, 3), "pos", dev)
+        if pos.dtype not in (torch.float32, torch.float64):
+            raise TypeError("pos must be float32 or float64")
+        _need(pos, pos.dtype, (n, 3), "pos", dev)
         _need(mass, torch.float32, (n,), "mass", dev)
         if type is not None:
             _need(type, torch.uint8, (n,), "type", dev)
         if box is not None:
             self.box = tuple(float(b) for b in box)
         self.n = n
-        self.handle = g3.g3_build_tree(self.ctx.handle, n, g3.G3_F32, _ptr(pos), _ptr(mass),
+        self.hdtype = pos.dtype  # the SPH calls' h follows the positions
+        pt = g3.G3_F64 if pos.dtype == torch.float64 else g3.G3_F32
+        self.handle = g3.g3_build_tree(self.ctx.handle, n, pt, _ptr(pos), _ptr(mass),
                                        _ptr(type), self.box, g3.g3_params.of(self.params),
                                        self.handle, _stream(dev))
         return self
@@ -121,8 +126,8 @@ def density(tree: Tree, params=None, h=None, active=None, solve_h: bool = True, 
     p = g3.g3_params.of(params or tree.params)
     n = tree.n
     o = out or {}
-    hh = h.clone() if h is not None else _zeros(tree, n)
-    _need(hh, torch.float32, (n,), "h", tree.ctx.device)
+    hh = h.clone() if h is not None else _zeros(tree, n, dtype=tree.hdtype)
+    _need(hh, tree.hdtype, (n,), "h", tree.ctx.device)
     res = dict(h=hh, rho=o.get("rho", _zeros(tree, n)), drho_dh=o.get("drho_dh", _zeros(tree, n)),
                omega=o.get("omega", _zeros(tree, n)),
                nngb=o.get("nngb", _zeros(tree, n, dtype=torch.int32)))
@@ -138,7 +143,8 @@ def hydro_force(tree: Tree, vel, u, h, rho, omega, params=None, active=None, out
     n = tree.n
     dev = tree.ctx.device
     _need(vel, torch.float32, (n, 3), "vel", dev)
-    for name, t in (("u", u), ("h", h), ("rho", rho), ("omega", omega)):
+    _need(h, tree.hdtype, (n,), "h", dev)
+    for name, t in (("u", u), ("rho", rho), ("omega", omega)):
         _need(t, torch.float32, (n,), name, dev)
     o = out or {}
     res = dict(acc=o.get("acc", _zeros(tree, n, 3)), dudt=o.get("dudt", _zeros(tree, n)),
@@ -170,7 +176,7 @@ def walk(tree: Tree, kind: int, params=None, h=None, active=None, capacity=None)
     dev = tree.ctx.device
     offsets = torch.zeros(na + 1, dtype=torch.int64, device=dev)
     if h is not None:
-        _need(h, torch.float32, (tree.n,), "h", dev)
+        _need(h, tree.hdtype, (tree.n,), "h", dev)
     cap = 0 if capacity is None else int(capacity)
     lst = torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)
     st, total = g3.g3_walk(tree.ctx.handle, tree.handle, kind, na, ap, _ptr(h), p, cap,

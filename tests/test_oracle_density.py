@@ -146,3 +146,24 @@ def test_invalid_target_number():
     t = oracle.Tree(w.pos, w.mass, w.box, gas_only=True)
     with pytest.raises(ValueError):
         oracle.density(t, inputs.Params(n_ngb=20.0))
+
+
+def test_fp64_decision_lists_match_brute_force():
+    """With FP64 decisions the neighbour test is ((dx dx + dy dy) + dz dz) < H H
+    in FP64 on the FP64 positions: numpy's elementwise FP64 arithmetic
+    evaluates the same expression."""
+    import dataclasses
+    w = inputs.plummer(n=3000, n_spheres=3, seed=31, n_ngb=64.0)
+    pos = w.pos + 1000.0
+    box = np.array(w.box, float)
+    box[:3] += 1000.0
+    t = oracle.Tree(pos, w.mass, box, type=w.type, gas_only=True)
+    p = dataclasses.replace(w.params, flags=oracle.FLAG_FP64_DECISIONS)
+    h = inputs.model_smoothing(w, 64.0)
+    gas = np.nonzero(w.type == 0)[0]
+    off, lst = oracle.lists(t, p, oracle.GATHER, active=gas[::17], h=h)
+    for a, i in enumerate(gas[::17]):
+        d = pos[gas] - pos[i]
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        ref = set(gas[r2 < h[i] * h[i]].tolist())
+        assert set(lst[off[a]:off[a + 1]].tolist()) == ref
