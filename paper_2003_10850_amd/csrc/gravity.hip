@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     float theta2, float eps2, float G, int inside_test, double theta64, double side,
     float *__restrict__ acc, float *__restrict__ pot, int32_t *__restrict__ nterms) {
   __shared__ Entry tiles[kWpb][kTile];
+  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];  // FP64 source positions
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
   const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
@@ -66,17 +67,13 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
   const float4 me = xm[s];
-  float3 xi = make_float3(me.x, me.y, me.z);
-  double4 p64 = make_double4(0, 0, 0, 0), cg = make_double4(0, 0, 0, 0);
-  float ai = 0.0f;  // |offset| of this lane (mixed precision band)
-  if constexpr (kF64) {
-    cg = x64[uniform(targets ? targets[g0] : (int)g0)];
-    p64 = x64[s];
-    xi = make_float3((float)(p64.x - cg.x), (float)(p64.y - cg.y), (float)(p64.z - cg.z));
-    ai = sqrtf(xi.x * xi.x + xi.y * xi.y + xi.z * xi.z);
-  }
+  const float3 xi = make_float3(me.x, me.y, me.z);
+  // mixed precision: every offset is the FP64 difference from this target,
+  // rounded to FP32 (exact to 2^-24 of itself)
+  const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
   const uint64_t ki = keys[s];
   Entry *tile = tiles[w];
+  double4 *tile64 = tiles64[w];
 
   // totals with Neumaier compensation terms; per-tile partials are plain
   float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
@@ -95,7 +92,17 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       // branch-free use test: the lane's mask bit, and not the target itself
       const uint32_t word = (uint32_t)(hiword ? e.meta.z : e.meta.y);
       const bool use = (__builtin_amdgcn_ubfe(word, bitpos, 1u) != 0u) & (e.meta.x != s);
-      const float dx = e.p.x - xi.x, dy = e.p.y - xi.y, dz = e.p.z - xi.z;
+      float dx, dy, dz;
+      if constexpr (kF64) {
+        const double4 q = tile64[k];
+        dx = (float)(q.x - p64.x);
+        dy = (float)(q.y - p64.y);
+        dz = (float)(q.z - p64.z);
+      } else {
+        dx = e.p.x - xi.x;
+        dy = e.p.y - xi.y;
+        dz = e.p.z - xi.z;
+      }
       const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
       const float rinv = __builtin_amdgcn_rsqf(r2);
       const float mr = (use ? e.p.w : 0.0f) * rinv;
@@ -118,24 +125,21 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   while (cur < nnodes) {
     const Node nd = nodes[cur];
     const bool act = cur >= resume;
-    float4 com = nd.com_m;  // centre of mass in the wave's frame, and mass
     double4 cn = make_double4(0, 0, 0, 0);
+    float r2;
     if constexpr (kF64) {
       cn = c64n[cur];
-      com = make_float4((float)(cn.x - cg.x), (float)(cn.y - cg.y), (float)(cn.z - cg.z),
-                        com.w);
+      r2 = dist2_exact((float)(cn.x - p64.x), (float)(cn.y - p64.y), (float)(cn.z - p64.z));
+    } else {
+      r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
+                       sub_exact(nd.com_m.z, xi.z));
     }
-    const float r2 = dist2_exact(sub_exact(com.x, xi.x), sub_exact(com.y, xi.y),
-                                 sub_exact(com.z, xi.z));
     bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
     if constexpr (kF64) {
-      // |FP32 r2 - FP64 r2| <= 2^-21.5 r (|o_i| + |o_c| + r) + 2^-23 r2 for
-      // offsets o; the FP64 test decides inside 4x that band
+      // the FP32 r2 of exact-to-2^-24 offsets is within about 2^-22 of the
+      // FP64 value (relative); inside 2^-19 of the threshold FP64 decides
       const float lhs = nd.hi_l.w * nd.hi_l.w, rhs = theta2 * r2;
-      const float r = sqrtf(r2);
-      const float ac = sqrtf(com.x * com.x + com.y * com.y + com.z * com.z);
-      const float band = rhs * 1.9073486e-6f * ((ai + ac) / fmaxf(r, 1e-30f) + 4.0f);
-      if (act && fabsf(lhs - rhs) <= band)
+      if (act && fabsf(lhs - rhs) <= rhs * 1.9073486e-6f)
         accept = open_accept64(ldexp(side, -(nd.meta.w & 255)), theta64, cn, p64);
     }
     if (inside_test) {
@@ -154,9 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       }
       if (lane == 0) {
         Entry e;
-        e.p = com;
+        e.p = nd.com_m;
         e.meta = make_int4(-1, (int)(uint32_t)amask, (int)(uint32_t)(amask >> 32), 0);
         tile[tc] = e;
+        if constexpr (kF64) tile64[tc] = cn;
       }
       ++tc;
     }
@@ -177,13 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       const int take = min(c, kTile - tc);
       if (lane < take) {
         Entry e;
-        if constexpr (kF64) {
-          const double4 pj = x64[st + lane];
-          e.p = make_float4((float)(pj.x - cg.x), (float)(pj.y - cg.y), (float)(pj.z - cg.z),
-                            (float)pj.w);
-        } else {
-          e.p = xm[st + lane];
-        }
+        e.p = xm[st + lane];  // FP32 mass (and FP32 position on the plain path)
+        if constexpr (kF64) tile64[tc + lane] = x64[st + lane];
         e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
         tile[tc + lane] = e;
       }

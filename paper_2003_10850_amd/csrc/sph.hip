@@ -79,16 +79,12 @@ __device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
   return (dx * dx + dy * dy) + dz * dz < H * H;
 }
 
-// Mixed precision: a wave works on FP32 offsets o = fl32(x - c) from a group
-// centre c (its first target), so their rounding scales with the group's
-// extent. The FP32 test r2 < fl32(H^2) on offsets differs from the exact
-// FP64 test by at most about 2^-21.5 (|o_i|/H + 3.4) H^2 for candidates
-// within reach; inside the band 2^-19 (|o_i|/H + 4) H^2 around the
-// threshold the FP64 test decides. This keeps every decision exact.
-__device__ __forceinline__ float band64(float3 o, float H2, float H) {
-  const float a = sqrtf(o.x * o.x + o.y * o.y + o.z * o.z);
-  return H2 * 1.9073486e-6f * (a / H + 4.0f);  // 2^-19
-}
+// Mixed precision: each pair works on the FP32 rounding of the FP64
+// difference x_j - x_i, so every offset is exact to 2^-24 of itself and
+// r2 = fmaf(dz,dz, fmaf(dy,dy, dx dx)) is within about 2^-22 of the FP64
+// value, relative. Inside the band 2^-19 H^2 around the threshold the FP64
+// test decides, which keeps every decision exact.
+constexpr float kBand64 = 1.9073486e-6f;  // 2^-19
 
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_density(
@@ -101,8 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
     unsigned long long *__restrict__ counters) {
   using HT = typename std::conditional<kF64, double, float>::type;
   HT *h = (HT *)hptr;
-  __shared__ float4 tiles[kWpb][kTile];
-  __shared__ int tidx[kWpb][kF64 ? kTile : 1];
+  __shared__ float4 tiles[kWpb][kF64 ? 1 : kTile];
+  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
   const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
@@ -112,17 +108,11 @@ __global__ __launch_bounds__(kBlock) void k_density(
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
   const int s0 = uniform(targets ? targets[g0] : (int)g0);
   const float4 me = xm[s];
-  const float3 xa = make_float3(me.x, me.y, me.z);  // FP32 position: box tests
+  const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
   const int cid = perm[s];
   float4 *tile = tiles[w];
-  // this lane's position in the wave's frame
-  float3 xi = xa;
-  double4 p64 = make_double4(0, 0, 0, 0), c64 = make_double4(0, 0, 0, 0);
-  if constexpr (kF64) {
-    c64 = x64[s0];
-    p64 = x64[s];
-    xi = make_float3((float)(p64.x - c64.x), (float)(p64.y - c64.y), (float)(p64.z - c64.z));
-  }
+  double4 *tile64 = tiles64[w];
+  const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
 
   HT hcur = valid ? h[cid] : HT(1);
   if (solve) {
@@ -149,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     // walk pruning radius: exact for FP32 positions, padded by the rounding
     // of FP32 absolute coordinates when the positions are FP64
     const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(hf + slack) : h2);
-    const float band = kF64 ? band64(xi, h2, hf) : 0.0f;
+    const float band = kF64 ? h2 * kBand64 : 0.0f;
     const float hinv = 1.0f / hf;
     // sums of m w and m wh: plain per tile, compensated across tiles
     float sw = 0.0f, swh = 0.0f, csw = 0.0f, cswh = 0.0f;
@@ -157,18 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_density(
     int tc = 0, cand = 0;
     auto flush = [&](int nc) {
       // unused slots sit at infinity and fail every neighbour test
-      if constexpr (kF64) {
-        float4 q = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-        if (lane < nc) {
-          const double4 pj = x64[cand];
-          q = make_float4((float)(pj.x - c64.x), (float)(pj.y - c64.y), (float)(pj.z - c64.z),
-                          (float)pj.w);
-        }
-        tile[lane] = q;
-        tidx[w][lane] = cand;
-      } else {
+      if constexpr (kF64)
+        tile64[lane] = (lane < nc) ? x64[cand] : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+      else
         tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-      }
       wave_sync();
       // every lane tests every entry (read by broadcast); the kernel sum runs
       // under the lanes that pass, and is skipped when none does. (Marking
@@ -176,19 +158,27 @@ __global__ __launch_bounds__(kBlock) void k_density(
       // slower: it costs occupancy and per-lane LDS addressing.)
       float pw = 0.0f, pwh = 0.0f;
       for (int k = 0; k < nc; ++k) {
-        const float4 q = tile[k];
-        const float r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y),
-                                     sub_exact(q.z, xi.z));
-        bool in = r2 < h2;
+        float r2, mj;
+        bool in;
         if constexpr (kF64) {
-          if (fabsf(r2 - h2) <= band) in = within64(p64, x64[tidx[w][k]], (double)hcur);
+          // offset from this target: the FP64 difference rounded to FP32
+          const double4 q = tile64[k];
+          r2 = dist2_exact((float)(q.x - p64.x), (float)(q.y - p64.y), (float)(q.z - p64.z));
+          mj = (float)q.w;
+          in = r2 < h2;
+          if (fabsf(r2 - h2) <= band) in = within64(p64, q, (double)hcur);
+        } else {
+          const float4 q = tile[k];
+          r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y), sub_exact(q.z, xi.z));
+          mj = q.w;
+          in = r2 < h2;
         }
         if (in) {
           const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
           float wv, whv;
           wc6_w_wh(u, wv, whv);
-          pw += q.w * wv;
-          pwh += q.w * whv;
+          pw += mj * wv;
+          pwh += mj * whv;
           ++cnt;
         }
       }
@@ -199,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     int cur = 0;
     while (cur < nnodes) {
       const Node nd = nodes[cur];
-      const bool want = box_dist2(xa, nd.lo_h, nd.hi_l) < hw2;
+      const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < hw2;
       if (__ballot(want) == 0ull) {
         cur = nd.meta.x;
         continue;
@@ -329,7 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     float slack, float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
     int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
-  __shared__ int tidx[kWpb][kF64 ? kTile : 1];
+  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
+  __shared__ double th64[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
   const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
@@ -338,16 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const bool valid = t < ntarg;
   const int s = valid ? (targets ? targets[t] : (int)t) : 0;
   const float4 me = xm[s], mv = vh[s], ma = aux[s];
-  const float3 xa = make_float3(me.x, me.y, me.z);  // FP32 position: box tests
-  float3 xi = xa;  // this lane's position in the wave's frame
-  double4 p64 = make_double4(0, 0, 0, 0), c64 = make_double4(0, 0, 0, 0);
-  double hi64 = 0.0;
-  if constexpr (kF64) {
-    c64 = x64[uniform(targets ? targets[g0] : (int)g0)];
-    p64 = x64[s];
-    hi64 = h64[s];
-    xi = make_float3((float)(p64.x - c64.x), (float)(p64.y - c64.y), (float)(p64.z - c64.z));
-  }
+  const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
+  const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
+  const double hi64 = kF64 ? h64[s] : 0.0;
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
   const float ki = kF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
@@ -358,20 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
 
   auto flush = [&](int nc) {
     if (lane < nc) {
+      T.xm[w][lane] = xm[cand];
       if constexpr (kF64) {
-        const double4 pj = x64[cand];
-        T.xm[w][lane] = make_float4((float)(pj.x - c64.x), (float)(pj.y - c64.y),
-                                    (float)(pj.z - c64.z), (float)pj.w);
-        tidx[w][lane] = cand;
-      } else {
-        T.xm[w][lane] = xm[cand];
+        tiles64[w][lane] = x64[cand];
+        th64[w][lane] = h64[cand];
       }
       T.vh[w][lane] = vh[cand];
       T.aux[w][lane] = aux[cand];
     } else {  // unused slots sit at infinity and fail every neighbour test
       T.xm[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (kF64) tidx[w][lane] = 0;
+      if constexpr (kF64) {
+        tiles64[w][lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        th64[w][lane] = 0.0;
+      }
     }
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
@@ -410,17 +394,25 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     for (int k = 0; k < nc; ++k) {
       const float4 q = T.xm[w][k];
       const float4 qv = T.vh[w][k];
-      const float dx = sub_exact(q.x, xi.x), dy = sub_exact(q.y, xi.y),
-                  dz = sub_exact(q.z, xi.z);
+      float dx, dy, dz;
+      if constexpr (kF64) {
+        // offset from this target: the FP64 difference rounded to FP32
+        const double4 q64 = tiles64[w][k];
+        dx = (float)(q64.x - p64.x);
+        dy = (float)(q64.y - p64.y);
+        dz = (float)(q64.z - p64.z);
+      } else {
+        dx = sub_exact(q.x, xi.x);
+        dy = sub_exact(q.y, xi.y);
+        dz = sub_exact(q.z, xi.z);
+      }
       const float r2 = dist2_exact(dx, dy, dz);
       const float H = fmaxf(hi, qv.w);
       const float H2 = sq_exact(H);
       bool in = r2 < H2;
       if constexpr (kF64) {
-        if (valid && fabsf(r2 - H2) <= band64(xi, H2, H)) {
-          const int j = tidx[w][k];
-          in = within64(p64, x64[j], fmax(hi64, h64[j]));
-        }
+        if (valid && fabsf(r2 - H2) <= H2 * kBand64)
+          in = within64(p64, tiles64[w][k], fmax(hi64, th64[w][k]));
       }
       if (in) {
         ++np;
@@ -438,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   while (cur < nnodes) {
     const Node nd = nodes[cur];
     const float hm = fmaxf(hi, nd.lo_h.w) + slack;
-    const bool want = hi > 0.0f && box_dist2(xa, nd.lo_h, nd.hi_l) < sq_exact(hm);
+    const bool want = hi > 0.0f && box_dist2(xi, nd.lo_h, nd.hi_l) < sq_exact(hm);
     if (__ballot(want) == 0ull) {
       cur = nd.meta.x;
       continue;
