@@ -172,6 +172,144 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     return out
 
 
+def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -> dict:
+    """The batching workload: a forest of n_snap Plummer snapshots (sizes
+    log-uniform in [1e3, 1e6]) with time-bin active sets. One step = the
+    interaction phase of the active particles of every snapshot (h solve and
+    density, hydro force, gravity) as one persistent launch per kernel,
+    captured once in a HIP graph and replayed. For comparison the same step
+    runs eagerly, and as separate per-snapshot trees and calls (the
+    unbatched way)."""
+    import torch
+    from paper_2003_10850_amd import inputs, ops
+
+    t0 = time.perf_counter()
+    b = inputs.batch(n_snap=n_snap, seed=seed)
+    print(f"bench: batched workload {b.name}: n={b.n} active={b.active.size} "
+          f"({time.perf_counter() - t0:.1f} s to draw)", file=sys.stderr, flush=True)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, mass, typ = T(b.pos.astype(np.float32)), T(b.mass.astype(np.float32)), T(b.type)
+    vel, u = T(b.vel.astype(np.float32)), T(b.u.astype(np.float32))
+    act = T(b.active)
+    ctx = ops.Context(dev)
+    boxes = [tuple(x) for x in b.boxes]
+    tree = ops.Tree(ctx, pos, mass, typ, boxes, b.params, snap_off=b.snap_off)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(3):
+        tree.build(pos, mass, typ, boxes, b.snap_off)
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - tb) / 3
+    n = b.n
+    # every particle's h, rho and omega: the state a simulation carries
+    base = ops.density(tree)
+    h0, rho0, om0 = base["h"].clone(), base["rho"].clone(), base["omega"].clone()
+    f32 = dict(dtype=torch.float32, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    B = dict(h=torch.zeros(n, **f32), rho=torch.zeros(n, **f32), drho_dh=torch.zeros(n, **f32),
+             omega=torch.zeros(n, **f32), nngb=torch.zeros(n, **i32),
+             acc=torch.zeros(n, 3, **f32), dudt=torch.zeros(n, **f32), vsig=torch.zeros(n, **f32),
+             npairs=torch.zeros(n, **i32), gacc=torch.zeros(n, 3, **f32),
+             pot=torch.zeros(n, **f32), nterms=torch.zeros(n, **i32))
+    rho_in, om_in = rho0.clone(), om0.clone()
+
+    def step():
+        B["h"].copy_(h0)  # last step's h is the first guess of the solve
+        ops.density(tree, active=act, out={k: B[k] for k in
+                                           ("h", "rho", "drho_dh", "omega", "nngb")})
+        ops.hydro_force(tree, vel, u, B["h"], rho_in, om_in, active=act,
+                        out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
+        ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
+                                           "nterms": B["nterms"]})
+
+    s = torch.cuda.Stream(dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        for _ in range(max(warmup, 1)):
+            step()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        eager_ms = 1e3 * (time.perf_counter() - te) / steps
+    torch.cuda.current_stream(dev).wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(max(warmup, 1)):
+        g.replay()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - tg) / steps
+    actn = b.active.astype(np.int64)
+    gas_act = actn[b.type[actn] == 0]
+    i_d = int(B["nngb"][T(gas_act)].sum())
+    i_h = int(B["npairs"][T(gas_act)].sum())
+    i_g = int(B["nterms"][act.long()].sum())
+    inter = i_d + i_h + i_g
+    nonconv = ctx.nonconverged(reset=True)
+    print(f"bench: batched graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms/step, "
+          f"build {build_ms:.2f} ms; interactions {inter}", file=sys.stderr, flush=True)
+
+    # unbatched: one tree and three calls per snapshot
+    trees = []
+    for k in range(b.n_snap):
+        r0, r1 = int(b.snap_off[k]), int(b.snap_off[k + 1])
+        a = b.active[(b.active >= r0) & (b.active < r1)] - r0
+        nk = r1 - r0
+        o = dict(h=torch.zeros(nk, **f32), rho=torch.zeros(nk, **f32),
+                 drho_dh=torch.zeros(nk, **f32), omega=torch.zeros(nk, **f32),
+                 nngb=torch.zeros(nk, **i32), acc=torch.zeros(nk, 3, **f32),
+                 dudt=torch.zeros(nk, **f32), vsig=torch.zeros(nk, **f32),
+                 npairs=torch.zeros(nk, **i32), gacc=torch.zeros(nk, 3, **f32),
+                 pot=torch.zeros(nk, **f32), nterms=torch.zeros(nk, **i32))
+        trees.append((ops.Tree(ctx, pos[r0:r1], mass[r0:r1], typ[r0:r1], boxes[k], b.params),
+                      r0, r1, T(a.astype(np.int32)), o))
+
+    def step_unbatched():
+        for t, r0, r1, a, o in trees:
+            o["h"].copy_(h0[r0:r1])
+            ops.density(t, active=a, out={k: o[k] for k in
+                                          ("h", "rho", "drho_dh", "omega", "nngb")})
+            ops.hydro_force(t, vel[r0:r1], u[r0:r1], o["h"], rho_in[r0:r1], om_in[r0:r1],
+                            active=a, out={k: o[k] for k in ("acc", "dudt", "vsig", "npairs")})
+            ops.gravity(t, active=a, out={"acc": o["gacc"], "pot": o["pot"],
+                                          "nterms": o["nterms"]})
+
+    step_unbatched()
+    torch.cuda.synchronize()
+    tu = time.perf_counter()
+    for _ in range(steps):
+        step_unbatched()
+    torch.cuda.synchronize()
+    unbatched_ms = 1e3 * (time.perf_counter() - tu) / steps
+    ctx.nonconverged(reset=True)
+    for t in trees:
+        t[0].close()
+    print(f"bench: unbatched {unbatched_ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return {
+        "workload": (f"{b.name}: {b.n_snap} Plummer snapshots (32 spheres + 20% background, "
+                     f"half gas), sizes log-uniform in [1e3, 1e6], n={b.n}, time-bin active "
+                     f"sets 2^-K with K = round(-log2 f), f log-uniform in [1e-3, 1]; "
+                     f"active {b.active.size}; FP32, 295 neighbours, theta=0.5, eps=1e-3"),
+        "value": inter / (graph_ms * 1e-3),
+        "unit": "interactions/s",
+        "ms_per_step": graph_ms,
+        "eager_ms_per_step": eager_ms,
+        "unbatched_ms_per_step": unbatched_ms,
+        "unbatched_value": inter / (unbatched_ms * 1e-3),
+        "forest_build_ms": build_ms,
+        "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
+        "h_nonconverged": nonconv,
+        "step": "h solve + density, hydro force, gravity over every snapshot's active set: "
+                "one persistent launch per kernel, the step captured in a HIP graph",
+    }
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -192,6 +330,8 @@ def main() -> int:
     ap.add_argument("--spheres", type=int, default=32)
     ap.add_argument("--cpu-samples", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -313,6 +453,8 @@ def main() -> int:
                    "h_passes_per_wave": passes / max(waves, 1), "path": "plain"},
         "roofline": roofline,
     }
+    if not args.no_batched:
+        line["batched"] = run_batched(dev, args.steps, args.warmup)
     if args.copy_calibration:
         copy_calibration(dev)
     if not args.no_cpu_baseline:

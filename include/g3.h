@@ -59,7 +59,10 @@ typedef enum { G3_F32 = 0, G3_F64 = 1 } g3_dtype;
 enum { G3_GATHER = 0, G3_SYMMETRIC = 1, G3_GRAVITY = 2 };
 
 typedef struct g3_ctx g3_ctx;   /* scratch pools, counters, last error */
-typedef struct g3_tree g3_tree; /* sorted copies and octrees of one snapshot */
+typedef struct g3_tree g3_tree; /* sorted copies and octrees of a forest of
+                                   snapshots (one snapshot: a plain tree) */
+
+enum { G3_MAX_SNAPSHOTS = 1 << 20 };
 
 /* Result-defining parameters (host struct, read during the call only). */
 typedef struct {
@@ -87,7 +90,8 @@ const char *g3_last_error(const g3_ctx *ctx);
 int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
 
 /*
- * Build (or rebuild in place) the octrees of one particle set: one over all
+ * Build (or rebuild in place) the octrees of one particle set (one
+ * snapshot, a forest of one tree; see g3_build_forest): one over all
  * particles (gravity) and one over the gas particles (SPH). The octree
  * follows Barnes & Hut (1986): the root is the cube `box`; a node is the set
  * of particles sharing a 3l-bit prefix of their 63-bit Morton key
@@ -99,11 +103,11 @@ int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
  *   n      particles (0 allowed)
  *   pos_t  G3_F32 (pos is float[n][3]: the plain path) or G3_F64 (pos is
  *          double[n][3]: the mixed-precision path). With G3_F64 the tree keeps
- *          the FP64 positions; the kernels work on FP32 offsets from each
- *          wavefront's group centre with compensated sums, take every
- *          neighbour and opening decision exactly in FP64 (an FP32 test on
- *          the offsets, re-tested in FP64 inside its error band), and solve
- *          h in FP64. The h arrays of that tree's SPH calls are double.
+ *          the FP64 positions; the kernels work on FP32 offsets (the FP64
+ *          difference from the target, rounded) with compensated sums, take
+ *          every neighbour and opening decision exactly in FP64 (an FP32 test
+ *          on the offsets, re-tested in FP64 inside its error band), and
+ *          solve h in FP64. The h arrays of that tree's SPH calls are double.
  *   pos    [n][3] positions;  mass [n];  type [n] (0 gas, 1 collisionless;
  *          NULL: all gas)
  *   box    (host) [4] = lower corner xyz, side > 0
@@ -114,6 +118,27 @@ int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
 int g3_build_tree(g3_ctx *ctx, int64_t n, int32_t pos_t, const void *pos,
                   const float *mass, const uint8_t *type, const double *box,
                   const g3_params *p, g3_tree **tree, void *stream);
+/*
+ * Build a forest: n_snap independent snapshots in one tree object, so that
+ * every later call serves the active particles of all of them in one
+ * launch per kernel (the regime of few and uneven active particles, which
+ * the paper names as its speedup limit, section 3). Snapshot k is the
+ * caller ids [snap_off[k], snap_off[k+1]) with its own root cube
+ * box[4k..4k+3]; each snapshot's octrees are exactly those g3_build_tree
+ * builds for it alone, and no interaction crosses snapshots. Particle
+ * arrays of the other calls span all n = snap_off[n_snap] particles
+ * (caller order), active ids are caller ids over the whole forest, and the
+ * exported octree is the concatenation of the snapshots' octrees (node
+ * skips and first members offset by the earlier snapshots).
+ *   n_snap    1..G3_MAX_SNAPSHOTS
+ *   snap_off  (host) [n_snap + 1], snap_off[0] = 0, non-decreasing (empty
+ *             snapshots allowed)
+ *   box       (host) [n_snap][4] = lower corner xyz, side > 0
+ * Other arguments as g3_build_tree. SYNCS. */
+int g3_build_forest(g3_ctx *ctx, int32_t n_snap, const int64_t *snap_off,
+                    int32_t pos_t, const void *pos, const float *mass,
+                    const uint8_t *type, const double *box, const g3_params *p,
+                    g3_tree **tree, void *stream);
 /* Release a tree (also released by g3_ctx_destroy). NULL is ignored. */
 void g3_tree_destroy(g3_ctx *ctx, g3_tree *tree);
 /* Sizes of one of the tree's octrees: which = 0 all particles, 1 gas.

@@ -1,16 +1,20 @@
 // The C ABI of libg3.so (declared in include/g3.h): argument checks, device
 // selection, scratch management and the order of the launches of each call.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "g3_device.h"
 #include "g3_internal.h"
 
 namespace g3 {
 
-int select_gas(g3_ctx *c, const uint8_t *type, int64_t n, int64_t *m_out, hipStream_t s);
+int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, hipStream_t s);
 
 void *scratch(g3_ctx *c, int slot, size_t bytes) {
   g3_ctx::Buf &b = c->scratch[slot];
@@ -112,34 +116,114 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-int compact_targets(g3_ctx *c, const Octree &o, const int32_t *iperm, int64_t n_caller,
-                    int64_t n_act, const int32_t *active, int32_t **targets, int32_t **rows,
-                    uint32_t **dcount, hipStream_t s) {
-  *targets = nullptr;
-  *rows = nullptr;
-  *dcount = nullptr;
-  if (!active || o.n == 0) return G3_OK;
+namespace {
+
+// Group table of one launch (one workgroup): snapshot k's targets start at
+// tstart[k] (its sorted start soff[k] counted through the compaction scan
+// `slot`, or soff[k] itself when every member is a target) and form
+// ceil(T_k / 64) groups starting at gstart[k]. Also clears the work queue.
+constexpr int kTableBlock = 1024;
+__global__ __launch_bounds__(kTableBlock) void k_group_table(
+    const int32_t *__restrict__ soff, int n_snap, const uint32_t *__restrict__ slot,
+    int32_t *__restrict__ tstart, int32_t *__restrict__ gstart, unsigned *__restrict__ queue) {
+  __shared__ int32_t part[kTableBlock];
+  const int tid = (int)threadIdx.x;
+  if (tid < 8) queue[tid] = 0u;
+  const int per = (n_snap + kTableBlock - 1) / kTableBlock;
+  const int k0 = min(tid * per, n_snap), k1 = min(k0 + per, n_snap);
+  auto first = [&](int k) { return slot ? (int32_t)slot[soff[k]] : soff[k]; };
+  int32_t sum = 0;
+  for (int k = k0; k < k1; ++k) sum += (first(k + 1) - first(k) + kWave - 1) / kWave;
+  part[tid] = sum;
+  __syncthreads();
+  for (int d = 1; d < kTableBlock; d <<= 1) {  // inclusive scan of the sums
+    const int32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t base = part[tid] - sum;
+  for (int k = k0; k < k1; ++k) {
+    const int32_t f = first(k);
+    tstart[k] = f;
+    gstart[k] = base;
+    base += (first(k + 1) - f + kWave - 1) / kWave;
+  }
+  if (tid == kTableBlock - 1) {
+    tstart[n_snap] = first(n_snap);
+    gstart[n_snap] = part[tid];
+  }
+}
+
+}  // namespace
+
+int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
+                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s) {
+  *w = Work();
   const int64_t m = o.n;
-  uint32_t *mark = (uint32_t *)scratch(c, kFlags, (m + 1) * sizeof(uint32_t));
-  uint32_t *slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
-  int32_t *rowp1 = (int32_t *)scratch(c, kCounts, (m + 1) * sizeof(int32_t));
-  uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m) * sizeof(uint32_t));
-  int32_t *tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
-  int32_t *rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
-  if (!mark || !slot || !rowp1 || !stmp || !tg || !rw)
-    return fail(c, G3_ENOMEM, "device allocation of the active-set scratch failed");
-  k_zero_u32<<<nblk(m), 256, 0, s>>>(mark, m);
-  if (n_act > 0)
-    k_mark<<<nblk(n_act), 256, 0, s>>>(active, n_act, iperm, n_caller, mark, rowp1);
-  hipError_t e = scan_u32(mark, slot, m, stmp, s);
-  if (e != hipSuccess) return hip_fail(c, e, "active-set scan");
-  k_compact<<<nblk(m), 256, 0, s>>>(mark, slot, rowp1, m, tg, rw);
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(c, e, "active-set compaction");
-  *targets = tg;
-  *rows = rw;
-  *dcount = slot + m;
+  if (m == 0) return G3_OK;
+  const int n_snap = t->n_snap;
+  int32_t *tg = nullptr, *rw = nullptr;
+  uint32_t *slot = nullptr;
+  if (active) {
+    uint32_t *mark = (uint32_t *)scratch(c, kFlags, (m + 1) * sizeof(uint32_t));
+    slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
+    int32_t *rowp1 = (int32_t *)scratch(c, kCounts, (m + 1) * sizeof(int32_t));
+    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m) * sizeof(uint32_t));
+    tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
+    rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
+    if (!mark || !slot || !rowp1 || !stmp || !tg || !rw)
+      return fail(c, G3_ENOMEM, "device allocation of the active-set scratch failed");
+    k_zero_u32<<<nblk(m), 256, 0, s>>>(mark, m);
+    if (n_act > 0)
+      k_mark<<<nblk(n_act), 256, 0, s>>>(active, n_act, iperm, t->n, mark, rowp1);
+    hipError_t e = scan_u32(mark, slot, m, stmp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "active-set scan");
+    k_compact<<<nblk(m), 256, 0, s>>>(mark, slot, rowp1, m, tg, rw);
+  }
+  int32_t *tab = (int32_t *)scratch(c, kGroups, (2 * ((size_t)n_snap + 1) + 8) * sizeof(int32_t));
+  if (!tab) return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+  int32_t *tstart = tab, *gstart = tab + n_snap + 1;
+  unsigned *queue = (unsigned *)(gstart + n_snap + 1);
+  k_group_table<<<1, kTableBlock, 0, s>>>(o.soff, n_snap, slot, tstart, gstart, queue);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "group table");
+  w->gs.targets = tg;
+  w->gs.tstart = tstart;
+  w->gs.gstart = gstart;
+  w->gs.nroot = o.nroot;
+  w->gs.sbox = t->sbox;
+  w->gs.queue = queue;
+  w->gs.n_snap = n_snap;
+  w->rows = rw;
+  w->max_groups = max_groups_of(active ? std::min<int64_t>(n_act, m) : m, n_snap);
   return G3_OK;
+}
+
+unsigned persistent_grid(const void *kern, int block, int64_t max_groups) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, int64_t> resident;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int64_t cap;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = resident.find({dev, kern});
+    if (it == resident.end()) {
+      int per_cu = 0, ncu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess ||
+          per_cu < 1)
+        per_cu = 1;
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          ncu < 1)
+        ncu = 1;
+      it = resident.emplace(std::make_pair(dev, kern), (int64_t)per_cu * ncu).first;
+    }
+    cap = it->second;
+  }
+  const int64_t waves_per_block = block / kWave;
+  const int64_t need = (max_groups + waves_per_block - 1) / waves_per_block;
+  return (unsigned)std::max<int64_t>(1, std::min(need, cap));
 }
 
 }  // namespace g3
@@ -173,7 +257,8 @@ int g3_ctx_create(g3_ctx **out, int device) {
 
 static void free_octree(Octree &o) {
   for (void *p : {(void *)o.keys, (void *)o.perm, (void *)o.xm, (void *)o.nodes, (void *)o.mom,
-                  (void *)o.vh, (void *)o.aux, (void *)o.x64, (void *)o.h64, (void *)o.c64})
+                  (void *)o.vh, (void *)o.aux, (void *)o.x64, (void *)o.h64, (void *)o.c64,
+                  (void *)o.soff, (void *)o.nroot})
     if (p) (void)hipFree(p);
   o = Octree();
 }
@@ -182,6 +267,8 @@ static void free_tree(g3_tree *t) {
   if (!t) return;
   if (t->iperm_all) (void)hipFree(t->iperm_all);
   if (t->iperm_gas) (void)hipFree(t->iperm_gas);
+  if (t->coff) (void)hipFree(t->coff);
+  if (t->sbox) (void)hipFree(t->sbox);
   free_octree(t->all);
   free_octree(t->gas);
   delete t;
@@ -218,21 +305,31 @@ int g3_ctx_stats(g3_ctx *c, int64_t *stats, int32_t reset) {
   return G3_OK;
 }
 
-int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const float *mass,
-                  const uint8_t *type, const double *box, const g3_params *p, g3_tree **tree,
-                  void *stream) {
+int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t pos_t,
+                    const void *pos, const float *mass, const uint8_t *type, const double *box,
+                    const g3_params *p, g3_tree **tree, void *stream) {
   if (!c) return G3_EINVAL;
-  if (n < 0 || n >= (int64_t)INT32_MAX) return fail(c, G3_EINVAL, "g3_build_tree: n out of range");
+  if (n_snap < 1 || n_snap > G3_MAX_SNAPSHOTS || !snap_off || !box)
+    return fail(c, G3_EINVAL, "g3_build_forest: need 1..G3_MAX_SNAPSHOTS snapshots, offsets and boxes");
+  if (snap_off[0] != 0) return fail(c, G3_EINVAL, "g3_build_forest: snap_off[0] must be 0");
+  for (int32_t k = 0; k < n_snap; ++k)
+    if (snap_off[k + 1] < snap_off[k])
+      return fail(c, G3_EINVAL, "g3_build_forest: snap_off must be non-decreasing");
+  const int64_t n = snap_off[n_snap];
+  if (n < 0 || n >= (int64_t)INT32_MAX) return fail(c, G3_EINVAL, "g3_build_forest: n out of range");
   if (pos_t != G3_F32 && pos_t != G3_F64)
-    return fail(c, G3_EINVAL, "g3_build_tree: pos_t must be G3_F32 or G3_F64");
-  if (n > 0 && (!pos || !mass)) return fail(c, G3_EINVAL, "g3_build_tree: null pos/mass");
-  if (!box || !(box[3] > 0.0) || !std::isfinite(box[0]) || !std::isfinite(box[1]) ||
-      !std::isfinite(box[2]) || !std::isfinite(box[3]))
-    return fail(c, G3_EINVAL, "g3_build_tree: box must be lo xyz and a finite side > 0");
-  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_build_tree: bad params");
-  if (!tree) return fail(c, G3_EINVAL, "g3_build_tree: null tree handle");
+    return fail(c, G3_EINVAL, "g3_build_forest: pos_t must be G3_F32 or G3_F64");
+  if (n > 0 && (!pos || !mass)) return fail(c, G3_EINVAL, "g3_build_forest: null pos/mass");
+  for (int32_t k = 0; k < n_snap; ++k) {
+    const double *b = box + 4 * k;
+    if (!(b[3] > 0.0) || !std::isfinite(b[0]) || !std::isfinite(b[1]) || !std::isfinite(b[2]) ||
+        !std::isfinite(b[3]))
+      return fail(c, G3_EINVAL, "g3_build_forest: every box must be lo xyz and a finite side > 0");
+  }
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_build_forest: bad params");
+  if (!tree) return fail(c, G3_EINVAL, "g3_build_forest: null tree handle");
   g3_tree *t = *tree;
-  if (t && t->owner != c) return fail(c, G3_ESTATE, "g3_build_tree: tree of another ctx");
+  if (t && t->owner != c) return fail(c, G3_ESTATE, "g3_build_forest: tree of another ctx");
   DeviceGuard g(c->device);
   int st = check_pending(c);
   if (st) return st;
@@ -253,31 +350,73 @@ int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const fl
     const int64_t cap = n > 0 ? n : 1;
     if (hipMalloc((void **)&t->iperm_all, cap * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void **)&t->iperm_gas, cap * sizeof(int32_t)) != hipSuccess)
-      return fail(c, G3_ENOMEM, "g3_build_tree: allocation failed");
+      return fail(c, G3_ENOMEM, "g3_build_forest: allocation failed");
     t->cap_n = cap;
   }
+  if (n_snap > t->cap_snap) {
+    for (void *q : {(void *)t->coff, (void *)t->sbox, (void *)t->all.soff, (void *)t->all.nroot,
+                    (void *)t->gas.soff, (void *)t->gas.nroot})
+      if (q) (void)hipFree(q);
+    t->coff = nullptr; t->sbox = nullptr;
+    t->all.soff = t->all.nroot = t->gas.soff = t->gas.nroot = nullptr;
+    t->cap_snap = 0;
+    const size_t k1 = (size_t)n_snap + 1;
+    if (hipMalloc((void **)&t->coff, k1 * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void **)&t->sbox, k1 * sizeof(double4)) != hipSuccess ||
+        hipMalloc((void **)&t->all.soff, k1 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&t->all.nroot, k1 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&t->gas.soff, k1 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&t->gas.nroot, k1 * sizeof(int32_t)) != hipSuccess)
+      return fail(c, G3_ENOMEM, "g3_build_forest: allocation failed");
+    t->cap_snap = n_snap;
+  }
   t->n = n;
-  std::memcpy(t->box, box, sizeof(t->box));
-  t->scale = std::ldexp(1.0, kMaxLevel) / box[3];
+  t->n_snap = n_snap;
+  t->snap_off.assign(snap_off, snap_off + n_snap + 1);
+  t->box.assign(box, box + 4 * (size_t)n_snap);
   t->leaf = p->leaf_size;
   t->f64 = pos_t == G3_F64;
   // FP64 positions are walked through their FP32 copies: pad every pruning
-  // radius by a bound on the rounding of coordinates as large as the box's
-  double amax = 0.0;
-  for (int a = 0; a < 3; ++a)
-    amax = std::max(amax, std::max(std::fabs(box[a]), std::fabs(box[a] + box[3])));
+  // radius by a bound on the rounding of coordinates as large as the boxes'
+  double amax = 0.0, smax = 0.0;
+  for (int32_t k = 0; k < n_snap; ++k) {
+    const double *b = box + 4 * k;
+    for (int a = 0; a < 3; ++a) amax = std::max(amax, std::max(std::fabs(b[a]), std::fabs(b[a] + b[3])));
+    smax = std::max(smax, b[3]);
+  }
+  t->max_side = smax;
   t->slack = t->f64 ? (float)std::ldexp(amax, -20) : 0.0f;
+  std::vector<double4> hb(n_snap);
+  for (int32_t k = 0; k < n_snap; ++k)
+    hb[k] = make_double4(box[4 * k], box[4 * k + 1], box[4 * k + 2], box[4 * k + 3]);
+  hipError_t e = hipMemcpyAsync(t->coff, t->snap_off.data(), (n_snap + 1) * sizeof(int64_t),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(t->sbox, hb.data(), n_snap * sizeof(double4), hipMemcpyHostToDevice, s);
+  // the host staging above is released on return: wait for the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest: snapshot table upload");
+  int64_t mgas = 0;
+  st = select_members(c, t, type, &mgas, s);
+  if (st) return st;
   st = build_octree(c, t, t->all, pos, t->f64, mass, n, s);
   if (st) return st;
-  hipError_t e = fill_i32(t->iperm_gas, -1, n, s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_build_tree");
-  int64_t mgas = 0;
-  st = select_gas(c, type, n, &mgas, s);
-  if (st) return st;
+  e = fill_i32(t->iperm_gas, -1, n, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest");
   st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s);
   if (st) return st;
   c->err.clear();
   return G3_OK;
+}
+
+int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const float *mass,
+                  const uint8_t *type, const double *box, const g3_params *p, g3_tree **tree,
+                  void *stream) {
+  if (!c) return G3_EINVAL;
+  if (n < 0 || n >= (int64_t)INT32_MAX) return fail(c, G3_EINVAL, "g3_build_tree: n out of range");
+  if (!box) return fail(c, G3_EINVAL, "g3_build_tree: null box");
+  const int64_t off[2] = {0, n};
+  return g3_build_forest(c, 1, off, pos_t, pos, mass, type, box, p, tree, stream);
 }
 
 void g3_tree_destroy(g3_ctx *c, g3_tree *t) {
@@ -336,7 +475,6 @@ static GravParams grav_params(const g3_params *p, const g3_tree *t) {
   gp.inside_test = p->theta * p->theta >= 0.33 ? 1 : 0;
   gp.f64 = t->f64;
   gp.theta = p->theta;
-  gp.side = t->box[3];
   return gp;
 }
 
@@ -402,18 +540,16 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
     if (e == hipSuccess && kind == G3_SYMMETRIC) e = refit_hmax(o, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk prep");
   }
-  int32_t *targets, *rows;
-  uint32_t *dcount;
-  st = compact_targets(c, o, iperm, t->n, n_act, active, &targets, &rows, &dcount, s);
+  Work wk;
+  st = prepare_work(c, t, o, iperm, n_act, active, &wk, s);
   if (st) return st;
-  const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
   int32_t *counts = (int32_t *)scratch(c, kWalkCounts, (n_act + 1) * sizeof(int32_t));
   int64_t *stmp = (int64_t *)scratch(c, kMisc, scan_tmp_elems(n_act) * sizeof(int64_t) + 64);
   if (!counts || !stmp) return fail(c, G3_ENOMEM, "g3_walk: allocation failed");
   e = fill_i32(counts, 0, n_act, s);
   GravParams gp = grav_params(p, t);
   if (e == hipSuccess)
-    e = launch_walk(o, kind, targets, rows, dcount, maxt, gp, counts, nullptr, nullptr, s);
+    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, counts, nullptr, nullptr, s);
   if (e == hipSuccess) e = scan_i32_to_i64(counts, offsets, n_act, stmp, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&c->pinned[3], offsets + n_act, sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -422,7 +558,9 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   *total = c->pinned[3];
   if (*total > capacity) return fail(c, G3_EOVERFLOW, "g3_walk: list exceeds capacity");
   if (*total > 0) {
-    e = launch_walk(o, kind, targets, rows, dcount, maxt, gp, counts, offsets, list, s);
+    // the fill pass takes the groups from a fresh queue
+    k_zero_u32<<<1, 64, 0, s>>>(wk.gs.queue, 8);
+    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, counts, offsets, list, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk fill pass");
   }
   c->err.clear();
@@ -444,14 +582,11 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const Octree &o = t->gas;
-  int32_t *targets, *rows;
-  uint32_t *dcount;
-  st = compact_targets(c, o, t->iperm_gas, t->n, n_act, active, &targets, &rows, &dcount, s);
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s);
   if (st) return st;
-  const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
-  const float hcap = (float)(2.0 * std::sqrt(3.0) * t->box[3]);
-  hipError_t e = launch_density(o, targets, dcount, maxt, sph_params(p, t), solve_h ? 1 : 0, h,
-                                rho, drho_dh, omega, nngb, c->counters, s, hcap);
+  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(p, t), solve_h ? 1 : 0, h,
+                                rho, drho_dh, omega, nngb, c->counters, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
   return G3_OK;
@@ -477,12 +612,10 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
   if (e == hipSuccess) e = refit_hmax(o, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
-  int32_t *targets, *rows;
-  uint32_t *dcount;
-  st = compact_targets(c, o, t->iperm_gas, t->n, n_act, active, &targets, &rows, &dcount, s);
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s);
   if (st) return st;
-  const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
-  e = launch_hydro(o, targets, dcount, maxt, sp, acc, dudt, vsig, npairs, s);
+  e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force");
   c->err.clear();
   return G3_OK;
@@ -500,13 +633,10 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const Octree &o = t->all;
-  int32_t *targets, *rows;
-  uint32_t *dcount;
-  st = compact_targets(c, o, t->iperm_all, t->n, n_act, active, &targets, &rows, &dcount, s);
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
   if (st) return st;
-  const int64_t maxt = active ? std::min<int64_t>(n_act, o.n) : o.n;
-  hipError_t e =
-      launch_gravity(o, targets, dcount, maxt, grav_params(p, t), acc, pot, nterms, s);
+  hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
   c->err.clear();
   return G3_OK;

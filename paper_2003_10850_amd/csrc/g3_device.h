@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "g3_internal.h"
+
 namespace g3 {
 
 // Order LDS traffic between the lanes of one wavefront (a compiler barrier
@@ -16,17 +18,6 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Renumber them so that XCD x runs one contiguous range of logical
-// blocks: spatially adjacent groups then share tree nodes and candidates in
-// the same L2. The map is a bijection of [0, nb).
-__device__ __forceinline__ int64_t xcd_block() {
-  constexpr unsigned kXcd = 8;
-  const unsigned b = blockIdx.x, nb = gridDim.x;
-  const unsigned x = b % kXcd, q = nb / kXcd, r = nb % kXcd;
-  return (int64_t)x * q + (x < r ? x : r) + b / kXcd;
-}
 
 // Broadcast of a wave-uniform value into a scalar register.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -70,6 +61,68 @@ __device__ __forceinline__ void neumaier_add(float &s, float &c, float x) {
 __device__ __forceinline__ float sq_exact(float a) {
 #pragma clang fp contract(off)
   return a * a;
+}
+
+}  // namespace g3
+
+namespace g3 {
+
+// Index k of the segment holding v, for a non-decreasing table
+// off[0..n] with off[0] <= v < off[n]: the largest k with off[k] <= v (so
+// empty segments are skipped).
+template <typename T>
+__device__ __forceinline__ int segment_of(const T *__restrict__ off, int n, int64_t v) {
+  int lo = 0, hi = n;  // off[lo] <= v < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)off[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+struct Group {
+  int t0, count;  // targets [t0, t0 + count), count in 1..64
+  int snap;       // snapshot
+  int root, end;  // the snapshot's nodes [root, end)
+};
+
+__device__ __forceinline__ Group group_at(const Groups &gs, int g) {
+  Group G;
+  const int k = segment_of(gs.gstart, gs.n_snap, g);
+  const int t1 = gs.tstart[k + 1];
+  G.t0 = gs.tstart[k] + (g - gs.gstart[k]) * 64;
+  G.count = min(64, t1 - G.t0);
+  G.snap = k;
+  G.root = gs.nroot[k];
+  G.end = gs.nroot[k + 1];
+  return G;
+}
+
+// Persistent launches: a wave takes groups one at a time from a queue until
+// none is left. The groups are split into 8 contiguous ranges, one per XCD
+// (workgroups are dispatched round-robin over the XCDs), so spatially close
+// groups share an L2; a wave drains its own XCD's range first and then
+// helps with the others. Returns the next group, or -1 when all are taken.
+// `range` is the wave's state (0 before the first call). Every wave leaves
+// after at most (its groups + 8) atomic increments.
+__device__ __forceinline__ int next_group(const Groups &gs, int &range) {
+  constexpr int kXcd = 8;
+  const int total = gs.gstart[gs.n_snap];
+  const int home = (int)(blockIdx.x % kXcd);
+  while (range < kXcd) {
+    const int r = (home + range) % kXcd;
+    const int lo = (int)(((int64_t)total * r) / kXcd);
+    const int hi = (int)(((int64_t)total * (r + 1)) / kXcd);
+    unsigned got = 0u;
+    if (lo < hi) {
+      if ((threadIdx.x & 63u) == 0u) got = atomicAdd(&gs.queue[r], 1u);
+      got = (unsigned)__builtin_amdgcn_readfirstlane((int)got);
+      if ((int64_t)lo + got < (int64_t)hi) return lo + (int)got;
+    }
+    ++range;
+  }
+  return -1;
 }
 
 }  // namespace g3

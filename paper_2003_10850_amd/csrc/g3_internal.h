@@ -47,6 +47,11 @@ struct Octree {
   int64_t cap_h64 = 0;
   double4 *c64 = nullptr;  // [nnodes] FP64 centre of mass and mass (FP64 trees)
   int64_t cap_c64 = 0;
+  // forest of snapshots: snapshot k owns the sorted members [soff[k], soff[k+1])
+  // and the nodes [nroot[k], nroot[k+1]) (its root first, when it has members)
+  int32_t *soff = nullptr;   // [n_snap + 1]
+  int32_t *nroot = nullptr;  // [n_snap + 1]
+  int64_t cap_snap = 0;
 };
 
 }  // namespace g3
@@ -56,8 +61,14 @@ struct g3_tree {
   int device = 0;
   int64_t n = 0;  // caller particles
   int64_t cap_n = 0;
-  double box[4] = {0, 0, 0, 1};
-  double scale = 0;  // 2^21 / side
+  // snapshots: caller ids [snap_off[k], snap_off[k+1]) in box k (lo xyz, side)
+  int32_t n_snap = 1;
+  std::vector<int64_t> snap_off;  // host [n_snap + 1]
+  std::vector<double> box;        // host [n_snap][4]
+  int64_t *coff = nullptr;        // device copy of snap_off
+  double4 *sbox = nullptr;        // device copy of the boxes
+  int64_t cap_snap = 0;
+  double max_side = 0;            // largest snapshot side
   int32_t leaf = 8;
   int32_t f64 = 0;   // positions (and h) are FP64: the mixed-precision path
   float slack = 0;   // bound on the rounding of the FP32 position copies
@@ -86,6 +97,7 @@ namespace g3 {
 enum Slot {
   kSortKeys = 0, kSortVals, kSortTmp, kScanTmp, kCounts, kOffsets,
   kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
+  kSnapKeys, kSnapKeysAlt, kGroups,
   kNumSlots
 };
 
@@ -101,11 +113,12 @@ hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
 hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp,
                            hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs by key bits [0, 64).
-// tmp must hold radix_tmp_bytes(n) bytes. Result ends in keys/vals.
+// Stable LSD radix sort of (key, value) pairs by key bits [0, bits), bits a
+// multiple of 8. tmp must hold radix_tmp_bytes(n) bytes. Result ends in
+// keys/vals.
 size_t radix_tmp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
-                            uint32_t *vals_alt, int64_t n, void *tmp, hipStream_t s);
+                            uint32_t *vals_alt, int64_t n, int bits, void *tmp, hipStream_t s);
 
 // Tree build of one octree (members already selected in `ids`/`keys`).
 int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
@@ -114,12 +127,40 @@ hipError_t refit_hmax(Octree &o, hipStream_t s);
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
-// Active set -> Morton-ordered target list of one octree. Writes
-// targets[0..cnt) (sorted positions) and rows (index in `active`), with
-// the count at *dcount (device). active == nullptr selects every member.
-int compact_targets(g3_ctx *c, const Octree &o, const int32_t *iperm, int64_t n_caller,
-                    int64_t n_act, const int32_t *active, int32_t **targets,
-                    int32_t **rows, uint32_t **dcount, hipStream_t s);
+// Work of one interaction launch: groups of up to 64 Morton-consecutive
+// targets (one per lane) that never straddle two snapshots of a forest.
+// Snapshot k holds targets [tstart[k], tstart[k+1]) and groups
+// [gstart[k], gstart[k+1]); its octree is the node range
+// [nroot[k], nroot[k+1]).
+struct Groups {
+  const int32_t *targets;  // compacted sorted positions; nullptr: every member
+  const int32_t *tstart;   // [n_snap + 1]
+  const int32_t *gstart;   // [n_snap + 1]
+  const int32_t *nroot;    // [n_snap + 1]
+  const double4 *sbox;     // [n_snap] snapshot box: lo xyz, side
+  unsigned *queue;         // [8] per-XCD counters, zero at launch
+  int n_snap;
+};
+
+// Upper bound on the groups of max_targets targets in n_snap snapshots.
+inline int64_t max_groups_of(int64_t max_targets, int64_t n_snap) {
+  return (max_targets + kWave - 1) / kWave + (n_snap < max_targets ? n_snap : max_targets);
+}
+
+// Active set -> group table of one octree (scratch owned by the ctx).
+// rows[t] is the index in `active` of target t (nullptr with every member
+// active: rows are then caller ids). max_groups bounds the group count.
+struct Work {
+  Groups gs;
+  const int32_t *rows;
+  int64_t max_groups;
+};
+int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
+                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s);
+
+// Grid of a persistent launch: the workgroups that can be resident at once
+// (occupancy of `kern` x compute units), or fewer if there are few groups.
+unsigned persistent_grid(const void *kern, int block, int64_t max_groups);
 
 struct SphParams {
   float n_ngb, h_tol, gamma, alpha;
@@ -129,32 +170,30 @@ struct SphParams {
   float slack;    // walk pruning pad for FP32 copies of FP64 positions (0 if FP32)
 };
 
-hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const SphParams &sp, int solve_h, void *h,
-                          float *rho, float *drho_dh, float *omega, int32_t *nngb,
-                          unsigned long long *counters, hipStream_t s, float hcap);
+hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_groups,
+                          const SphParams &sp, int solve_h, void *h, float *rho,
+                          float *drho_dh, float *omega, int32_t *nngb,
+                          unsigned long long *counters, hipStream_t s);
 hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const void *h,
                              const float *rho, const float *omega, float gamma, int f64,
                              hipStream_t s);
-hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                        int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
-                        float *vsig, int32_t *npairs, hipStream_t s);
+hipError_t launch_hydro(const Octree &gas, const Groups &gs, int64_t max_groups,
+                        const SphParams &sp, float *acc, float *dudt, float *vsig,
+                        int32_t *npairs, hipStream_t s);
 
 struct GravParams {
   float theta2, eps2, G;
   int inside_test;  // evaluate the cube-containment test (theta^2 >= 1/3)
   int f64;          // FP64 positions: mixed-precision kernels, FP64 decisions
   double theta;     // opening angle (FP64 decisions)
-  double side;      // root cube side (node sides for FP64 decisions)
 };
-hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const GravParams &gp, float *acc, float *pot,
-                          int32_t *nterms, hipStream_t s);
+hipError_t launch_gravity(const Octree &all, const Groups &gs, int64_t max_groups,
+                          const GravParams &gp, float *acc, float *pot, int32_t *nterms,
+                          hipStream_t s);
 
 // Walk lists: counts pass (list == nullptr) or fill pass.
-hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
-                       const uint32_t *dcount, int64_t max_targets,
-                       const GravParams &gp, int32_t *counts, const int64_t *offsets,
-                       int32_t *list, hipStream_t s);
+hipError_t launch_walk(const Octree &o, int kind, const Groups &gs, const int32_t *rows,
+                       int64_t max_groups, const GravParams &gp, int32_t *counts,
+                       const int64_t *offsets, int32_t *list, hipStream_t s);
 
 }  // namespace g3

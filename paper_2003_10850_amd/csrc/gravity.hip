@@ -51,21 +51,21 @@ __device__ __forceinline__ bool open_accept64(double l, double theta, double4 c,
 // offsets could disagree with the FP64 one, the FP64 test decides.
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_gravity(
-    const Node *__restrict__ nodes, const double4 *__restrict__ c64n, int nnodes,
+    const Node *__restrict__ nodes, const double4 *__restrict__ c64n,
     const float4 *__restrict__ xm, const double4 *__restrict__ x64,
-    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ targets, const uint32_t *__restrict__ dcount, int64_t ntmax,
-    float theta2, float eps2, float G, int inside_test, double theta64, double side,
+    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
+    float theta2, float eps2, float G, int inside_test, double theta64,
     float *__restrict__ acc, float *__restrict__ pot, int32_t *__restrict__ nterms) {
   __shared__ Entry tiles[kWpb][kTile];
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];  // FP64 source positions
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
-  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
-  if (g0 >= ntarg) return;
-  const int64_t t = g0 + lane;
-  const bool valid = t < ntarg;
-  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+  const Group grp = group_at(gs, g);
+  const int64_t t = grp.t0 + lane;
+  const bool valid = lane < grp.count;
+  const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
+  const double side = kF64 ? gs.sbox[grp.snap].w : 0.0;  // root cube side
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
   // mixed precision: every offset is the FP64 difference from this target,
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     wave_sync();
   };
 
-  int resume = valid ? 0 : INT32_MAX;  // lanes idle while cur < resume
-  int cur = 0;
-  while (cur < nnodes) {
+  int resume = valid ? grp.root : INT32_MAX;  // lanes idle while cur < resume
+  int cur = grp.root;
+  while (cur < grp.end) {
     const Node nd = nodes[cur];
     const bool act = cur >= resume;
     double4 cn = make_double4(0, 0, 0, 0);
@@ -209,19 +209,19 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     if (pot) pot[cid] = G * ph;
     if (nterms) nterms[cid] = nt;
   }
+  }  // groups
 }
 
 }  // namespace
 
-hipError_t launch_gravity(const Octree &all, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const GravParams &gp, float *acc, float *pot,
-                          int32_t *nterms, hipStream_t s) {
-  if (max_targets <= 0 || all.nnodes == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
+hipError_t launch_gravity(const Octree &all, const Groups &gs, int64_t max_groups,
+                          const GravParams &gp, float *acc, float *pot, int32_t *nterms,
+                          hipStream_t s) {
+  if (max_groups <= 0 || all.nnodes == 0) return hipSuccess;
   auto kern = gp.f64 ? k_gravity<true> : k_gravity<false>;
-  kern<<<blocks, kBlock, 0, s>>>(all.nodes, all.c64, (int)all.nnodes, all.xm, all.x64, all.keys,
-                                 all.perm, targets, dcount, max_targets, gp.theta2, gp.eps2,
-                                 gp.G, gp.inside_test, gp.theta, gp.side, acc, pot, nterms);
+  kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
+      all.nodes, all.c64, all.xm, all.x64, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
+      gp.inside_test, gp.theta, acc, pot, nterms);
   return hipGetLastError();
 }
 

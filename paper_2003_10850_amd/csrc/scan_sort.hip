@@ -216,7 +216,7 @@ size_t radix_tmp_bytes(int64_t n) {
 }
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
-                            uint32_t *vals_alt, int64_t n, void *tmp, hipStream_t s) {
+                            uint32_t *vals_alt, int64_t n, int bits, void *tmp, hipStream_t s) {
   if (n <= 1) return hipSuccess;
   const int64_t nb = (n + kRsTile - 1) / kRsTile;
   const int64_t h = nb * kRsBins;
@@ -225,7 +225,8 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
   uint32_t *stmp = offs + h + 1;
   uint64_t *ka = keys, *kb = keys_alt;
   uint32_t *va = vals, *vb = vals_alt;
-  for (int shift = 0; shift < 64; shift += kRsBits) {
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += kRsBits, ++passes) {
     k_rs_hist<<<(unsigned)nb, kRsBlock, 0, s>>>(ka, n, shift, hist, (int)nb);
     hipError_t e = scan_u32(hist, offs, h, stmp, s);
     if (e != hipSuccess) return e;
@@ -233,7 +234,13 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  return hipGetLastError();  // eight passes: the result is back in keys/vals
+  if (passes & 1) {  // the result is in the alternate buffers: copy it back
+    hipError_t e = hipMemcpyAsync(keys, keys_alt, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vals, vals_alt, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
 }
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {

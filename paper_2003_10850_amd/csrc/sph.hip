@@ -47,8 +47,9 @@ __device__ __forceinline__ float wc6_f(float q) {
 // First guess of h for a group: descend from the root along the group's
 // first member while the child still holds >= n_ngb members, then take the
 // mean density of that node's bounding box (of its cube if the box is flat).
-__device__ float group_density_guess(const Node *__restrict__ nodes, int s0, float n_ngb) {
-  int cur = 0;
+__device__ float group_density_guess(const Node *__restrict__ nodes, int root, int s0,
+                                     float n_ngb) {
+  int cur = root;
   for (;;) {
     const int4 meta = nodes[cur].meta;
     if (meta.w & kLeafBit) break;
@@ -88,10 +89,9 @@ constexpr float kBand64 = 1.9073486e-6f;  // 2^-19
 
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_density(
-    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
-    const double4 *__restrict__ x64, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ targets, const uint32_t *__restrict__ dcount, int64_t ntmax,
-    float n_ngb, float tol, float hcap, int solve, int max_iter, int walk_leaf, float slack,
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const double4 *__restrict__ x64, const int32_t *__restrict__ perm, const Groups gs,
+    float n_ngb, float tol, int solve, int max_iter, int walk_leaf, float slack,
     void *__restrict__ hptr, float *__restrict__ rho, float *__restrict__ drho_dh,
     float *__restrict__ omega, int32_t *__restrict__ nngb,
     unsigned long long *__restrict__ counters) {
@@ -100,13 +100,15 @@ __global__ __launch_bounds__(kBlock) void k_density(
   __shared__ float4 tiles[kWpb][kF64 ? 1 : kTile];
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
-  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
-  if (g0 >= ntarg) return;
-  const int64_t t = g0 + lane;
-  const bool valid = t < ntarg;
-  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
-  const int s0 = uniform(targets ? targets[g0] : (int)g0);
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+  const Group grp = group_at(gs, g);
+  const int64_t t = grp.t0 + lane;
+  const bool valid = lane < grp.count;
+  const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
+  const int s0 = uniform(gs.targets ? gs.targets[grp.t0] : grp.t0);
+  // h_hi is capped at twice the diagonal of the snapshot's box
+  const float hcap = (float)(3.4641016151377544 * gs.sbox[grp.snap].w);
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
   const int cid = perm[s];
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
   HT hcur = valid ? h[cid] : HT(1);
   if (solve) {
     if (__ballot(valid && !(hcur > HT(0)))) {
-      const float rho_g = group_density_guess(nodes, s0, n_ngb);
+      const float rho_g = group_density_guess(nodes, grp.root, s0, n_ngb);
       const float guess = cbrtf(3.0f * n_ngb * me.w / (4.0f * 3.14159265f * rho_g));
       if (!(hcur > HT(0))) hcur = (HT)fminf(guess, hcap);
     }
@@ -186,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
       neumaier_add(swh, cswh, pwh);
       wave_sync();
     };
-    int cur = 0;
-    while (cur < nnodes) {
+    int cur = grp.root;
+    while (cur < grp.end) {
       const Node nd = nodes[cur];
       const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < hw2;
       if (__ballot(want) == 0ull) {
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     if (nngb) nngb[cid] = res_n;
     if (failed) atomicAdd(&counters[0], 1ull);
   }
+  }  // groups
 }
 
 template <typename HT>
@@ -311,23 +314,22 @@ struct HydroTile {
 
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_hydro(
-    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
     const double4 *__restrict__ x64, const double *__restrict__ h64,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ targets,
-    const uint32_t *__restrict__ dcount, int64_t ntmax, float alpha, int walk_leaf,
+    const int32_t *__restrict__ perm, const Groups gs, float alpha, int walk_leaf,
     float slack, float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
     int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
   __shared__ double th64[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
-  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
-  if (g0 >= ntarg) return;
-  const int64_t t = g0 + lane;
-  const bool valid = t < ntarg;
-  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+  const Group grp = group_at(gs, g);
+  const int64_t t = grp.t0 + lane;
+  const bool valid = lane < grp.count;
+  const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
   const float4 me = xm[s], mv = vh[s], ma = aux[s];
   const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
   const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
@@ -426,8 +428,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     wave_sync();
   };
 
-  int cur = 0;
-  while (cur < nnodes) {
+  int cur = grp.root;
+  while (cur < grp.end) {
     const Node nd = nodes[cur];
     const float hm = fmaxf(hi, nd.lo_h.w) + slack;
     const bool want = hi > 0.0f && box_dist2(xi, nd.lo_h, nd.hi_l) < sq_exact(hm);
@@ -471,22 +473,22 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     if (vsig) vsig[cid] = vs;
     if (npairs) npairs[cid] = np - 1;  // the self pair always passes the test
   }
+  }  // groups
 }
 
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_density(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                          int64_t max_targets, const SphParams &sp, int solve_h, void *h,
-                          float *rho, float *drho_dh, float *omega, int32_t *nngb,
-                          unsigned long long *counters, hipStream_t s, float hcap) {
-  if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
+hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_groups,
+                          const SphParams &sp, int solve_h, void *h, float *rho,
+                          float *drho_dh, float *omega, int32_t *nngb,
+                          unsigned long long *counters, hipStream_t s) {
+  if (max_groups <= 0 || gas.nnodes == 0) return hipSuccess;
   auto kern = sp.f64 ? k_density<true> : k_density<false>;
-  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
-      gas.nodes, (int)gas.nnodes, gas.xm, gas.x64, gas.perm, targets, dcount, max_targets,
-      sp.n_ngb, sp.h_tol, hcap, solve_h, sp.max_iter, sp.walk_leaf, sp.slack, h, rho, drho_dh,
-      omega, nngb, counters);
+  kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
+      gas.nodes, gas.xm, gas.x64, gas.perm, gs, sp.n_ngb, sp.h_tol, solve_h, sp.max_iter,
+      sp.walk_leaf, sp.slack, h, rho, drho_dh, omega, nngb, counters);
   return hipGetLastError();
 }
 
@@ -514,14 +516,14 @@ hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, cons
   return hipGetLastError();
 }
 
-hipError_t launch_hydro(const Octree &gas, const int32_t *targets, const uint32_t *dcount,
-                        int64_t max_targets, const SphParams &sp, float *acc, float *dudt,
-                        float *vsig, int32_t *npairs, hipStream_t s) {
-  if (max_targets <= 0 || gas.nnodes == 0) return hipSuccess;
+hipError_t launch_hydro(const Octree &gas, const Groups &gs, int64_t max_groups,
+                        const SphParams &sp, float *acc, float *dudt, float *vsig,
+                        int32_t *npairs, hipStream_t s) {
+  if (max_groups <= 0 || gas.nnodes == 0) return hipSuccess;
   auto kern = sp.f64 ? k_hydro<true> : k_hydro<false>;
-  kern<<<nblk(max_targets, kBlock), kBlock, 0, s>>>(
-      gas.nodes, (int)gas.nnodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, gas.perm, targets,
-      dcount, max_targets, sp.alpha, sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
+  kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
+      gas.nodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, gas.perm, gs, sp.alpha,
+      sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
   return hipGetLastError();
 }
 

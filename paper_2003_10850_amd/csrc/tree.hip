@@ -50,16 +50,58 @@ __device__ __forceinline__ uint64_t morton_key(const T *p, double lx, double ly,
          spread3(cell_of(p[2], lz, scale));
 }
 
-// keys and identity values for the members selected by sel (nullptr: all)
+// keys and identity values for the members selected by sel (nullptr: all),
+// each keyed in the box of its snapshot (caller ids [coff[k], coff[k+1]))
 template <typename T>
 __global__ void k_keys(const T *__restrict__ pos, const int32_t *__restrict__ sel,
-                       int64_t m, double lx, double ly, double lz, double scale,
+                       int64_t m, const int64_t *__restrict__ coff,
+                       const double4 *__restrict__ sbox, int n_snap,
                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int64_t i = sel ? sel[k] : k;
-  keys[k] = morton_key(pos + 3 * i, lx, ly, lz, scale);
+  const double4 b = sbox[n_snap > 1 ? segment_of(coff, n_snap, i) : 0];
+  const double scale = 2097152.0 / b.w;  // 2^21 / side
+  keys[k] = morton_key(pos + 3 * i, b.x, b.y, b.z, scale);
   vals[k] = (uint32_t)i;
+}
+
+// Forest: the snapshot of each key-sorted member, for a stable sort by
+// snapshot after the sort by key.
+__global__ void k_snap_keys(const uint32_t *__restrict__ vals, int64_t m,
+                            const int64_t *__restrict__ coff, int n_snap,
+                            uint64_t *__restrict__ skey, uint32_t *__restrict__ sidx) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  skey[k] = (uint64_t)segment_of(coff, n_snap, (int64_t)vals[k]);
+  sidx[k] = (uint32_t)k;
+}
+
+__global__ void k_gather_sorted(const uint32_t *__restrict__ sidx, int64_t m,
+                                const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const uint32_t j = sidx[k];
+  kout[k] = kin[j];
+  vout[k] = vin[j];
+}
+
+// Sorted start of each snapshot: slot[coff[k]] (members before coff[k]
+// selected by the exclusive scan `slot`), or coff[k] when all are members.
+__global__ void k_soff(const int64_t *__restrict__ coff, int n_snap,
+                       const uint32_t *__restrict__ slot, int32_t *__restrict__ soff) {
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k > n_snap) return;
+  soff[k] = slot ? (int32_t)slot[coff[k]] : (int32_t)coff[k];
+}
+
+// First node of each snapshot: the first node its first member starts.
+__global__ void k_nroot(const uint32_t *__restrict__ off, const int32_t *__restrict__ soff,
+                        int n_snap, int32_t *__restrict__ nroot) {
+  const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k > n_snap) return;
+  nroot[k] = (int32_t)off[soff[k]];
 }
 
 __global__ void k_gas_flags(const uint8_t *__restrict__ type, int64_t n,
@@ -102,7 +144,9 @@ __device__ __forceinline__ int cpl(uint64_t a, uint64_t b) {
 constexpr int kMaxLeaf = 64;
 
 __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restrict__ keys,
-                                                        int64_t m, int B,
+                                                        int64_t m,
+                                                        const int32_t *__restrict__ soff,
+                                                        int n_snap, int B,
                                                         uint32_t *__restrict__ cnt,
                                                         uint8_t *__restrict__ lev,
                                                         int32_t *__restrict__ maxlev) {
@@ -118,21 +162,24 @@ __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restri
   if (p >= m) return;
   const uint64_t *kw = win + B + threadIdx.x;  // kw[d] = key of member p + d
   const uint64_t kp = kw[0];
-  const int delta = (p == 0) ? 0 : cpl(kp, kw[-1]) + 1;
+  // members of other snapshots count as missing: each snapshot is a tree
+  const int sn = n_snap > 1 ? segment_of(soff, n_snap, p) : 0;
+  const int64_t s0 = soff[sn], s1 = soff[sn + 1];
+  const int delta = (p == s0) ? 0 : cpl(kp, kw[-1]) + 1;
   // B-th largest of the window prefix lengths: merge two non-increasing runs
   int i = 1, j = 1;
   int val = -1;
-  int a = (p - 1 >= 0) ? cpl(kp, kw[-1]) : -1;
-  int b = (p + 1 < m) ? cpl(kp, kw[1]) : -1;
+  int a = (p - 1 >= s0) ? cpl(kp, kw[-1]) : -1;
+  int b = (p + 1 < s1) ? cpl(kp, kw[1]) : -1;
   for (int step = 0; step < B; ++step) {
     if (a >= b) {
       val = a;
       ++i;
-      a = (p - i >= 0 && i <= B) ? cpl(kp, kw[-i]) : -1;
+      a = (p - i >= s0 && i <= B) ? cpl(kp, kw[-i]) : -1;
     } else {
       val = b;
       ++j;
-      b = (p + j < m && j <= B) ? cpl(kp, kw[j]) : -1;
+      b = (p + j < s1 && j <= B) ? cpl(kp, kw[j]) : -1;
     }
   }
   int d = val + 1;
@@ -144,14 +191,18 @@ __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restri
 }
 
 __global__ void k_nodes(const uint64_t *__restrict__ keys, int64_t m,
+                        const int32_t *__restrict__ soff, int n_snap,
+                        const double4 *__restrict__ sbox,
                         const uint32_t *__restrict__ off, const uint8_t *__restrict__ lev,
-                        int64_t nnodes, float side, Node *__restrict__ nodes) {
+                        int64_t nnodes, Node *__restrict__ nodes) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
   const int delta = lev[2 * p], d = lev[2 * p + 1];
   if (d < delta) return;
   const uint64_t kp = keys[p];
-  int64_t end = m;  // members of the level-l node: [p, end)
+  const int sn = n_snap > 1 ? segment_of(soff, n_snap, p) : 0;
+  const float side = (float)sbox[sn].w;
+  int64_t end = soff[sn + 1];  // members of the level-l node: [p, end)
   for (int l = delta; l <= d; ++l) {
     // first q in (p, end] with cpl(p, q) < l (end shrinks as l grows)
     int64_t lo = p + 1, hi = end;  // answer in [lo, hi]
@@ -277,7 +328,11 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   o.n = m;
   o.nnodes = 0;
   o.max_level = 0;
-  if (m == 0) return G3_OK;
+  if (m == 0) {  // no members: every snapshot's node range is empty
+    const hipError_t e = fill_i32(o.nroot, 0, t->n_snap + 1, s);
+    if (e != hipSuccess) { c->err = "fill launch failed"; return G3_EHIP; }
+    return G3_OK;
+  }
   if (f64 && (!o.x64 || o.cap_x64 < m)) {
     if (o.x64) (void)hipFree(o.x64);
     o.x64 = nullptr;
@@ -321,13 +376,30 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   const int32_t *sel = nullptr;
   if (gas && m != t->n) sel = (const int32_t *)scratch(c, kFlags, 0);  // filled by caller
   if (f64)
-    k_keys<double><<<nblk(m), kBlock, 0, s>>>((const double *)pos, sel, m, t->box[0], t->box[1],
-                                              t->box[2], t->scale, o.keys, vals);
+    k_keys<double><<<nblk(m), kBlock, 0, s>>>((const double *)pos, sel, m, t->coff, t->sbox,
+                                              t->n_snap, o.keys, vals);
   else
-    k_keys<float><<<nblk(m), kBlock, 0, s>>>((const float *)pos, sel, m, t->box[0], t->box[1],
-                                             t->box[2], t->scale, o.keys, vals);
-  hipError_t e = radix_sort_pairs(o.keys, vals, kalt, valt, m, rtmp, s);
+    k_keys<float><<<nblk(m), kBlock, 0, s>>>((const float *)pos, sel, m, t->coff, t->sbox,
+                                             t->n_snap, o.keys, vals);
+  hipError_t e = radix_sort_pairs(o.keys, vals, kalt, valt, m, 64, rtmp, s);
   if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
+  if (t->n_snap > 1) {
+    // stable sort of the key-sorted members by snapshot: (snapshot, key) order
+    uint64_t *skey = (uint64_t *)scratch(c, kSnapKeys, 2 * m * sizeof(uint64_t));
+    uint64_t *skey_alt = (uint64_t *)scratch(c, kSnapKeysAlt, m * sizeof(uint64_t));
+    if (!skey || !skey_alt) { c->err = "device allocation of build scratch failed"; return G3_ENOMEM; }
+    uint32_t *sidx = (uint32_t *)(skey + m);
+    int bits = 8;
+    while (bits < 32 && (int64_t(1) << bits) < t->n_snap) bits += 8;
+    k_snap_keys<<<nblk(m), kBlock, 0, s>>>(vals, m, t->coff, t->n_snap, skey, sidx);
+    e = radix_sort_pairs(skey, sidx, skey_alt, cnt, m, bits, rtmp, s);
+    if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
+    k_gather_sorted<<<nblk(m), kBlock, 0, s>>>(sidx, m, o.keys, vals, kalt, valt);
+    e = hipMemcpyAsync(o.keys, kalt, m * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vals, valt, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) { c->err = "snapshot sort copy failed"; return G3_EHIP; }
+  }
   int32_t *iperm = gas ? t->iperm_gas : t->iperm_all;
   if (f64)
     k_permute<double><<<nblk(m), kBlock, 0, s>>>(vals, m, (const double *)pos, mass, o.xm, x64,
@@ -339,7 +411,8 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   if (e != hipSuccess) { c->err = "perm copy failed"; return G3_EHIP; }
   e = fill_i32(maxlev, 0, 1, s);
   if (e != hipSuccess) { c->err = "fill launch failed"; return G3_EHIP; }
-  k_node_counts<<<nblk(m), kBlock, 0, s>>>(o.keys, m, t->leaf, cnt, lev, maxlev);
+  k_node_counts<<<nblk(m), kBlock, 0, s>>>(o.keys, m, o.soff, t->n_snap, t->leaf, cnt, lev,
+                                           maxlev);
   e = scan_u32(cnt, off, m, stmp, s);
   if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
   int64_t *pin = c->pinned;
@@ -375,7 +448,9 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   }
   o.nnodes = nnodes;
   o.max_level = maxl;
-  k_nodes<<<nblk(m), kBlock, 0, s>>>(o.keys, m, off, lev, nnodes, (float)t->box[3], o.nodes);
+  k_nodes<<<nblk(m), kBlock, 0, s>>>(o.keys, m, o.soff, t->n_snap, t->sbox, off, lev, nnodes,
+                                     o.nodes);
+  k_nroot<<<nblk(t->n_snap + 1), kBlock, 0, s>>>(off, o.soff, t->n_snap, o.nroot);
   for (int l = maxl; l >= 0; --l)
     k_moments_level<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, o.mom, f64 ? o.c64 : nullptr,
                                                      nnodes, o.xm, x64, l);
@@ -391,10 +466,18 @@ hipError_t refit_hmax(Octree &o, hipStream_t s) {
 }
 
 // Gas member selection for the gas octree: ids of the gas particles in
-// caller order, written to the kFlags scratch slot; returns their number
-// (SYNCS to read it).
-int select_gas(g3_ctx *c, const uint8_t *type, int64_t n, int64_t *m_out, hipStream_t s) {
-  if (!type) { *m_out = n; return G3_OK; }
+// caller order, written to the kFlags scratch slot, and the sorted start of
+// each snapshot in the gas octree; returns their number (SYNCS to read it).
+// The all-particle octree's snapshot starts are the caller offsets.
+int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, hipStream_t s) {
+  const int64_t n = t->n;
+  const unsigned sb = nblk(t->n_snap + 1);
+  k_soff<<<sb, kBlock, 0, s>>>(t->coff, t->n_snap, nullptr, t->all.soff);
+  if (!type) {
+    k_soff<<<sb, kBlock, 0, s>>>(t->coff, t->n_snap, nullptr, t->gas.soff);
+    *m_out = n;
+    return G3_OK;
+  }
   uint32_t *flags = (uint32_t *)scratch(c, kCounts, (n + 1) * sizeof(uint32_t));
   uint32_t *slot = (uint32_t *)scratch(c, kOffsets, (n + 1) * sizeof(uint32_t));
   uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(n) * sizeof(uint32_t));
@@ -404,6 +487,7 @@ int select_gas(g3_ctx *c, const uint8_t *type, int64_t n, int64_t *m_out, hipStr
   hipError_t e = scan_u32(flags, slot, n, stmp, s);
   if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
   k_gas_compact<<<nblk(n), kBlock, 0, s>>>(flags, slot, n, ids);
+  k_soff<<<sb, kBlock, 0, s>>>(t->coff, t->n_snap, slot, t->gas.soff);
   e = hipMemcpyAsync(&c->pinned[2], slot + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { c->err = std::string("gas count readback: ") + hipGetErrorString(e); return G3_EHIP; }

@@ -10,22 +10,19 @@ namespace g3 {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWpb = kBlock / kWave;
 
 __global__ __launch_bounds__(kBlock) void k_walk_sph(
-    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
-    const float4 *__restrict__ vh, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ targets, const int32_t *__restrict__ rows,
-    const uint32_t *__restrict__ dcount, int64_t ntmax, int symmetric,
-    int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
-    int32_t *__restrict__ list) {
-  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
-  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
-  if (g0 >= ntarg) return;
-  const int64_t t = g0 + lane;
-  const bool valid = t < ntarg;
-  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const float4 *__restrict__ vh, const int32_t *__restrict__ perm, const Groups gs,
+    const int32_t *__restrict__ rows, int symmetric, int32_t *__restrict__ counts,
+    const int64_t *__restrict__ offsets, int32_t *__restrict__ list) {
+  const int lane = lane_id();
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+  const Group grp = group_at(gs, g);
+  const int64_t t = grp.t0 + lane;
+  const bool valid = lane < grp.count;
+  const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
   // rows follow `active`; with every particle active they are caller ids
   const int64_t row = valid ? (rows ? (int64_t)rows[t] : (int64_t)perm[s]) : 0;
   const float4 me = xm[s];
@@ -34,8 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_sph(
   const float h2 = valid ? sq_exact(hi) : -1.0f;
   int64_t pos = (list && valid) ? offsets[row] : 0;
   int cnt = 0;
-  int cur = 0;
-  while (cur < nnodes) {
+  int cur = grp.root;
+  while (cur < grp.end) {
     const Node nd = nodes[cur];
     const float d2 = box_dist2(xi, nd.lo_h, nd.hi_l);
     const bool want = valid && (symmetric ? d2 < sq_exact(fmaxf(hi, nd.lo_h.w)) : d2 < h2);
@@ -62,6 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_sph(
     cur = nd.meta.x;
   }
   if (valid && !list) counts[row] = cnt;
+  }  // groups
 }
 
 __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
@@ -72,19 +70,18 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_walk_grav(
-    const Node *__restrict__ nodes, int nnodes, const float4 *__restrict__ xm,
-    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ targets, const int32_t *__restrict__ rows,
-    const uint32_t *__restrict__ dcount, int64_t ntmax, float theta2, int inside_test,
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
+    const int32_t *__restrict__ rows, float theta2, int inside_test,
     int32_t *__restrict__ counts, const int64_t *__restrict__ offsets,
     int32_t *__restrict__ list) {
-  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
-  const int64_t ntarg = targets ? (int64_t)(*dcount) : ntmax;
-  const int64_t g0 = (xcd_block() * kWpb + w) * kWave;
-  if (g0 >= ntarg) return;
-  const int64_t t = g0 + lane;
-  const bool valid = t < ntarg;
-  const int s = valid ? (targets ? targets[t] : (int)t) : 0;
+  const int lane = lane_id();
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+  const Group grp = group_at(gs, g);
+  const int64_t t = grp.t0 + lane;
+  const bool valid = lane < grp.count;
+  const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
   // rows follow `active`; with every particle active they are caller ids
   const int64_t row = valid ? (rows ? (int64_t)rows[t] : (int64_t)perm[s]) : 0;
   const float4 me = xm[s];
@@ -92,9 +89,9 @@ __global__ __launch_bounds__(kBlock) void k_walk_grav(
   const uint64_t ki = keys[s];
   int64_t pos = (list && valid) ? offsets[row] : 0;
   int cnt = 0;
-  int resume = valid ? 0 : INT32_MAX;
-  int cur = 0;
-  while (cur < nnodes) {
+  int resume = valid ? grp.root : INT32_MAX;
+  int cur = grp.root;
+  while (cur < grp.end) {
     const Node nd = nodes[cur];
     const bool act = cur >= resume;
     const float r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
@@ -128,24 +125,22 @@ __global__ __launch_bounds__(kBlock) void k_walk_grav(
     cur = nd.meta.x;
   }
   if (valid && !list) counts[row] = cnt;
+  }  // groups
 }
 
 }  // namespace
 
-hipError_t launch_walk(const Octree &o, int kind, const int32_t *targets, const int32_t *rows,
-                       const uint32_t *dcount, int64_t max_targets,
-                       const GravParams &gp, int32_t *counts, const int64_t *offsets,
-                       int32_t *list, hipStream_t s) {
-  if (max_targets <= 0 || o.nnodes == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((max_targets + kBlock - 1) / kBlock);
+hipError_t launch_walk(const Octree &o, int kind, const Groups &gs, const int32_t *rows,
+                       int64_t max_groups, const GravParams &gp, int32_t *counts,
+                       const int64_t *offsets, int32_t *list, hipStream_t s) {
+  if (max_groups <= 0 || o.nnodes == 0) return hipSuccess;
   if (kind == G3_GRAVITY)
-    k_walk_grav<<<blocks, kBlock, 0, s>>>(o.nodes, (int)o.nnodes, o.xm, o.keys, o.perm, targets,
-                                          rows, dcount, max_targets, gp.theta2, gp.inside_test,
-                                          counts, offsets, list);
+    k_walk_grav<<<persistent_grid((const void *)k_walk_grav, kBlock, max_groups), kBlock, 0, s>>>(
+        o.nodes, o.xm, o.keys, o.perm, gs, rows, gp.theta2, gp.inside_test, counts, offsets,
+        list);
   else
-    k_walk_sph<<<blocks, kBlock, 0, s>>>(o.nodes, (int)o.nnodes, o.xm, o.vh, o.perm, targets,
-                                         rows, dcount, max_targets, kind == G3_SYMMETRIC,
-                                         counts, offsets, list);
+    k_walk_sph<<<persistent_grid((const void *)k_walk_sph, kBlock, max_groups), kBlock, 0, s>>>(
+        o.nodes, o.xm, o.vh, o.perm, gs, rows, kind == G3_SYMMETRIC, counts, offsets, list);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
 
 # every symbol include/g3.h declares
 EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
-           "g3_build_tree", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
+           "g3_build_tree", "g3_build_forest", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity")
 
 
@@ -65,6 +65,7 @@ def lib():
             "g3_last_error": ([P], ctypes.c_char_p),
             "g3_ctx_stats": ([P, P, i32], ctypes.c_int),
             "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_build_forest": ([P, i32, P, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_tree_destroy": ([P, P], None),
             "g3_tree_info": ([P, i32, P, P], ctypes.c_int),
             "g3_tree_export": ([P, P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -117,6 +118,23 @@ def g3_build_tree(ctx, n, pos_t, pos, mass, type_, box, params, tree, stream) ->
     st = lib().g3_build_tree(ctx, int(n), int(pos_t), pos, mass, type_ or None, b,
                              ctypes.byref(params), ctypes.byref(h), stream)
     _check(ctx, st, "g3_build_tree")
+    return h.value
+
+
+def g3_build_forest(ctx, snap_off, pos_t, pos, mass, type_, boxes, params, tree, stream) -> int:
+    """snap_off: n_snap + 1 host ints; boxes: n_snap x 4 host doubles; tree:
+    existing handle or 0. Returns the handle."""
+    off = [int(x) for x in snap_off]
+    ns = len(off) - 1
+    flat = [float(x) for b in boxes for x in b]
+    if ns < 1 or len(flat) != 4 * ns:
+        raise ValueError("need n_snap >= 1 offsets + 1 and n_snap boxes of 4")
+    o = (ctypes.c_int64 * (ns + 1))(*off)
+    b = (ctypes.c_double * (4 * ns))(*flat)
+    h = ctypes.c_void_p(tree or None)
+    st = lib().g3_build_forest(ctx, ns, o, int(pos_t), pos, mass, type_ or None, b,
+                               ctypes.byref(params), ctypes.byref(h), stream)
+    _check(ctx, st, "g3_build_forest")
     return h.value
 
 

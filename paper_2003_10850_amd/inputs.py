@@ -21,6 +21,11 @@ Workloads (all in a unit box, non-periodic, G = 1, equal masses 1/N):
   over one decade, centres uniform in [0.1, 0.9]^3) and 20 % uniform,
   Gaussian velocities sigma = 0.1, u = 1; 295 target neighbours,
   eps = 1e-3 (the 2^21-particle paper-like case).
+* ``batch``     - a forest of independent ``plummer`` snapshots with sizes
+  log-uniform in [1e3, 1e6], each with the active set of one step of a
+  hierarchical (power-of-two) time-step scheme: the fraction 2^-K of its
+  particles with the shortest time steps (the densest, as free-fall times
+  go), K = round(-log2 f) for f log-uniform in [1e-3, 1].
 """
 from __future__ import annotations
 
@@ -73,7 +78,7 @@ def uniform(n: int = 4096, seed: int = 0) -> Workload:
     pos = rng.random((n, 3))
     return Workload(
         name=f"uniform_n{n}_seed{seed}", pos=pos, vel=np.zeros((n, 3)),
-        mass=np.full(n, 1.0 / n), u=np.ones(n),
+        mass=np.full(n, 1.0 / max(n, 1)), u=np.ones(n),
         type=np.zeros(n, np.uint8), box=np.array([0.0, 0.0, 0.0, 1.0]),
         params=Params(n_ngb=64.0, eps=0.01), seed=seed)
 
@@ -135,6 +140,73 @@ def plummer(n: int = 1 << 21, n_spheres: int = 32, seed: int = 1,
         params=Params(n_ngb=n_ngb, eps=eps), seed=seed)
     w.model = dict(centres=centres, counts=counts, a=scale_radius, n_bg=n_bg)
     return w
+
+
+@dataclass
+class Batch:
+    """Snapshots concatenated in caller order: snapshot k is the rows
+    [snap_off[k], snap_off[k+1]) of every array, in its own box boxes[k]."""
+    name: str
+    snaps: list
+    pos: np.ndarray
+    vel: np.ndarray
+    mass: np.ndarray
+    u: np.ndarray
+    type: np.ndarray
+    snap_off: np.ndarray       # [S+1] int64
+    boxes: np.ndarray          # [S,4]
+    active: np.ndarray         # int32 caller ids over the whole forest
+    level: np.ndarray          # [S] time-bin level K: active fraction 2^-K
+    params: Params = field(default_factory=Params)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_snap(self) -> int:
+        return len(self.snaps)
+
+
+def timestep_active(w: Workload, level: int) -> np.ndarray:
+    """Active set of a hierarchical time-step scheme at a step where the
+    bins of time step dt_max 2^-K and shorter are due: the fraction 2^-K
+    of the particles with the highest model density (shortest free-fall
+    time), as sorted caller ids."""
+    k = max(1, int(np.ceil(w.n * 2.0 ** -level))) if w.n else 0
+    rank = np.argsort(-model_gas_density(w), kind="stable")
+    return np.sort(rank[:k]).astype(np.int32)
+
+
+def batch(n_snap: int = 64, n_min: float = 1e3, n_max: float = 1e6, seed: int = 2,
+          f_min: float = 1e-3, n_spheres: int = 32, n_ngb: float = 295.0,
+          eps: float = 1e-3, shift_boxes: bool = False) -> Batch:
+    """Forest workload: n_snap Plummer snapshots (as ``plummer``) with sizes
+    log-uniform in [n_min, n_max] and time-bin active sets. With shift_boxes
+    snapshot k lives in the unit box at (k, 0, 0) instead of the origin."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(10.0 ** rng.uniform(np.log10(n_min), np.log10(n_max), n_snap)).astype(np.int64)
+    frac = 10.0 ** rng.uniform(np.log10(f_min), 0.0, n_snap)
+    level = np.clip(np.rint(-np.log2(frac)), 0, None).astype(np.int64)
+    snaps, act, boxes = [], [], []
+    off = [0]
+    for k in range(n_snap):
+        w = plummer(n=int(sizes[k]), n_spheres=n_spheres, seed=seed * 1000 + k, n_ngb=n_ngb,
+                    eps=eps)
+        if shift_boxes:
+            w.pos = w.pos + np.array([float(k), 0.0, 0.0])
+            w.box = np.array([float(k), 0.0, 0.0, 1.0])
+            w.model["centres"] = w.model["centres"] + np.array([float(k), 0.0, 0.0])
+        snaps.append(w)
+        act.append(timestep_active(w, int(level[k])) + off[-1])
+        boxes.append(w.box)
+        off.append(off[-1] + w.n)
+    cat = lambda f: np.concatenate([getattr(w, f) for w in snaps])
+    return Batch(name=f"batch_s{n_snap}_seed{seed}", snaps=snaps, pos=cat("pos"), vel=cat("vel"),
+                 mass=cat("mass"), u=cat("u"), type=cat("type"),
+                 snap_off=np.array(off, np.int64), boxes=np.array(boxes),
+                 active=np.concatenate(act).astype(np.int32), level=level,
+                 params=Params(n_ngb=n_ngb, eps=eps))
 
 
 def model_gas_density(w: Workload) -> np.ndarray:

@@ -58,16 +58,18 @@ class Context:
 
 
 class Tree:
-    """The octrees of one particle set (all particles, and the gas ones)."""
+    """The octrees of one particle set (all particles, and the gas ones), or
+    of a forest of snapshots: ``snap_off`` (n_snap + 1 offsets into the
+    particle arrays) with one box per snapshot in ``box``."""
 
     def __init__(self, ctx: Context, pos, mass, type=None, box=(0.0, 0.0, 0.0, 1.0),
-                 params=None):
+                 params=None, snap_off=None):
         self.ctx = ctx
         self.handle = 0
         self.params = params
-        self.build(pos, mass, type, box)
+        self.build(pos, mass, type, box, snap_off)
 
-    def build(self, pos, mass, type=None, box=None):
+    def build(self, pos, mass, type=None, box=None, snap_off=None):
         """pos float32 (plain path) or float64 (mixed-precision path)."""
         dev = self.ctx.device
         n = int(pos.shape[0])
@@ -78,13 +80,18 @@ class Tree:
         if type is not None:
             _need(type, torch.uint8, (n,), "type", dev)
         if box is not None:
-            self.box = tuple(float(b) for b in box)
+            b = [[float(x) for x in row] for row in box] if snap_off is not None \
+                else [[float(x) for x in box]]
+            self.box = b
+        self.snap_off = [0, n] if snap_off is None else [int(x) for x in snap_off]
+        if self.snap_off[-1] != n:
+            raise ValueError("snap_off must end at the particle count")
         self.n = n
         self.hdtype = pos.dtype  # the SPH calls' h follows the positions
         pt = g3.G3_F64 if pos.dtype == torch.float64 else g3.G3_F32
-        self.handle = g3.g3_build_tree(self.ctx.handle, n, pt, _ptr(pos), _ptr(mass),
-                                       _ptr(type), self.box, g3.g3_params.of(self.params),
-                                       self.handle, _stream(dev))
+        self.handle = g3.g3_build_forest(self.ctx.handle, self.snap_off, pt, _ptr(pos),
+                                         _ptr(mass), _ptr(type), self.box,
+                                         g3.g3_params.of(self.params), self.handle, _stream(dev))
         return self
 
     def info(self, which: int):
@@ -122,11 +129,17 @@ def _zeros(tree, *shape, dtype=torch.float32):
 
 
 def density(tree: Tree, params=None, h=None, active=None, solve_h: bool = True, out=None):
-    """SPH density of the active gas particles; returns a dict of tensors."""
+    """SPH density of the active gas particles; returns a dict of tensors.
+
+    h: first guess (solve_h) or the given h, copied; out["h"] instead is
+    used in place (its values are the guess or the given h)."""
     p = g3.g3_params.of(params or tree.params)
     n = tree.n
     o = out or {}
-    hh = h.clone() if h is not None else _zeros(tree, n, dtype=tree.hdtype)
+    if "h" in o:
+        hh = o["h"]
+    else:
+        hh = h.clone() if h is not None else _zeros(tree, n, dtype=tree.hdtype)
     _need(hh, tree.hdtype, (n,), "h", tree.ctx.device)
     res = dict(h=hh, rho=o.get("rho", _zeros(tree, n)), drho_dh=o.get("drho_dh", _zeros(tree, n)),
                omega=o.get("omega", _zeros(tree, n)),
