@@ -85,6 +85,12 @@ def lib():
         L.g3ref_gravity.restype = ctypes.c_int
         L.g3ref_lists.argtypes = [P, i32, i64, P, P, P, P, P]
         L.g3ref_lists.restype = ctypes.c_int
+        L.g3ref_density_backward.argtypes = [P, i64, P, P] + [P] * 7
+        L.g3ref_density_backward.restype = ctypes.c_int
+        L.g3ref_hydro_backward.argtypes = [P, i64, P, P] + [P] * 14
+        L.g3ref_hydro_backward.restype = ctypes.c_int
+        L.g3ref_gravity_backward.argtypes = [P, i64, P, P] + [P] * 4
+        L.g3ref_gravity_backward.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -221,3 +227,58 @@ def lists(tree: Tree, params, kind: int, active=None, h=None):
     lib().g3ref_lists(tree._h, int(kind), act.size, _ptr(act), ctypes.byref(p),
                       _ptr(hh), _ptr(off), _ptr(lst))
     return off, lst
+
+
+def _opt(a, shape=None):
+    return None if a is None else _f64(a, shape)
+
+
+def density_backward(tree: Tree, params, h, g_rho=None, g_drho_dh=None, g_omega=None,
+                     active=None) -> dict:
+    """Gradients (pos [n,3], mass [n], h [n]) of sum_i g_rho_i rho_i +
+    g_drho_dh_i drho_i/dh + g_omega_i Omega_i over the active gas i."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(pos=np.zeros((n, 3)), mass=np.zeros(n), h=np.zeros(n))
+    ins = [_f64(h), _opt(g_rho), _opt(g_drho_dh), _opt(g_omega)]
+    st = lib().g3ref_density_backward(tree._h, act.size, _ptr(act),
+                                      ctypes.byref(Params.of(params)),
+                                      *[_ptr(a) for a in ins],
+                                      *[_ptr(out[k]) for k in ("pos", "mass", "h")])
+    if st != OK:
+        raise ValueError(f"g3ref_density_backward status {st}")
+    return out
+
+
+def hydro_backward(tree: Tree, params, vel, u, h, rho, omega, g_acc=None, g_dudt=None,
+                   active=None) -> dict:
+    """Gradients (pos, vel, mass, h, u, rho, omega) of
+    sum_i g_acc_i . a_i + g_dudt_i du_i/dt over the active gas i."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(pos=np.zeros((n, 3)), vel=np.zeros((n, 3)), mass=np.zeros(n), h=np.zeros(n),
+               u=np.zeros(n), rho=np.zeros(n), omega=np.zeros(n))
+    ins = [_f64(vel, (-1, 3)), _f64(u), _f64(h), _f64(rho), _f64(omega),
+           _opt(g_acc, (-1, 3)), _opt(g_dudt)]
+    st = lib().g3ref_hydro_backward(tree._h, act.size, _ptr(act),
+                                    ctypes.byref(Params.of(params)), *[_ptr(a) for a in ins],
+                                    *[_ptr(out[k]) for k in
+                                      ("pos", "vel", "mass", "h", "u", "rho", "omega")])
+    if st != OK:
+        raise ValueError(f"g3ref_hydro_backward status {st}")
+    return out
+
+
+def gravity_backward(tree: Tree, params, g_acc=None, g_pot=None, active=None) -> dict:
+    """Gradients (pos [n,3], mass [n]) of sum_i g_acc_i . a_i + g_pot_i phi_i
+    over the active i (Barnes-Hut decisions fixed)."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(pos=np.zeros((n, 3)), mass=np.zeros(n))
+    st = lib().g3ref_gravity_backward(tree._h, act.size, _ptr(act),
+                                      ctypes.byref(Params.of(params)),
+                                      _ptr(_opt(g_acc, (-1, 3))), _ptr(_opt(g_pot)),
+                                      _ptr(out["pos"]), _ptr(out["mass"]))
+    if st != OK:
+        raise ValueError(f"g3ref_gravity_backward status {st}")
+    return out

@@ -638,3 +638,394 @@ int g3ref_lists(const g3ref_tree *tp, int32_t kind, int64_t n_act, const int64_t
 }
 
 } // extern "C"
+
+/* ================================================================ adjoints
+ *
+ * Gradients of the three modules with respect to their inputs, for a
+ * scalar loss whose derivatives with respect to the module outputs (the
+ * upstream gradients) are given at the active rows. Neighbour sets and
+ * Barnes-Hut decisions are held fixed (the forward is piecewise smooth in
+ * them), h is an input (no derivative through its solve), and the results
+ * are ADDED to the caller's gradient arrays.
+ *
+ * Every derivative below is taken mechanically: each pair's (or term's)
+ * contribution is evaluated once more in forward-mode dual numbers seeded
+ * on that pair's input variables, so the partials are those of the forward
+ * formula as written, with no hand-derived expression. Only the two plain
+ * chain rules that tie pairs to particle data are written out: a node
+ * monopole's dependence on its members (M = sum m, c = sum m x / M) and the
+ * sum over pairs.
+ */
+
+namespace {
+
+/* value and K partial derivatives */
+template <int K>
+struct Dual {
+  double v;
+  double d[K];
+  Dual() : v(0.0) { std::fill(d, d + K, 0.0); }
+  Dual(double x) : v(x) { std::fill(d, d + K, 0.0); }  // NOLINT: constants
+  static Dual var(double x, int k) {
+    Dual r(x);
+    r.d[k] = 1.0;
+    return r;
+  }
+};
+
+template <int K> Dual<K> operator+(const Dual<K> &a, const Dual<K> &b) {
+  Dual<K> r(a.v + b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int K> Dual<K> operator-(const Dual<K> &a, const Dual<K> &b) {
+  Dual<K> r(a.v - b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int K> Dual<K> operator-(const Dual<K> &a) {
+  Dual<K> r(-a.v);
+  for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int K> Dual<K> operator*(const Dual<K> &a, const Dual<K> &b) {
+  Dual<K> r(a.v * b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int K> Dual<K> operator/(const Dual<K> &a, const Dual<K> &b) {
+  Dual<K> r(a.v / b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+template <int K> Dual<K> operator+(const Dual<K> &a, double b) { return a + Dual<K>(b); }
+template <int K> Dual<K> operator+(double a, const Dual<K> &b) { return Dual<K>(a) + b; }
+template <int K> Dual<K> operator-(const Dual<K> &a, double b) { return a - Dual<K>(b); }
+template <int K> Dual<K> operator-(double a, const Dual<K> &b) { return Dual<K>(a) - b; }
+template <int K> Dual<K> operator*(const Dual<K> &a, double b) { return a * Dual<K>(b); }
+template <int K> Dual<K> operator*(double a, const Dual<K> &b) { return Dual<K>(a) * b; }
+template <int K> Dual<K> operator/(const Dual<K> &a, double b) { return a / Dual<K>(b); }
+template <int K> Dual<K> operator/(double a, const Dual<K> &b) { return Dual<K>(a) / b; }
+template <int K> Dual<K> sqrt(const Dual<K> &a) {
+  const double s = std::sqrt(a.v);
+  Dual<K> r(s);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] / (2.0 * s);
+  return r;
+}
+
+/* Wendland C6 value, dW/dh and F = (1/r) dW/dr at q = r/h < 1 (the forward
+ * formulas of wc6), on any scalar type; zero at and beyond the support. */
+template <class T>
+void wc6_t(const T &r, const T &h, T *W, T *Wh, T *F) {
+  const T q = r / h;
+  if (!(q.v < 1.0)) {
+    *W = T(0.0);
+    *Wh = T(0.0);
+    *F = T(0.0);
+    return;
+  }
+  const T t = 1.0 - q;
+  const T t2 = t * t, t4 = t2 * t2, t7 = t4 * t2 * t, t8 = t7 * t;
+  const T h3 = h * h * h, h4 = h3 * h, h5 = h4 * h;
+  const T p8 = 1.0 + q * (8.0 + q * (25.0 + q * 32.0));
+  const T p7 = 1.0 + q * (7.0 + q * 16.0);
+  const T ph = -3.0 + q * (-21.0 + q * (-29.0 + q * (133.0 + q * 448.0)));
+  *W = kWc6 / h3 * t8 * p8;
+  *Wh = kWc6 / h4 * t7 * ph;
+  *F = -22.0 * kWc6 / h5 * t7 * p7;
+}
+
+/* |x_i - x_j| in duals; a pair at zero separation has r = 0 with no
+ * position derivative (the kernel is even in r, so dW/dx vanishes there) */
+template <int K>
+Dual<K> separation(const Dual<K> *xi, const Dual<K> *xj) {
+  const Dual<K> dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
+  const Dual<K> r2 = dx * dx + dy * dy + dz * dz;
+  if (!(r2.v > 0.0)) return Dual<K>(0.0);
+  return sqrt(r2);
+}
+
+/* Per-thread gradient buffers, summed in thread order at the end. */
+struct GradBuf {
+  std::vector<std::vector<double>> b;
+  GradBuf(int nt, size_t len) : b((size_t)nt, std::vector<double>(len, 0.0)) {}
+  std::vector<double> &mine() {
+#ifdef _OPENMP
+    return b[(size_t)omp_get_thread_num()];
+#else
+    return b[0];
+#endif
+  }
+  void add_to(double *out, size_t len) const {
+    if (!out) return;
+    for (const auto &v : b)
+      for (size_t i = 0; i < len; ++i) out[i] += v[i];
+  }
+};
+
+int nthreads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Density adjoint. Loss L = sum_i (g_rho_i rho_i + g_drho_i drho_i/dh +
+ * g_omega_i Omega_i) over the active gas i; rho, drho/dh and Omega as in
+ * g3ref_density at the given h. Adds dL/dx, dL/dm, dL/dh to g_pos [n][3],
+ * g_mass [n], g_h [n] (each nullable). */
+int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                           const g3ref_params *p, const double *h, const double *g_rho,
+                           const double *g_drho, const double *g_omega, double *g_pos,
+                           double *g_mass, double *g_h) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !h) return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+  const size_t n = (size_t)t.n;
+  const int nt = nthreads();
+  GradBuf gx(nt, 3 * n), gm(nt, n), gh(nt, n);
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    const double hi = h[i];
+    std::vector<int64_t> nb;
+    walk_leaves(t, 0, &t.pos[3 * i], [&](int64_t) { return hi * kPruneMargin; }, [&](int64_t j) {
+      if (is_gas(t, j) && within(t, i, j, hi, p->flags)) nb.push_back(j);
+    });
+    // the outputs at the given h
+    double rho = 0.0, drho = 0.0;
+    for (int64_t j : nb) {
+      double W, dWdr, Wh, F;
+      wc6(dist(t, i, j), hi, &W, &dWdr, &Wh, &F);
+      rho += t.mass[j] * W;
+      drho += t.mass[j] * Wh;
+    }
+    // Omega = 1 + h drho / (3 rho): partials by duals in (rho, drho, h)
+    using D3 = Dual<3>;
+    const D3 R = D3::var(rho, 0), Rp = D3::var(drho, 1), Hh = D3::var(hi, 2);
+    const D3 Om = 1.0 + Hh * Rp / (3.0 * R);
+    const double go = g_omega ? g_omega[i] : 0.0;
+    const double grho = (g_rho ? g_rho[i] : 0.0) + go * Om.d[0];
+    const double gdrho = (g_drho ? g_drho[i] : 0.0) + go * Om.d[1];
+    std::vector<double> &GX = gx.mine(), &GM = gm.mine(), &GH = gh.mine();
+    GH[i] += go * Om.d[2];
+    // each pair: (m_j W(r, h_i), m_j dW/dh(r, h_i)) in duals over
+    // x_i (0-2), x_j (3-5), m_j (6), h_i (7)
+    using D8 = Dual<8>;
+    for (int64_t j : nb) {
+      D8 xi[3], xj[3];
+      for (int c = 0; c < 3; ++c) {
+        xi[c] = D8::var(t.pos[3 * i + c], c);
+        xj[c] = D8::var(t.pos[3 * j + c], 3 + c);
+      }
+      const D8 mj = D8::var(t.mass[j], 6), H = D8::var(hi, 7);
+      D8 W, Wh, F;
+      wc6_t(separation(xi, xj), H, &W, &Wh, &F);
+      const D8 cr = mj * W, cd = mj * Wh;
+      for (int c = 0; c < 3; ++c) {
+        GX[3 * i + c] += grho * cr.d[c] + gdrho * cd.d[c];
+        GX[3 * j + c] += grho * cr.d[3 + c] + gdrho * cd.d[3 + c];
+      }
+      GM[j] += grho * cr.d[6] + gdrho * cd.d[6];
+      GH[i] += grho * cr.d[7] + gdrho * cd.d[7];
+    }
+  }
+  gx.add_to(g_pos, 3 * n);
+  gm.add_to(g_mass, n);
+  gh.add_to(g_h, n);
+  return G3REF_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+/* Hydro adjoint. Loss L = sum_i (g_acc_i . a_i + g_dudt_i du_i/dt) over the
+ * active gas i, with a and du/dt as in g3ref_hydro (the signal velocity is
+ * not differentiated). Adds the derivatives with respect to positions,
+ * velocities, masses, h, u, rho and Omega of every gas particle to the
+ * caller's arrays (each nullable). */
+int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                         const g3ref_params *p, const double *vel, const double *u,
+                         const double *h, const double *rho, const double *omega,
+                         const double *g_acc, const double *g_dudt, double *g_pos,
+                         double *g_vel, double *g_mass, double *g_h, double *g_u,
+                         double *g_rho, double *g_omega) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !vel || !u || !h ||
+      !rho || !omega)
+    return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+  const size_t n = (size_t)t.n;
+  const double gm = p->gamma, alpha = p->alpha;
+  std::vector<double> hmax(t.nodes.size(), 0.0);
+  for (size_t k = 0; k < t.nodes.size(); ++k)
+    for (int64_t s = t.nodes[k].start; s < t.nodes[k].start + t.nodes[k].count; ++s)
+      hmax[k] = std::max(hmax[k], h[t.order[s]]);
+  const int nt = nthreads();
+  GradBuf gx(nt, 3 * n), gv(nt, 3 * n), gms(nt, n), gh(nt, n), gu(nt, n), gr(nt, n), go(nt, n);
+  /* duals over the pair's inputs:
+   *  0-2 x_i, 3-5 x_j, 6-8 v_i, 9-11 v_j, 12 m_j, 13 h_i, 14 h_j,
+   *  15 u_i, 16 u_j, 17 rho_i, 18 rho_j, 19 Omega_i, 20 Omega_j */
+  using D = Dual<21>;
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    const double ga[3] = {g_acc ? g_acc[3 * i] : 0.0, g_acc ? g_acc[3 * i + 1] : 0.0,
+                          g_acc ? g_acc[3 * i + 2] : 0.0};
+    const double gd = g_dudt ? g_dudt[i] : 0.0;
+    if (ga[0] == 0.0 && ga[1] == 0.0 && ga[2] == 0.0 && gd == 0.0) continue;
+    const double hi = h[i];
+    std::vector<int64_t> nb;
+    walk_leaves(t, 0, &t.pos[3 * i], [&](int64_t k) { return std::max(hi, hmax[k]) * kPruneMargin; },
+                [&](int64_t j) {
+      if (j != i && is_gas(t, j) && within(t, i, j, std::max(hi, h[j]), p->flags)) nb.push_back(j);
+    });
+    std::vector<double> &GX = gx.mine(), &GV = gv.mine(), &GM = gms.mine(), &GH = gh.mine(),
+                        &GU = gu.mine(), &GR = gr.mine(), &GO = go.mine();
+    for (int64_t j : nb) {
+      D xi[3], xj[3], vi[3], vj[3];
+      for (int c = 0; c < 3; ++c) {
+        xi[c] = D::var(t.pos[3 * i + c], c);
+        xj[c] = D::var(t.pos[3 * j + c], 3 + c);
+        vi[c] = D::var(vel[3 * i + c], 6 + c);
+        vj[c] = D::var(vel[3 * j + c], 9 + c);
+      }
+      const D mj = D::var(t.mass[j], 12), Hi = D::var(hi, 13), Hj = D::var(h[j], 14);
+      const D ui = D::var(u[i], 15), uj = D::var(u[j], 16);
+      const D ri = D::var(rho[i], 17), rj = D::var(rho[j], 18);
+      const D oi = D::var(omega[i], 19), oj = D::var(omega[j], 20);
+      const D r = separation(xi, xj);
+      if (!(r.v > 0.0)) continue;  // pairs at zero separation add nothing
+      const D x[3] = {xi[0] - xj[0], xi[1] - xj[1], xi[2] - xj[2]};
+      const D v[3] = {vi[0] - vj[0], vi[1] - vj[1], vi[2] - vj[2]};
+      // the forward formulas of g3ref_hydro
+      const D Ai = (gm - 1.0) * ri * ui / (oi * ri * ri);
+      const D Aj = (gm - 1.0) * rj * uj / (oj * rj * rj);
+      const D ci = sqrt(gm * (gm - 1.0) * ui), cj = sqrt(gm * (gm - 1.0) * uj);
+      D W, Wh, gi, gj;
+      wc6_t(r, Hi, &W, &Wh, &gi);
+      wc6_t(r, Hj, &W, &Wh, &gj);
+      const D vx = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
+      const D w = vx / r;
+      D Pi(0.0);
+      if (w.v < 0.0) {
+        const D vsig = ci + cj - 3.0 * w;
+        Pi = -0.5 * alpha * vsig * w / (0.5 * (ri + rj));
+      }
+      const D gbar = 0.5 * (gi + gj);
+      const D tp = -mj * (Ai * gi + Aj * gj);
+      const D tv = -mj * Pi * gbar;
+      const D coef = tp + tv;
+      const D du = mj * Ai * gi * vx + 0.5 * mj * Pi * gbar * vx;
+      // dL/dvar = sum_c ga_c d(coef x_c)/dvar + gd d(du)/dvar
+      D L = gd * du;
+      for (int c = 0; c < 3; ++c) L = L + ga[c] * (coef * x[c]);
+      for (int c = 0; c < 3; ++c) {
+        GX[3 * i + c] += L.d[c];
+        GX[3 * j + c] += L.d[3 + c];
+        GV[3 * i + c] += L.d[6 + c];
+        GV[3 * j + c] += L.d[9 + c];
+      }
+      GM[j] += L.d[12];
+      GH[i] += L.d[13];
+      GH[j] += L.d[14];
+      GU[i] += L.d[15];
+      GU[j] += L.d[16];
+      GR[i] += L.d[17];
+      GR[j] += L.d[18];
+      GO[i] += L.d[19];
+      GO[j] += L.d[20];
+    }
+  }
+  gx.add_to(g_pos, 3 * n);
+  gv.add_to(g_vel, 3 * n);
+  gms.add_to(g_mass, n);
+  gh.add_to(g_h, n);
+  gu.add_to(g_u, n);
+  gr.add_to(g_rho, n);
+  go.add_to(g_omega, n);
+  return G3REF_OK;
+}
+
+/* Gravity adjoint. Loss L = sum_i (g_acc_i . a_i + g_pot_i phi_i) over the
+ * active i, with a and phi as in g3ref_gravity (opening decisions fixed).
+ * A particle term depends on x_i, x_j and m_j; an accepted node's monopole
+ * term on x_i and the node's M and c, which depend on its members through
+ * M = sum_k m_k and c = sum_k m_k x_k / M:
+ *   dc/dx_k = (m_k / M) I,  dc/dm_k = (x_k - c) / M,  dM/dm_k = 1.
+ * Adds dL/dx and dL/dm to g_pos [n][3] and g_mass [n] (each nullable). */
+int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *active,
+                           const g3ref_params *p, const double *g_acc, const double *g_pot,
+                           double *g_pos, double *g_mass) {
+  if (!all || !valid_params(p) || n_act < 0 || (n_act > 0 && !active)) return G3REF_EINVAL;
+  const g3ref_tree &t = *all;
+  const size_t n = (size_t)t.n, nn = t.nodes.size();
+  const double e2 = p->eps * p->eps, G = p->G;
+  const int nt = nthreads();
+  // per node: dL/dc (3) and dL/dM
+  GradBuf gx(nt, 3 * n), gms(nt, n), gc(nt, 3 * nn), gM(nt, nn);
+  /* duals: 0-2 x_i, 3-5 source position, 6 source mass */
+  using D = Dual<7>;
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || t.nodes.empty()) continue;
+    const double ga[3] = {g_acc ? g_acc[3 * i] : 0.0, g_acc ? g_acc[3 * i + 1] : 0.0,
+                          g_acc ? g_acc[3 * i + 2] : 0.0};
+    const double gp = g_pot ? g_pot[i] : 0.0;
+    std::vector<double> &GX = gx.mine(), &GM = gms.mine(), &GC = gc.mine(), &GMn = gM.mine();
+    bh_walk(t, 0, i, p->theta, p->flags, [&](double m, const double *c, int64_t id) {
+      D xi[3], xs[3];
+      for (int k = 0; k < 3; ++k) {
+        xi[k] = D::var(t.pos[3 * i + k], k);
+        xs[k] = D::var(c[k], 3 + k);
+      }
+      const D ms = D::var(m, 6);
+      // the forward formulas of g3ref_gravity
+      const D x[3] = {xi[0] - xs[0], xi[1] - xs[1], xi[2] - xs[2]};
+      const D r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      const D inv = 1.0 / sqrt(r2 + e2);
+      const D inv3 = inv * inv * inv;
+      D L = gp * (-G * ms * inv);
+      for (int k = 0; k < 3; ++k) L = L + ga[k] * (-G * ms * x[k] * inv3);
+      for (int k = 0; k < 3; ++k) GX[3 * i + k] += L.d[k];
+      if (id >= 0) {
+        for (int k = 0; k < 3; ++k) GX[3 * id + k] += L.d[3 + k];
+        GM[id] += L.d[6];
+      } else {
+        const int64_t nd = -id - 1;
+        for (int k = 0; k < 3; ++k) GC[3 * nd + k] += L.d[3 + k];
+        GMn[nd] += L.d[6];
+      }
+    });
+  }
+  gx.add_to(g_pos, 3 * n);
+  gms.add_to(g_mass, n);
+  // node adjoints to their members
+  std::vector<double> GCt(3 * nn, 0.0), GMt(nn, 0.0);
+  gc.add_to(GCt.data(), 3 * nn);
+  gM.add_to(GMt.data(), nn);
+  for (size_t k = 0; k < nn; ++k) {
+    const RefNode &nd = t.nodes[k];
+    if (GCt[3 * k] == 0.0 && GCt[3 * k + 1] == 0.0 && GCt[3 * k + 2] == 0.0 && GMt[k] == 0.0)
+      continue;
+    for (int64_t s = nd.start; s < nd.start + nd.count; ++s) {
+      const int64_t j = t.order[s];
+      double dot = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        if (g_pos) g_pos[3 * j + c] += GCt[3 * k + c] * t.mass[j] / nd.M;
+        dot += GCt[3 * k + c] * (t.pos[3 * j + c] - nd.com[c]);
+      }
+      if (g_mass) g_mass[j] += GMt[k] + dot / nd.M;
+    }
+  }
+  return G3REF_OK;
+}
+
+}  // extern "C"

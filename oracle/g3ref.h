@@ -107,6 +107,26 @@ int g3ref_lists(const g3ref_tree *t, int32_t kind, int64_t n_act,
                 const int64_t *active, const g3ref_params *p, const double *h,
                 int64_t *offsets, int64_t *list);
 
+/* Adjoints (gradients) of the three modules for a scalar loss whose
+ * derivatives with respect to the outputs are given at the active rows;
+ * neighbour sets and Barnes-Hut decisions held fixed, h an input. Results
+ * are ADDED to the [n] (or [n][3]) gradient arrays; every pointer argument
+ * named g_* is nullable. Partials come from forward-mode dual numbers over
+ * each pair's or term's inputs. */
+int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                           const g3ref_params *p, const double *h, const double *g_rho,
+                           const double *g_drho, const double *g_omega, double *g_pos,
+                           double *g_mass, double *g_h);
+int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                         const g3ref_params *p, const double *vel, const double *u,
+                         const double *h, const double *rho, const double *omega,
+                         const double *g_acc, const double *g_dudt, double *g_pos,
+                         double *g_vel, double *g_mass, double *g_h, double *g_u,
+                         double *g_rho, double *g_omega);
+int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *active,
+                           const g3ref_params *p, const double *g_acc, const double *g_pot,
+                           double *g_pos, double *g_mass);
+
 #ifdef __cplusplus
 }
 #endif
