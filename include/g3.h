@@ -235,6 +235,49 @@ int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                const int32_t *active, const g3_params *p, float *acc,
                float *pot, int32_t *nterms, void *stream);
 
+/*
+ * Adjoints (the _backward twins). The paper stops at the forward modules;
+ * these give the gradients of a scalar loss L with respect to the modules'
+ * inputs, from the gradients of L with respect to their outputs at the
+ * active rows (upstream gradients; NULL means zero). Neighbour sets and
+ * Barnes-Hut decisions are those the forward call takes at the same inputs
+ * (the forward maps are piecewise smooth in them), and h is an input: there
+ * is no derivative through the h solve. Gradients are ADDED (+=) to the
+ * caller's [n] / [n][3] arrays in caller order, each nullable; inactive
+ * particles receive what the active particles' sums owe them. FP32 trees
+ * only (G3_EINVAL otherwise). Density and hydro adjoints are gathered per
+ * particle in a fixed order (run-to-run identical); the gravity adjoint adds
+ * the source side of each term with atomics, so its last bits may vary
+ * between runs.
+ *
+ * Density: L's upstream gradients g_rho, g_drho_dh, g_omega; rho and
+ * drho_dh are the forward outputs at the active rows (they enter through
+ * omega). Outputs dL/dpos, dL/dmass, dL/dh. */
+int g3_density_backward(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                        const int32_t *active, const g3_params *p,
+                        const float *h, const float *rho, const float *drho_dh,
+                        const float *g_rho, const float *g_drho_dh,
+                        const float *g_omega, float *g_pos, float *g_mass,
+                        float *g_h, void *stream);
+/* Hydro force: upstream g_acc [n][3], g_dudt [n] (the signal velocity is
+ * not differentiated); inputs as g3_hydro_force. Outputs dL/dpos, dL/dvel,
+ * dL/dmass, dL/dh, dL/du, dL/drho, dL/domega. */
+int g3_hydro_force_backward(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                            const int32_t *active, const g3_params *p,
+                            const float *vel, const float *u, const float *h,
+                            const float *rho, const float *omega,
+                            const float *g_acc, const float *g_dudt,
+                            float *g_pos, float *g_vel, float *g_mass,
+                            float *g_h, float *g_u, float *g_rho,
+                            float *g_omega, void *stream);
+/* Gravity: upstream g_acc [n][3], g_pot [n]. Node monopoles pass their
+ * gradients to their members through M = sum m and c = sum m x / M.
+ * Outputs dL/dpos, dL/dmass. */
+int g3_gravity_backward(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
+                        const int32_t *active, const g3_params *p,
+                        const float *g_acc, const float *g_pot, float *g_pos,
+                        float *g_mass, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,11 +85,11 @@ def lib():
         L.g3ref_gravity.restype = ctypes.c_int
         L.g3ref_lists.argtypes = [P, i32, i64, P, P, P, P, P]
         L.g3ref_lists.restype = ctypes.c_int
-        L.g3ref_density_backward.argtypes = [P, i64, P, P] + [P] * 7
+        L.g3ref_density_backward.argtypes = [P, i64, P, P] + [P] * 8
         L.g3ref_density_backward.restype = ctypes.c_int
-        L.g3ref_hydro_backward.argtypes = [P, i64, P, P] + [P] * 14
+        L.g3ref_hydro_backward.argtypes = [P, i64, P, P] + [P] * 15
         L.g3ref_hydro_backward.restype = ctypes.c_int
-        L.g3ref_gravity_backward.argtypes = [P, i64, P, P] + [P] * 4
+        L.g3ref_gravity_backward.argtypes = [P, i64, P, P] + [P] * 5
         L.g3ref_gravity_backward.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -240,13 +240,15 @@ def density_backward(tree: Tree, params, h, g_rho=None, g_drho_dh=None, g_omega=
     act = _active(tree.n, active)
     n = tree.n
     out = dict(pos=np.zeros((n, 3)), mass=np.zeros(n), h=np.zeros(n))
+    S = np.zeros(5 * n)
     ins = [_f64(h), _opt(g_rho), _opt(g_drho_dh), _opt(g_omega)]
     st = lib().g3ref_density_backward(tree._h, act.size, _ptr(act),
                                       ctypes.byref(Params.of(params)),
                                       *[_ptr(a) for a in ins],
-                                      *[_ptr(out[k]) for k in ("pos", "mass", "h")])
+                                      *[_ptr(out[k]) for k in ("pos", "mass", "h")], _ptr(S))
     if st != OK:
         raise ValueError(f"g3ref_density_backward status {st}")
+    out["S"] = dict(pos=S[:3 * n].reshape(n, 3), mass=S[3 * n:4 * n], h=S[4 * n:])
     return out
 
 
@@ -258,14 +260,18 @@ def hydro_backward(tree: Tree, params, vel, u, h, rho, omega, g_acc=None, g_dudt
     n = tree.n
     out = dict(pos=np.zeros((n, 3)), vel=np.zeros((n, 3)), mass=np.zeros(n), h=np.zeros(n),
                u=np.zeros(n), rho=np.zeros(n), omega=np.zeros(n))
+    S = np.zeros(11 * n)
     ins = [_f64(vel, (-1, 3)), _f64(u), _f64(h), _f64(rho), _f64(omega),
            _opt(g_acc, (-1, 3)), _opt(g_dudt)]
     st = lib().g3ref_hydro_backward(tree._h, act.size, _ptr(act),
                                     ctypes.byref(Params.of(params)), *[_ptr(a) for a in ins],
                                     *[_ptr(out[k]) for k in
-                                      ("pos", "vel", "mass", "h", "u", "rho", "omega")])
+                                      ("pos", "vel", "mass", "h", "u", "rho", "omega")], _ptr(S))
     if st != OK:
         raise ValueError(f"g3ref_hydro_backward status {st}")
+    out["S"] = dict(pos=S[:3 * n].reshape(n, 3), vel=S[3 * n:6 * n].reshape(n, 3),
+                    mass=S[6 * n:7 * n], h=S[7 * n:8 * n], u=S[8 * n:9 * n],
+                    rho=S[9 * n:10 * n], omega=S[10 * n:])
     return out
 
 
@@ -275,10 +281,12 @@ def gravity_backward(tree: Tree, params, g_acc=None, g_pot=None, active=None) ->
     act = _active(tree.n, active)
     n = tree.n
     out = dict(pos=np.zeros((n, 3)), mass=np.zeros(n))
+    S = np.zeros(4 * n)
     st = lib().g3ref_gravity_backward(tree._h, act.size, _ptr(act),
                                       ctypes.byref(Params.of(params)),
                                       _ptr(_opt(g_acc, (-1, 3))), _ptr(_opt(g_pot)),
-                                      _ptr(out["pos"]), _ptr(out["mass"]))
+                                      _ptr(out["pos"]), _ptr(out["mass"]), _ptr(S))
     if st != OK:
         raise ValueError(f"g3ref_gravity_backward status {st}")
+    out["S"] = dict(pos=S[:3 * n].reshape(n, 3), mass=S[3 * n:])
     return out

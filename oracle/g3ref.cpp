@@ -745,21 +745,35 @@ Dual<K> separation(const Dual<K> *xi, const Dual<K> *xj) {
   return sqrt(r2);
 }
 
-/* Per-thread gradient buffers, summed in thread order at the end. */
-struct GradBuf {
-  std::vector<std::vector<double>> b;
-  GradBuf(int nt, size_t len) : b((size_t)nt, std::vector<double>(len, 0.0)) {}
-  std::vector<double> &mine() {
-#ifdef _OPENMP
-    return b[(size_t)omp_get_thread_num()];
-#else
-    return b[0];
-#endif
+/* Per-thread gradient buffers, summed in thread order at the end. Each
+ * entry also sums the magnitudes of the contributions added to it (the
+ * scale of its rounding error in any order of summation). */
+struct Mine {
+  std::vector<double> &v, &a;
+  void add(size_t i, double x) {
+    v[i] += x;
+    a[i] += std::fabs(x);
   }
-  void add_to(double *out, size_t len) const {
-    if (!out) return;
-    for (const auto &v : b)
-      for (size_t i = 0; i < len; ++i) out[i] += v[i];
+};
+
+struct GradBuf {
+  std::vector<std::vector<double>> b, s;
+  GradBuf(int nt, size_t len)
+      : b((size_t)nt, std::vector<double>(len, 0.0)), s((size_t)nt, std::vector<double>(len, 0.0)) {}
+  Mine mine() {
+#ifdef _OPENMP
+    const size_t t = (size_t)omp_get_thread_num();
+#else
+    const size_t t = 0;
+#endif
+    return Mine{b[t], s[t]};
+  }
+  void add_to(double *out, double *mag, size_t len) const {
+    for (size_t t = 0; t < b.size(); ++t)
+      for (size_t i = 0; i < len; ++i) {
+        if (out) out[i] += b[t][i];
+        if (mag) mag[i] += s[t][i];
+      }
   }
 };
 
@@ -782,7 +796,7 @@ extern "C" {
 int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
                            const g3ref_params *p, const double *h, const double *g_rho,
                            const double *g_drho, const double *g_omega, double *g_pos,
-                           double *g_mass, double *g_h) {
+                           double *g_mass, double *g_h, double *S) {
   if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !h) return G3REF_EINVAL;
   const g3ref_tree &t = *gas;
   const size_t n = (size_t)t.n;
@@ -812,8 +826,8 @@ int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *
     const double go = g_omega ? g_omega[i] : 0.0;
     const double grho = (g_rho ? g_rho[i] : 0.0) + go * Om.d[0];
     const double gdrho = (g_drho ? g_drho[i] : 0.0) + go * Om.d[1];
-    std::vector<double> &GX = gx.mine(), &GM = gm.mine(), &GH = gh.mine();
-    GH[i] += go * Om.d[2];
+    Mine GX = gx.mine(), GM = gm.mine(), GH = gh.mine();
+    GH.add(i, go * Om.d[2]);
     // each pair: (m_j W(r, h_i), m_j dW/dh(r, h_i)) in duals over
     // x_i (0-2), x_j (3-5), m_j (6), h_i (7)
     using D8 = Dual<8>;
@@ -828,16 +842,16 @@ int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *
       wc6_t(separation(xi, xj), H, &W, &Wh, &F);
       const D8 cr = mj * W, cd = mj * Wh;
       for (int c = 0; c < 3; ++c) {
-        GX[3 * i + c] += grho * cr.d[c] + gdrho * cd.d[c];
-        GX[3 * j + c] += grho * cr.d[3 + c] + gdrho * cd.d[3 + c];
+        GX.add(3 * i + c, grho * cr.d[c] + gdrho * cd.d[c]);
+        GX.add(3 * j + c, grho * cr.d[3 + c] + gdrho * cd.d[3 + c]);
       }
-      GM[j] += grho * cr.d[6] + gdrho * cd.d[6];
-      GH[i] += grho * cr.d[7] + gdrho * cd.d[7];
+      GM.add(j, grho * cr.d[6] + gdrho * cd.d[6]);
+      GH.add(i, grho * cr.d[7] + gdrho * cd.d[7]);
     }
   }
-  gx.add_to(g_pos, 3 * n);
-  gm.add_to(g_mass, n);
-  gh.add_to(g_h, n);
+  gx.add_to(g_pos, S, 3 * n);
+  gm.add_to(g_mass, S ? S + 3 * n : nullptr, n);
+  gh.add_to(g_h, S ? S + 4 * n : nullptr, n);
   return G3REF_OK;
 }
 
@@ -855,7 +869,7 @@ int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *ac
                          const double *h, const double *rho, const double *omega,
                          const double *g_acc, const double *g_dudt, double *g_pos,
                          double *g_vel, double *g_mass, double *g_h, double *g_u,
-                         double *g_rho, double *g_omega) {
+                         double *g_rho, double *g_omega, double *S) {
   if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !vel || !u || !h ||
       !rho || !omega)
     return G3REF_EINVAL;
@@ -886,8 +900,8 @@ int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *ac
                 [&](int64_t j) {
       if (j != i && is_gas(t, j) && within(t, i, j, std::max(hi, h[j]), p->flags)) nb.push_back(j);
     });
-    std::vector<double> &GX = gx.mine(), &GV = gv.mine(), &GM = gms.mine(), &GH = gh.mine(),
-                        &GU = gu.mine(), &GR = gr.mine(), &GO = go.mine();
+    Mine GX = gx.mine(), GV = gv.mine(), GM = gms.mine(), GH = gh.mine(),
+                        GU = gu.mine(), GR = gr.mine(), GO = go.mine();
     for (int64_t j : nb) {
       D xi[3], xj[3], vi[3], vj[3];
       for (int c = 0; c < 3; ++c) {
@@ -927,29 +941,30 @@ int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *ac
       D L = gd * du;
       for (int c = 0; c < 3; ++c) L = L + ga[c] * (coef * x[c]);
       for (int c = 0; c < 3; ++c) {
-        GX[3 * i + c] += L.d[c];
-        GX[3 * j + c] += L.d[3 + c];
-        GV[3 * i + c] += L.d[6 + c];
-        GV[3 * j + c] += L.d[9 + c];
+        GX.add(3 * i + c, L.d[c]);
+        GX.add(3 * j + c, L.d[3 + c]);
+        GV.add(3 * i + c, L.d[6 + c]);
+        GV.add(3 * j + c, L.d[9 + c]);
       }
-      GM[j] += L.d[12];
-      GH[i] += L.d[13];
-      GH[j] += L.d[14];
-      GU[i] += L.d[15];
-      GU[j] += L.d[16];
-      GR[i] += L.d[17];
-      GR[j] += L.d[18];
-      GO[i] += L.d[19];
-      GO[j] += L.d[20];
+      GM.add(j, L.d[12]);
+      GH.add(i, L.d[13]);
+      GH.add(j, L.d[14]);
+      GU.add(i, L.d[15]);
+      GU.add(j, L.d[16]);
+      GR.add(i, L.d[17]);
+      GR.add(j, L.d[18]);
+      GO.add(i, L.d[19]);
+      GO.add(j, L.d[20]);
     }
   }
-  gx.add_to(g_pos, 3 * n);
-  gv.add_to(g_vel, 3 * n);
-  gms.add_to(g_mass, n);
-  gh.add_to(g_h, n);
-  gu.add_to(g_u, n);
-  gr.add_to(g_rho, n);
-  go.add_to(g_omega, n);
+  auto at = [&](size_t off) { return S ? S + off : nullptr; };
+  gx.add_to(g_pos, at(0), 3 * n);
+  gv.add_to(g_vel, at(3 * n), 3 * n);
+  gms.add_to(g_mass, at(6 * n), n);
+  gh.add_to(g_h, at(7 * n), n);
+  gu.add_to(g_u, at(8 * n), n);
+  gr.add_to(g_rho, at(9 * n), n);
+  go.add_to(g_omega, at(10 * n), n);
   return G3REF_OK;
 }
 
@@ -962,7 +977,7 @@ int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *ac
  * Adds dL/dx and dL/dm to g_pos [n][3] and g_mass [n] (each nullable). */
 int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *active,
                            const g3ref_params *p, const double *g_acc, const double *g_pot,
-                           double *g_pos, double *g_mass) {
+                           double *g_pos, double *g_mass, double *S) {
   if (!all || !valid_params(p) || n_act < 0 || (n_act > 0 && !active)) return G3REF_EINVAL;
   const g3ref_tree &t = *all;
   const size_t n = (size_t)t.n, nn = t.nodes.size();
@@ -979,7 +994,7 @@ int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *
     const double ga[3] = {g_acc ? g_acc[3 * i] : 0.0, g_acc ? g_acc[3 * i + 1] : 0.0,
                           g_acc ? g_acc[3 * i + 2] : 0.0};
     const double gp = g_pot ? g_pot[i] : 0.0;
-    std::vector<double> &GX = gx.mine(), &GM = gms.mine(), &GC = gc.mine(), &GMn = gM.mine();
+    Mine GX = gx.mine(), GM = gms.mine(), GC = gc.mine(), GMn = gM.mine();
     bh_walk(t, 0, i, p->theta, p->flags, [&](double m, const double *c, int64_t id) {
       D xi[3], xs[3];
       for (int k = 0; k < 3; ++k) {
@@ -994,35 +1009,38 @@ int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *
       const D inv3 = inv * inv * inv;
       D L = gp * (-G * ms * inv);
       for (int k = 0; k < 3; ++k) L = L + ga[k] * (-G * ms * x[k] * inv3);
-      for (int k = 0; k < 3; ++k) GX[3 * i + k] += L.d[k];
+      for (int k = 0; k < 3; ++k) GX.add(3 * i + k, L.d[k]);
       if (id >= 0) {
-        for (int k = 0; k < 3; ++k) GX[3 * id + k] += L.d[3 + k];
-        GM[id] += L.d[6];
+        for (int k = 0; k < 3; ++k) GX.add(3 * id + k, L.d[3 + k]);
+        GM.add(id, L.d[6]);
       } else {
         const int64_t nd = -id - 1;
-        for (int k = 0; k < 3; ++k) GC[3 * nd + k] += L.d[3 + k];
-        GMn[nd] += L.d[6];
+        for (int k = 0; k < 3; ++k) GC.add(3 * nd + k, L.d[3 + k]);
+        GMn.add(nd, L.d[6]);
       }
     });
   }
-  gx.add_to(g_pos, 3 * n);
-  gms.add_to(g_mass, n);
+  gx.add_to(g_pos, S, 3 * n);
+  gms.add_to(g_mass, S ? S + 3 * n : nullptr, n);
   // node adjoints to their members
-  std::vector<double> GCt(3 * nn, 0.0), GMt(nn, 0.0);
-  gc.add_to(GCt.data(), 3 * nn);
-  gM.add_to(GMt.data(), nn);
+  std::vector<double> GCt(3 * nn, 0.0), GMt(nn, 0.0), SCt(3 * nn, 0.0), SMt(nn, 0.0);
+  gc.add_to(GCt.data(), SCt.data(), 3 * nn);
+  gM.add_to(GMt.data(), SMt.data(), nn);
   for (size_t k = 0; k < nn; ++k) {
     const RefNode &nd = t.nodes[k];
     if (GCt[3 * k] == 0.0 && GCt[3 * k + 1] == 0.0 && GCt[3 * k + 2] == 0.0 && GMt[k] == 0.0)
       continue;
     for (int64_t s = nd.start; s < nd.start + nd.count; ++s) {
       const int64_t j = t.order[s];
-      double dot = 0.0;
+      double dot = 0.0, sdot = 0.0;
       for (int c = 0; c < 3; ++c) {
         if (g_pos) g_pos[3 * j + c] += GCt[3 * k + c] * t.mass[j] / nd.M;
+        if (S) S[3 * j + c] += SCt[3 * k + c] * t.mass[j] / nd.M;
         dot += GCt[3 * k + c] * (t.pos[3 * j + c] - nd.com[c]);
+        sdot += SCt[3 * k + c] * std::fabs(t.pos[3 * j + c] - nd.com[c]);
       }
       if (g_mass) g_mass[j] += GMt[k] + dot / nd.M;
+      if (S) S[3 * n + j] += SMt[k] + sdot / nd.M;
     }
   }
   return G3REF_OK;

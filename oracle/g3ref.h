@@ -112,20 +112,22 @@ int g3ref_lists(const g3ref_tree *t, int32_t kind, int64_t n_act,
  * neighbour sets and Barnes-Hut decisions held fixed, h an input. Results
  * are ADDED to the [n] (or [n][3]) gradient arrays; every pointer argument
  * named g_* is nullable. Partials come from forward-mode dual numbers over
- * each pair's or term's inputs. */
+ * each pair's or term's inputs. S (nullable) receives, per gradient entry,
+ * the sum of the magnitudes of the contributions added to it, laid out as
+ * the gradient arguments concatenated in order ([n][3] before [n]). */
 int g3ref_density_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
                            const g3ref_params *p, const double *h, const double *g_rho,
                            const double *g_drho, const double *g_omega, double *g_pos,
-                           double *g_mass, double *g_h);
+                           double *g_mass, double *g_h, double *S);
 int g3ref_hydro_backward(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
                          const g3ref_params *p, const double *vel, const double *u,
                          const double *h, const double *rho, const double *omega,
                          const double *g_acc, const double *g_dudt, double *g_pos,
                          double *g_vel, double *g_mass, double *g_h, double *g_u,
-                         double *g_rho, double *g_omega);
+                         double *g_rho, double *g_omega, double *S);
 int g3ref_gravity_backward(const g3ref_tree *all, int64_t n_act, const int64_t *active,
                            const g3ref_params *p, const double *g_acc, const double *g_pot,
-                           double *g_pos, double *g_mass);
+                           double *g_pos, double *g_mass, double *S);
 
 #ifdef __cplusplus
 }

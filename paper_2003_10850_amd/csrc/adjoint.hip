@@ -1,0 +1,753 @@
+// Adjoint (backward) kernels of the density, hydro force and gravity: the
+// gradients of a scalar loss with respect to positions, masses, smoothing
+// lengths (and the hydro inputs), given its gradients with respect to the
+// module outputs at the active particles. Neighbour sets and Barnes-Hut
+// decisions are those of the forward call (the forward map is piecewise
+// smooth in them) and h is an input.
+//
+// SPH adjoints are gathered: every gas particle walks its symmetric
+// neighbourhood r < max(h_p, h_q) once and adds both what its own sums owe
+// to its inputs and what its neighbours' sums owe to them, so each
+// gradient is written by one lane in a fixed order (deterministic). The
+// gravity adjoint is scattered: a wave sums the source-side terms of a tile
+// entry over its lanes with DPP row operations and adds them with one
+// atomic per entry; node adjoints are then pushed down to the members.
+#include "g3_device.h"
+#include "g3_internal.h"
+
+namespace g3 {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWpb = kBlock / kWave;
+constexpr int kTile = kWave;
+constexpr float kC = 6.7889530412636603f;  // 1365 / (64 pi)
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Wendland C6 (support h, q = r/h) and the derivatives the adjoints need,
+// each zero at and beyond the support:
+//   W    = C/h^3 (1-q)^8 (1 + 8q + 25q^2 + 32q^3)
+//   W_h  = dW/dh        = C/h^4 (1-q)^7 (-3 - 21q - 29q^2 + 133q^3 + 448q^4)
+//   F    = (1/r) dW/dr  = -22 C/h^5 (1-q)^7 (1 + 7q + 16q^2)
+//   G    = (1/r) dW_h/dr = dF/dh = 22 C/h^6 (1-q)^6 (5 + 30q + 21q^2 - 224q^3)
+//   W_hh = d^2W/dh^2    = 6 C/h^5 (1-q)^6 (2 + 12q - 13q^2 - 218q^3 - 287q^4 + 1120q^5)
+struct Wc6 {
+  float W, Wh, F, G, Whh;
+};
+
+__device__ __forceinline__ Wc6 wc6_all(float r, float hinv) {
+  const float q = r * hinv;
+  const float t = fmaxf(1.0f - q, 0.0f);
+  const float t2 = t * t, t3 = t2 * t, t6 = t3 * t3, t7 = t6 * t;
+  const float h2 = hinv * hinv, h3 = h2 * hinv, h4 = h2 * h2, h5 = h4 * hinv, h6 = h3 * h3;
+  Wc6 k;
+  k.W = kC * h3 * t7 * t * (1.0f + q * (8.0f + q * (25.0f + q * 32.0f)));
+  k.Wh = kC * h4 * t7 * (-3.0f + q * (-21.0f + q * (-29.0f + q * (133.0f + q * 448.0f))));
+  k.F = -22.0f * kC * h5 * t7 * (1.0f + q * (7.0f + q * 16.0f));
+  k.G = 22.0f * kC * h6 * t6 * (5.0f + q * (30.0f + q * (21.0f - q * 224.0f)));
+  k.Whh = 6.0f * kC * h5 * t6 *
+          (2.0f + q * (12.0f + q * (-13.0f + q * (-218.0f + q * (-287.0f + q * 1120.0f)))));
+  return k;
+}
+
+// ---------------------------------------------------------------- density
+
+// Upstream gradients of the density outputs folded into the two sums:
+// Omega = 1 + h rho' / (3 rho) gives
+//   gbar_rho  = g_rho  - g_omega h rho' / (3 rho^2)
+//   gbar_rho' = g_rho' + g_omega h / (3 rho)
+//   dL/dh    += g_omega rho' / (3 rho)        (the explicit h of Omega)
+// written into bw[s] = (h, gbar_rho, gbar_rho', 0) at the active gas rows.
+__global__ void k_density_bwd_prep(const int32_t *__restrict__ active, int64_t n_act,
+                                   const int32_t *__restrict__ iperm, int64_t n_caller,
+                                   const float *__restrict__ h, const float *__restrict__ rho,
+                                   const float *__restrict__ drho, const float *__restrict__ g_rho,
+                                   const float *__restrict__ g_drho,
+                                   const float *__restrict__ g_omega, float4 *__restrict__ bw,
+                                   float *__restrict__ g_h) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_act) return;
+  const int32_t id = active ? active[a] : (int32_t)a;
+  if (id < 0 || (int64_t)id >= n_caller) return;
+  const int32_t s = iperm[id];
+  if (s < 0) return;
+  const float hi = h[id], r = rho[id], rp = drho[id];
+  const float go = g_omega ? g_omega[id] : 0.0f;
+  const float gr = (g_rho ? g_rho[id] : 0.0f) - go * hi * rp / (3.0f * r * r);
+  const float gd = (g_drho ? g_drho[id] : 0.0f) + go * hi / (3.0f * r);
+  bw[s] = make_float4(hi, gr, gd, 0.0f);
+  if (g_h && go != 0.0f) g_h[id] += go * rp / (3.0f * r);
+}
+
+__global__ void k_density_bwd_init(const int32_t *__restrict__ perm, int64_t m,
+                                   const float *__restrict__ h, float4 *__restrict__ bw) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < m) bw[s] = make_float4(h[perm[s]], 0.0f, 0.0f, 0.0f);
+}
+
+// One lane per gas particle p, over every q with r < max(h_p, h_q):
+//   own sums (r < h_p):  a = gbar_rho_p m_q F(r,h_p) + gbar_rho'_p m_q G(r,h_p)
+//       dL/dx_p += a (x_p - x_q)
+//       dL/dh_p += m_q (gbar_rho_p W_h(r,h_p) + gbar_rho'_p W_hh(r,h_p))
+//   q's sums (r < h_q):  b = gbar_rho_q m_p F(r,h_q) + gbar_rho'_q m_p G(r,h_q)
+//       dL/dx_p += b (x_p - x_q)
+//       dL/dm_p += gbar_rho_q W(r,h_q) + gbar_rho'_q W_h(r,h_q)
+// The pair q = p (r = 0) adds the self terms of h and m.
+__global__ __launch_bounds__(kBlock) void k_density_bwd(
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const float4 *__restrict__ bw, const int32_t *__restrict__ perm, const Groups gs,
+    float *__restrict__ g_pos, float *__restrict__ g_mass, float *__restrict__ g_h) {
+  __shared__ float4 tx[kWpb][kTile];
+  __shared__ float4 tb[kWpb][kTile];
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+    const Group grp = group_at(gs, g);
+    const bool valid = lane < grp.count;
+    const int s = valid ? grp.t0 + lane : grp.t0;
+    const float4 me = xm[s], mb = bw[s];
+    const float hp = valid ? mb.x : -1.0f;
+    const float hp2 = sq_exact(hp), hinv = 1.0f / mb.x;
+    const bool own_on = valid && (mb.y != 0.0f || mb.z != 0.0f);
+    float gx = 0.f, gy = 0.f, gz = 0.f, gm = 0.f, gh = 0.f;
+    float cx = 0.f, cy = 0.f, cz = 0.f, cm = 0.f, ch = 0.f;
+    int tc = 0, cand = 0;
+    auto flush = [&](int nc) {
+      if (lane < nc) {
+        tx[w][lane] = xm[cand];
+        tb[w][lane] = bw[cand];
+      } else {
+        tx[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        tb[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      wave_sync();
+      float px = 0.f, py = 0.f, pz = 0.f, pm = 0.f, ph = 0.f;
+      for (int k = 0; k < nc; ++k) {
+        const float4 q = tx[w][k], qb = tb[w][k];
+        const float dx = sub_exact(q.x, me.x), dy = sub_exact(q.y, me.y),
+                    dz = sub_exact(q.z, me.z);
+        const float r2 = dist2_exact(dx, dy, dz);
+        const bool own = own_on && r2 < hp2;
+        const bool nbr = valid && (qb.y != 0.0f || qb.z != 0.0f) && r2 < sq_exact(qb.x);
+        if (own || nbr) {
+          const float r = __builtin_amdgcn_sqrtf(r2);
+          float a = 0.0f;
+          if (own) {
+            const Wc6 kp = wc6_all(r, hinv);
+            a = q.w * (mb.y * kp.F + mb.z * kp.G);
+            ph += q.w * (mb.y * kp.Wh + mb.z * kp.Whh);
+          }
+          if (nbr) {
+            const Wc6 kq = wc6_all(r, 1.0f / qb.x);
+            a += me.w * (qb.y * kq.F + qb.z * kq.G);
+            pm += qb.y * kq.W + qb.z * kq.Wh;
+          }
+          // x_p - x_q = -(dx, dy, dz)
+          px -= a * dx;
+          py -= a * dy;
+          pz -= a * dz;
+        }
+      }
+      neumaier_add(gx, cx, px);
+      neumaier_add(gy, cy, py);
+      neumaier_add(gz, cz, pz);
+      neumaier_add(gm, cm, pm);
+      neumaier_add(gh, ch, ph);
+      wave_sync();
+    };
+    int cur = grp.root;
+    while (cur < grp.end) {
+      const Node nd = nodes[cur];
+      const float hm = fmaxf(hp, nd.lo_h.w);
+      const bool want = valid && box_dist2(make_float3(me.x, me.y, me.z), nd.lo_h, nd.hi_l) <
+                                     sq_exact(hm);
+      if (__ballot(want) == 0ull) {
+        cur = nd.meta.x;
+        continue;
+      }
+      if (!(nd.meta.w & kLeafBit) && nd.meta.z > kTile) {
+        ++cur;
+        continue;
+      }
+      int st = nd.meta.y, c = nd.meta.z;
+      while (c > 0) {
+        const int take = min(c, kTile - tc);
+        if (lane >= tc && lane < tc + take) cand = st + lane - tc;
+        tc += take;
+        st += take;
+        c -= take;
+        if (tc == kTile) {
+          flush(kTile);
+          tc = 0;
+        }
+      }
+      cur = nd.meta.x;
+    }
+    if (tc > 0) flush(tc);
+    if (valid) {
+      const int cid = perm[s];
+      if (g_pos) {
+        g_pos[3 * cid] += gx + cx;
+        g_pos[3 * cid + 1] += gy + cy;
+        g_pos[3 * cid + 2] += gz + cz;
+      }
+      if (g_mass) g_mass[cid] += gm + cm;
+      if (g_h) g_h[cid] += gh + ch;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- gravity
+
+// v shifted by a DPP row operation; lanes without a source read 0
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf,
+                                                    false));
+}
+
+// Sum of v over the 64 lanes, left in lane 63: an inclusive scan within
+// each row of 16 lanes (row_shr 1, 2, 4, 8), then the last lane of rows 0
+// and 2 added to rows 1 and 3 (row_bcast 15) and lane 31 to rows 2 and 3
+// (row_bcast 31). Every lane must be active.
+__device__ __forceinline__ float wave_total_in_lane63(float v) {
+  v += dpp_or_zero<0x111>(v);
+  v += dpp_or_zero<0x112>(v);
+  v += dpp_or_zero<0x114>(v);
+  v += dpp_or_zero<0x118>(v);
+  v += dpp_or_zero<0x142, 0xa>(v);
+  v += dpp_or_zero<0x143, 0xc>(v);
+  return v;
+}
+
+struct __align__(16) GEntry {
+  float4 p;   // source position, mass
+  int4 meta;  // sorted source index, or -(node + 1); mask low, mask high; unused
+};
+
+__device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
+#pragma clang fp contract(off)
+  const float lhs = l * l;
+  const float rhs = theta2 * r2;
+  return lhs < rhs;
+}
+
+// The Barnes-Hut walk of the forward kernel; each term of target i with
+// source s (x = x_i - x_s, S = r^2 + eps^2) and upstream gradients
+// (ga, gp) of a_i and phi_i contributes
+//   dL/dx  = G m ( -ga / S^(3/2) + 3 (ga . x) x / S^(5/2) + gp x / S^(3/2) )
+//   dL/dx_i += dL/dx,  dL/dx_s -= dL/dx,  dL/dm_s = -G ((ga . x) / S^(3/2) + gp / S^(1/2)).
+// The source side of a tile entry is summed over the wave's lanes and added
+// once: to the particle's sorted slot, or to the node's (dL/dc, dL/dM).
+__global__ __launch_bounds__(kBlock) void k_gravity_bwd(
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
+    float theta2, float eps2, float G, int inside_test, const float *__restrict__ g_acc,
+    const float *__restrict__ g_pot, float4 *__restrict__ gsrc, float4 *__restrict__ gnode) {
+  __shared__ GEntry tiles[kWpb][kTile];
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  GEntry *tile = tiles[w];
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+    const Group grp = group_at(gs, g);
+    const int64_t t = grp.t0 + lane;
+    const bool valid = lane < grp.count;
+    const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
+    const float4 me = xm[s];
+    const uint64_t ki = keys[s];
+    const int cid = perm[s];
+    const float gax = valid && g_acc ? g_acc[3 * cid] : 0.f;
+    const float gay = valid && g_acc ? g_acc[3 * cid + 1] : 0.f;
+    const float gaz = valid && g_acc ? g_acc[3 * cid + 2] : 0.f;
+    const float gpp = valid && g_pot ? g_pot[cid] : 0.f;
+    float ox = 0.f, oy = 0.f, oz = 0.f, cox = 0.f, coy = 0.f, coz = 0.f;
+    int tc = 0;
+    const bool hiword = lane >= 32;
+    const uint32_t bitpos = (uint32_t)lane & 31u;
+    auto flush = [&](int nc) {
+      wave_sync();
+      float px = 0.f, py = 0.f, pz = 0.f;
+      for (int k = 0; k < nc; ++k) {
+        const GEntry e = tile[k];
+        const uint32_t word = (uint32_t)(hiword ? e.meta.z : e.meta.y);
+        const bool use = (__builtin_amdgcn_ubfe(word, bitpos, 1u) != 0u) & (e.meta.x != s);
+        const float dx = e.p.x - me.x, dy = e.p.y - me.y, dz = e.p.z - me.z;  // x_s - x_i
+        const float S = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        const float inv = __builtin_amdgcn_rsqf(S);
+        const float inv3 = inv * inv * inv;
+        const float Gm = use ? G * e.p.w : 0.0f;
+        const float gx_ = -(gax * dx + gay * dy + gaz * dz);  // ga . x, x = x_i - x_s
+        const float c3 = 3.0f * gx_ * inv3 * inv * inv;
+        // dL/dx with x = -(dx, dy, dz)
+        const float Dx = Gm * (-gax * inv3 - c3 * dx - gpp * dx * inv3);
+        const float Dy = Gm * (-gay * inv3 - c3 * dy - gpp * dy * inv3);
+        const float Dz = Gm * (-gaz * inv3 - c3 * dz - gpp * dz * inv3);
+        const float Dm = use ? -G * (gx_ * inv3 + gpp * inv) : 0.0f;
+        px += Dx;
+        py += Dy;
+        pz += Dz;
+        const float sx = wave_total_in_lane63(-Dx);
+        const float sy = wave_total_in_lane63(-Dy);
+        const float sz = wave_total_in_lane63(-Dz);
+        const float sm = wave_total_in_lane63(Dm);
+        if (lane == 63) {
+          float4 *dst = e.meta.x >= 0 ? &gsrc[e.meta.x] : &gnode[-e.meta.x - 1];
+          atomicAdd(&dst->x, sx);
+          atomicAdd(&dst->y, sy);
+          atomicAdd(&dst->z, sz);
+          atomicAdd(&dst->w, sm);
+        }
+      }
+      neumaier_add(ox, cox, px);
+      neumaier_add(oy, coy, py);
+      neumaier_add(oz, coz, pz);
+      wave_sync();
+    };
+    int resume = valid ? grp.root : INT32_MAX;
+    int cur = grp.root;
+    while (cur < grp.end) {
+      const Node nd = nodes[cur];
+      const bool act = cur >= resume;
+      const float r2 = dist2_exact(sub_exact(nd.com_m.x, me.x), sub_exact(nd.com_m.y, me.y),
+                                   sub_exact(nd.com_m.z, me.z));
+      bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
+      if (inside_test) {
+        const int level = nd.meta.w & 255;
+        const uint64_t nk = keys[nd.meta.y];
+        accept = accept && (((ki ^ nk) >> (3 * (kMaxLevel - level))) != 0ull);
+      }
+      const uint64_t amask = __ballot(accept);
+      const uint64_t omask = __ballot(act && !accept);
+      if (accept) resume = nd.meta.x;
+      if (amask) {
+        if (tc == kTile) {
+          flush(kTile);
+          tc = 0;
+        }
+        if (lane == 0) {
+          GEntry e;
+          e.p = nd.com_m;
+          e.meta = make_int4(-(cur + 1), (int)(uint32_t)amask, (int)(uint32_t)(amask >> 32), 0);
+          tile[tc] = e;
+        }
+        ++tc;
+      }
+      if (omask == 0ull) {
+        cur = nd.meta.x;
+        continue;
+      }
+      if (!(nd.meta.w & kLeafBit)) {
+        ++cur;
+        continue;
+      }
+      int st = nd.meta.y, c = nd.meta.z;
+      while (c > 0) {
+        if (tc == kTile) {
+          flush(kTile);
+          tc = 0;
+        }
+        const int take = min(c, kTile - tc);
+        if (lane < take) {
+          GEntry e;
+          e.p = xm[st + lane];
+          e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
+          tile[tc + lane] = e;
+        }
+        tc += take;
+        st += take;
+        c -= take;
+      }
+      cur = nd.meta.x;
+    }
+    if (tc > 0) flush(tc);
+    if (valid) {
+      atomicAdd(&gsrc[s].x, ox + cox);
+      atomicAdd(&gsrc[s].y, oy + coy);
+      atomicAdd(&gsrc[s].z, oz + coz);
+    }
+  }
+}
+
+__global__ void k_zero_f4(float4 *__restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Node adjoints (dL/dc, dL/dM) to the members. With c = sum m x / M and
+// M = sum m, a member k of node a receives (m_k / M_a) dL/dc_a on x_k and
+// dL/dM_a + dL/dc_a . (x_k - c_a) / M_a on m_k. Summed over the ancestors of
+// k's leaf l, top-down in FP64:
+//   P_n = sum_a dL/dc_a / M_a,  Q_n = sum_a dL/dM_a,
+//   R_n = sum_a dL/dc_a . (c_n - c_a) / M_a = R_parent + P_parent . (c_n - c_parent)
+// and then x_k gets m_k P_l, m_k gets Q_l + R_l + P_l . (x_k - c_l).
+__global__ void k_push_init(const float4 *__restrict__ gnode, const double4 *__restrict__ mom,
+                            int64_t nn, double4 *__restrict__ pq, double *__restrict__ rr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const float4 g = gnode[k];
+  const double M = mom[k].x;
+  const double inv = M > 0.0 ? 1.0 / M : 0.0;
+  pq[k] = make_double4(g.x * inv, g.y * inv, g.z * inv, (double)g.w);
+  rr[k] = 0.0;
+}
+
+__global__ void k_push_level(const Node *__restrict__ nodes, const double4 *__restrict__ mom,
+                             int64_t nn, int level, double4 *__restrict__ pq,
+                             double *__restrict__ rr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int4 meta = nodes[k].meta;
+  if ((meta.w & 255) != level || (meta.w & kLeafBit)) return;
+  const double4 P = pq[k];
+  const double R = rr[k];
+  const double4 mk = mom[k];
+  const double ik = mk.x > 0.0 ? 1.0 / mk.x : 0.0;
+  const double cx = mk.y * ik, cy = mk.z * ik, cz = mk.w * ik;
+  int64_t c = k + 1;
+  while (c < meta.x) {
+    const double4 mc = mom[c];
+    const double ic = mc.x > 0.0 ? 1.0 / mc.x : 0.0;
+    double4 q = pq[c];
+    q.x += P.x;
+    q.y += P.y;
+    q.z += P.z;
+    q.w += P.w;
+    pq[c] = q;
+    rr[c] = R + P.x * (mc.y * ic - cx) + P.y * (mc.z * ic - cy) + P.z * (mc.w * ic - cz);
+    c = nodes[c].meta.x;
+  }
+}
+
+__global__ void k_push_leaves(const Node *__restrict__ nodes, const double4 *__restrict__ mom,
+                              int64_t nn, const float4 *__restrict__ xm,
+                              const double4 *__restrict__ pq, const double *__restrict__ rr,
+                              float4 *__restrict__ gsrc) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int4 meta = nodes[k].meta;
+  if (!(meta.w & kLeafBit)) return;
+  const double4 P = pq[k];
+  const double R = rr[k];
+  const double4 mk = mom[k];
+  const double ik = mk.x > 0.0 ? 1.0 / mk.x : 0.0;
+  const double cx = mk.y * ik, cy = mk.z * ik, cz = mk.w * ik;
+  for (int s = meta.y; s < meta.y + meta.z; ++s) {
+    const float4 p = xm[s];
+    float4 g = gsrc[s];
+    g.x += (float)(p.w * P.x);
+    g.y += (float)(p.w * P.y);
+    g.z += (float)(p.w * P.z);
+    g.w += (float)(P.w + R + P.x * (p.x - cx) + P.y * (p.y - cy) + P.z * (p.z - cz));
+    gsrc[s] = g;
+  }
+}
+
+__global__ void k_scatter_grad(const int32_t *__restrict__ perm, int64_t m,
+                               const float4 *__restrict__ gsrc, float *__restrict__ g_pos,
+                               float *__restrict__ g_mass) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int cid = perm[s];
+  const float4 g = gsrc[s];
+  if (g_pos) {
+    g_pos[3 * cid] += g.x;
+    g_pos[3 * cid + 1] += g.y;
+    g_pos[3 * cid + 2] += g.z;
+  }
+  if (g_mass) g_mass[cid] += g.w;
+}
+
+// ------------------------------------------------------------------ hydro
+
+// F = (1/r) dW/dr and its derivatives dF/dr, dF/dh (= G above):
+//   F_r = 528 C/h^6 q (1-q)^6 (1 + 6q)
+__device__ __forceinline__ void wc6_f_derivs(float r, float hinv, float &F, float &Fr,
+                                             float &Fh) {
+  const float q = r * hinv;
+  const float t = fmaxf(1.0f - q, 0.0f);
+  const float t2 = t * t, t3 = t2 * t, t6 = t3 * t3;
+  const float h2 = hinv * hinv, h5 = h2 * h2 * hinv, h6 = h5 * hinv;
+  F = -22.0f * kC * h5 * t6 * t * (1.0f + q * (7.0f + q * 16.0f));
+  Fr = 528.0f * kC * h6 * t6 * q * (1.0f + 6.0f * q);
+  Fh = 22.0f * kC * h6 * t6 * (5.0f + q * (30.0f + q * (21.0f - q * 224.0f)));
+}
+
+// One side of a particle's hydro data: position and mass, velocity and h,
+// (A, c, rho, 1/h), and the upstream gradients (g_acc, g_dudt) of its sums.
+struct HSide {
+  float4 xm, vh, aux, up;
+};
+
+// Partials of one pair term (target i, neighbour j) of
+//   l = g_acc_i . a_ij + g_dudt_i du_ij,
+//   a_ij  = -m_j (A_i g_i + A_j g_j + Pi gbar) x,   x = x_i - x_j, v = v_i - v_j
+//   du_ij = m_j (A_i g_i + Pi gbar / 2) v.x,        g_k = F(r, h_k), gbar = (g_i + g_j)/2
+//   Pi = -alpha (c_i + c_j - 3w) w / (rho_i + rho_j) if w = v.x / r < 0, else 0,
+// with respect to the target's inputs (side 0) or the neighbour's (side 1):
+// d[0..2] position, d[3..5] velocity, d[6] h, d[7] A, d[8] c, d[9] rho
+// through Pi, d[10] m (neighbour only). The chain rules used:
+//   dl/dx = coef g_acc + L_vx v + (L_r / r) x,  dl/dv = L_vx x,
+//   L_vx = dl/dvx + dl/dPi dPi/dw / r,  L_r = sum_k dl/dg_k F_r(r,h_k) - dl/dPi dPi/dw w / r.
+__device__ __forceinline__ void hydro_pair_partials(const HSide &I, const HSide &J, float alpha,
+                                                    float dx, float dy, float dz, float r,
+                                                    int side, float *d) {
+  // x = x_i - x_j (dx, dy, dz given as that difference)
+  const float mj = J.xm.w;
+  const float vxx = I.vh.x - J.vh.x, vyy = I.vh.y - J.vh.y, vzz = I.vh.z - J.vh.z;
+  const float vx = vxx * dx + vyy * dy + vzz * dz;
+  const float rinv = 1.0f / r;
+  const float w = vx * rinv;
+  float gi, gir, gih, gj, gjr, gjh;
+  wc6_f_derivs(r, I.aux.w, gi, gir, gih);
+  wc6_f_derivs(r, J.aux.w, gj, gjr, gjh);
+  const float Ai = I.aux.x, Aj = J.aux.x, ci = I.aux.y, cj = J.aux.y;
+  const float rsum = I.aux.z + J.aux.z;
+  const bool neg = w < 0.0f;
+  const float Pi = neg ? -alpha * (ci + cj - 3.0f * w) * w / rsum : 0.0f;
+  const float Pw = neg ? -alpha * (ci + cj - 6.0f * w) / rsum : 0.0f;
+  const float Pc = neg ? -alpha * w / rsum : 0.0f;
+  const float Prho = neg ? -Pi / rsum : 0.0f;
+  const float gbar = 0.5f * (gi + gj);
+  const float gax = I.up.x, gay = I.up.y, gaz = I.up.z, gd = I.up.w;
+  const float sdot = gax * dx + gay * dy + gaz * dz;
+  const float T1 = Ai * gi, T2 = Aj * gj;
+  const float dPi = mj * gbar * (0.5f * gd * vx - sdot);
+  const float dgb = mj * Pi * (0.5f * gd * vx - sdot);
+  const float dgi = mj * Ai * (gd * vx - sdot) + 0.5f * dgb;
+  const float dgj = -mj * Aj * sdot + 0.5f * dgb;
+  const float coef = -mj * (T1 + T2 + Pi * gbar);
+  const float Lvx = gd * mj * (T1 + 0.5f * Pi * gbar) + dPi * Pw * rinv;
+  const float Lr = dgi * gir + dgj * gjr - dPi * Pw * w * rinv;
+  const float lr = Lr * rinv;
+  const float px = coef * gax + Lvx * vxx + lr * dx;
+  const float py = coef * gay + Lvx * vyy + lr * dy;
+  const float pz = coef * gaz + Lvx * vzz + lr * dz;
+  if (side == 0) {
+    d[0] = px; d[1] = py; d[2] = pz;
+    d[3] = Lvx * dx; d[4] = Lvx * dy; d[5] = Lvx * dz;
+    d[6] = dgi * gih;
+    d[7] = mj * gi * (gd * vx - sdot);
+    d[8] = dPi * Pc;
+    d[9] = dPi * Prho;
+    d[10] = 0.0f;
+  } else {
+    d[0] = -px; d[1] = -py; d[2] = -pz;
+    d[3] = -Lvx * dx; d[4] = -Lvx * dy; d[5] = -Lvx * dz;
+    d[6] = dgj * gjh;
+    d[7] = -mj * gj * sdot;
+    d[8] = dPi * Pc;
+    d[9] = dPi * Prho;
+    d[10] = -(T1 + T2 + Pi * gbar) * sdot + gd * (T1 + 0.5f * Pi * gbar) * vx;  // l / m_j
+  }
+}
+
+__global__ void k_hydro_bwd_up(const int32_t *__restrict__ active, int64_t n_act,
+                               const int32_t *__restrict__ iperm, int64_t n_caller,
+                               const float *__restrict__ g_acc, const float *__restrict__ g_dudt,
+                               float4 *__restrict__ up) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_act) return;
+  const int32_t id = active ? active[a] : (int32_t)a;
+  if (id < 0 || (int64_t)id >= n_caller) return;
+  const int32_t s = iperm[id];
+  if (s < 0) return;
+  up[s] = make_float4(g_acc ? g_acc[3 * id] : 0.f, g_acc ? g_acc[3 * id + 1] : 0.f,
+                      g_acc ? g_acc[3 * id + 2] : 0.f, g_dudt ? g_dudt[id] : 0.f);
+}
+
+// One lane per gas particle p over every q != p with r < max(h_p, h_q):
+// the pair (target p, neighbour q) if p is active, and (target q,
+// neighbour p) if q is active. Then A and c are mapped back to u, rho and
+// Omega: A = (gamma-1) u / (Omega rho), c = sqrt(gamma (gamma-1) u).
+__global__ __launch_bounds__(kBlock) void k_hydro_bwd(
+    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const float4 *__restrict__ vh, const float4 *__restrict__ aux,
+    const float4 *__restrict__ up, const int32_t *__restrict__ perm, const Groups gs,
+    float alpha, float gamma, const float *__restrict__ u, const float *__restrict__ omega,
+    float *__restrict__ g_pos, float *__restrict__ g_vel, float *__restrict__ g_mass,
+    float *__restrict__ g_h, float *__restrict__ g_u, float *__restrict__ g_rho,
+    float *__restrict__ g_omega) {
+  __shared__ HSide T[kWpb][kTile];
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  int range = 0;
+  for (int g; (g = next_group(gs, range)) >= 0;) {
+    const Group grp = group_at(gs, g);
+    const bool valid = lane < grp.count;
+    const int s = valid ? (gs.targets ? gs.targets[grp.t0 + lane] : grp.t0 + lane) : grp.t0;
+    HSide P;
+    P.xm = xm[s];
+    P.vh = vh[s];
+    P.aux = aux[s];
+    P.up = up[s];
+    const float hp = valid ? P.vh.w : -1.0f;
+    const bool p_on = valid && (P.up.x != 0.f || P.up.y != 0.f || P.up.z != 0.f || P.up.w != 0.f);
+    constexpr int kN = 11;
+    float acc[kN], cmp[kN];
+#pragma unroll
+    for (int k = 0; k < kN; ++k) acc[k] = cmp[k] = 0.0f;
+    int tc = 0, cand = 0;
+    auto flush = [&](int nc) {
+      if (lane < nc) {
+        T[w][lane].xm = xm[cand];
+        T[w][lane].vh = vh[cand];
+        T[w][lane].aux = aux[cand];
+        T[w][lane].up = up[cand];
+      } else {
+        T[w][lane].xm = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        T[w][lane].vh = make_float4(0.f, 0.f, 0.f, 0.f);
+        T[w][lane].aux = make_float4(0.f, 0.f, 1.f, 1.f);
+        T[w][lane].up = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      wave_sync();
+      float part[kN];
+#pragma unroll
+      for (int k = 0; k < kN; ++k) part[k] = 0.0f;
+      for (int k = 0; k < nc; ++k) {
+        const HSide Q = T[w][k];
+        const float dx = sub_exact(Q.xm.x, P.xm.x), dy = sub_exact(Q.xm.y, P.xm.y),
+                    dz = sub_exact(Q.xm.z, P.xm.z);  // x_q - x_p
+        const float r2 = dist2_exact(dx, dy, dz);
+        const bool in = valid && r2 < sq_exact(fmaxf(hp, Q.vh.w)) && r2 > 0.0f;
+        const bool q_on = Q.up.x != 0.f || Q.up.y != 0.f || Q.up.z != 0.f || Q.up.w != 0.f;
+        if (in && (p_on || q_on)) {
+          const float r = __builtin_amdgcn_sqrtf(r2);
+          float d[kN];
+          if (p_on) {  // target p, neighbour q: x = x_p - x_q
+            hydro_pair_partials(P, Q, alpha, -dx, -dy, -dz, r, 0, d);
+#pragma unroll
+            for (int k = 0; k < kN; ++k) part[k] += d[k];
+          }
+          if (q_on) {  // target q, neighbour p: x = x_q - x_p
+            hydro_pair_partials(Q, P, alpha, dx, dy, dz, r, 1, d);
+#pragma unroll
+            for (int k = 0; k < kN; ++k) part[k] += d[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kN; ++k) neumaier_add(acc[k], cmp[k], part[k]);
+      wave_sync();
+    };
+    int cur = grp.root;
+    while (cur < grp.end) {
+      const Node nd = nodes[cur];
+      const float hm = fmaxf(hp, nd.lo_h.w);
+      const bool want = valid && box_dist2(make_float3(P.xm.x, P.xm.y, P.xm.z), nd.lo_h,
+                                           nd.hi_l) < sq_exact(hm);
+      if (__ballot(want) == 0ull) {
+        cur = nd.meta.x;
+        continue;
+      }
+      if (!(nd.meta.w & kLeafBit) && nd.meta.z > kTile) {
+        ++cur;
+        continue;
+      }
+      int st = nd.meta.y, c = nd.meta.z;
+      while (c > 0) {
+        const int take = min(c, kTile - tc);
+        if (lane >= tc && lane < tc + take) cand = st + lane - tc;
+        tc += take;
+        st += take;
+        c -= take;
+        if (tc == kTile) {
+          flush(kTile);
+          tc = 0;
+        }
+      }
+      cur = nd.meta.x;
+    }
+    if (tc > 0) flush(tc);
+    if (valid) {
+      float tot[kN];
+#pragma unroll
+      for (int k = 0; k < kN; ++k) tot[k] = acc[k] + cmp[k];
+      const int cid = perm[s];
+      if (g_pos) {
+        g_pos[3 * cid] += tot[0];
+        g_pos[3 * cid + 1] += tot[1];
+        g_pos[3 * cid + 2] += tot[2];
+      }
+      if (g_vel) {
+        g_vel[3 * cid] += tot[3];
+        g_vel[3 * cid + 1] += tot[4];
+        g_vel[3 * cid + 2] += tot[5];
+      }
+      if (g_h) g_h[cid] += tot[6];
+      if (g_mass) g_mass[cid] += tot[10];
+      // A = (gamma-1) u / (Omega rho): dA/du = (gamma-1)/(Omega rho),
+      // dA/dOmega = -A/Omega, dA/drho = -A/rho; dc/du = c / (2u)
+      const float A = P.aux.x, cc = P.aux.y, rp = P.aux.z, up_ = u[cid], om = omega[cid];
+      const float gA = tot[7], gc = tot[8];
+      if (g_u) g_u[cid] += gA * (gamma - 1.0f) / (om * rp) + (up_ > 0.0f ? gc * cc / (2.0f * up_) : 0.0f);
+      if (g_omega) g_omega[cid] += -gA * A / om;
+      if (g_rho) g_rho[cid] += -gA * A / rp + tot[9];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_hydro_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                            const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                            const int32_t *active, float alpha, float gamma, const float *u,
+                            const float *omega, const float *g_acc, const float *g_dudt,
+                            float4 *up, float *g_pos, float *g_vel, float *g_mass, float *g_h,
+                            float *g_u, float *g_rho, float *g_omega, hipStream_t s) {
+  const int64_t m = gas.n;
+  if (m == 0) return hipSuccess;
+  k_zero_f4<<<nblk(m), kBlock, 0, s>>>(up, m);
+  const int64_t na = active ? n_act : n_caller;
+  if (na > 0)
+    k_hydro_bwd_up<<<nblk(na), kBlock, 0, s>>>(active, na, iperm, n_caller, g_acc, g_dudt, up);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_hydro_bwd<<<persistent_grid((const void *)k_hydro_bwd, kBlock, max_groups), kBlock, 0, s>>>(
+      gas.nodes, gas.xm, gas.vh, gas.aux, up, gas.perm, all_gas, alpha, gamma, u, omega, g_pos,
+      g_vel, g_mass, g_h, g_u, g_rho, g_omega);
+  return hipGetLastError();
+}
+
+hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_groups,
+                              const GravParams &gp, const float *g_acc, const float *g_pot,
+                              float4 *gsrc, float4 *gnode, double4 *pq, double *rr,
+                              float *g_pos, float *g_mass, hipStream_t s) {
+  const int64_t m = all.n, nn = all.nnodes;
+  if (m == 0 || nn == 0) return hipSuccess;
+  k_zero_f4<<<nblk(m), kBlock, 0, s>>>(gsrc, m);
+  k_zero_f4<<<nblk(nn), kBlock, 0, s>>>(gnode, nn);
+  if (max_groups > 0)
+    k_gravity_bwd<<<persistent_grid((const void *)k_gravity_bwd, kBlock, max_groups), kBlock, 0,
+                    s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
+                         gp.inside_test, g_acc, g_pot, gsrc, gnode);
+  k_push_init<<<nblk(nn), kBlock, 0, s>>>(gnode, all.mom, nn, pq, rr);
+  for (int l = 0; l < all.max_level; ++l)
+    k_push_level<<<nblk(nn), kBlock, 0, s>>>(all.nodes, all.mom, nn, l, pq, rr);
+  k_push_leaves<<<nblk(nn), kBlock, 0, s>>>(all.nodes, all.mom, nn, all.xm, pq, rr, gsrc);
+  k_scatter_grad<<<nblk(m), kBlock, 0, s>>>(all.perm, m, gsrc, g_pos, g_mass);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                              const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                              const int32_t *active, const float *h, const float *rho,
+                              const float *drho, const float *g_rho, const float *g_drho,
+                              const float *g_omega, float *g_pos, float *g_mass, float *g_h,
+                              hipStream_t s) {
+  const int64_t m = gas.n;
+  if (m == 0) return hipSuccess;
+  float4 *bw = gas.aux;  // (h, gbar_rho, gbar_rho', 0) per sorted gas member
+  k_density_bwd_init<<<nblk(m), kBlock, 0, s>>>(gas.perm, m, h, bw);
+  const int64_t na = active ? n_act : n_caller;
+  if (na > 0)
+    k_density_bwd_prep<<<nblk(na), kBlock, 0, s>>>(active, na, iperm, n_caller, h, rho, drho,
+                                                    g_rho, g_drho, g_omega, bw, g_h);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_density_bwd<<<persistent_grid((const void *)k_density_bwd, kBlock, max_groups), kBlock, 0,
+                  s>>>(gas.nodes, gas.xm, bw, gas.perm, all_gas, g_pos, g_mass, g_h);
+  return hipGetLastError();
+}
+
+}  // namespace g3

@@ -642,4 +642,104 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   return G3_OK;
 }
 
+int g3_density_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                        const g3_params *p, const float *h, const float *rho,
+                        const float *drho_dh, const float *g_rho, const float *g_drho_dh,
+                        const float *g_omega, float *g_pos, float *g_mass, float *g_h,
+                        void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_density_backward");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_density_backward: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_density_backward: FP32 trees only");
+  if (t->gas.n > 0 && (!h || !rho || !drho_dh))
+    return fail(c, G3_EINVAL, "g3_density_backward: h, rho and drho_dh are required");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  if (o.n == 0) return G3_OK;
+  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_backward prep");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
+  if (st) return st;
+  e = launch_density_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active, h, rho,
+                         drho_dh, g_rho, g_drho_dh, g_omega, g_pos, g_mass, g_h, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_backward");
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                            const g3_params *p, const float *vel, const float *u,
+                            const float *h, const float *rho, const float *omega,
+                            const float *g_acc, const float *g_dudt, float *g_pos, float *g_vel,
+                            float *g_mass, float *g_h, float *g_u, float *g_rho,
+                            float *g_omega, void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_hydro_force_backward");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_hydro_force_backward: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_hydro_force_backward: FP32 trees only");
+  if (t->gas.n > 0 && (!vel || !u || !h || !rho || !omega))
+    return fail(c, G3_EINVAL, "g3_hydro_force_backward: null input");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  if (o.n == 0) return G3_OK;
+  const SphParams sp = sph_params(p, t);
+  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_backward prep");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
+  if (st) return st;
+  float4 *up = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));
+  if (!up) return fail(c, G3_ENOMEM, "g3_hydro_force_backward: scratch allocation failed");
+  e = launch_hydro_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active, sp.alpha,
+                       sp.gamma, u, omega, g_acc, g_dudt, up, g_pos, g_vel, g_mass, g_h, g_u,
+                       g_rho, g_omega, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_backward");
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_gravity_backward(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
+                        const g3_params *p, const float *g_acc, const float *g_pot,
+                        float *g_pos, float *g_mass, void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_gravity_backward");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_gravity_backward: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_gravity_backward: FP32 trees only");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const Octree &o = t->all;
+  if (o.n == 0) return G3_OK;
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
+  if (st) return st;
+  float4 *gsrc = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));
+  float4 *gnode = (float4 *)scratch(c, kAdjNode, o.nnodes * sizeof(float4));
+  double4 *pq = (double4 *)scratch(c, kAdjPQ, o.nnodes * sizeof(double4));
+  double *rr = (double *)scratch(c, kAdjR, o.nnodes * sizeof(double));
+  if (!gsrc || !gnode || !pq || !rr)
+    return fail(c, G3_ENOMEM, "g3_gravity_backward: scratch allocation failed");
+  hipError_t e = launch_gravity_bwd(o, wk.gs, wk.max_groups, grav_params(p, t), g_acc, g_pot,
+                                    gsrc, gnode, pq, rr, g_pos, g_mass, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_gravity_backward");
+  c->err.clear();
+  return G3_OK;
+}
+
 }  // extern "C"

@@ -85,7 +85,7 @@ struct g3_ctx {
     void *p = nullptr;
     size_t bytes = 0;
   };
-  Buf scratch[16];
+  Buf scratch[24];
   unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
   int64_t *pinned = nullptr;               // host pinned readback slots [8]
   hipStream_t last_stream = nullptr;
@@ -97,7 +97,7 @@ namespace g3 {
 enum Slot {
   kSortKeys = 0, kSortVals, kSortTmp, kScanTmp, kCounts, kOffsets,
   kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
-  kSnapKeys, kSnapKeysAlt, kGroups,
+  kSnapKeys, kSnapKeysAlt, kGroups, kAdjSrc, kAdjNode, kAdjPQ, kAdjR,
   kNumSlots
 };
 
@@ -190,6 +190,30 @@ struct GravParams {
 hipError_t launch_gravity(const Octree &all, const Groups &gs, int64_t max_groups,
                           const GravParams &gp, float *acc, float *pot, int32_t *nterms,
                           hipStream_t s);
+
+// Adjoints. Gradients are ADDED to the caller-order arrays (nullable).
+// Density: every gas member walks its symmetric neighbourhood (all_gas:
+// the groups of every gas member); the node hmax must be refit from h.
+hipError_t launch_density_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                              const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                              const int32_t *active, const float *h, const float *rho,
+                              const float *drho, const float *g_rho, const float *g_drho,
+                              const float *g_omega, float *g_pos, float *g_mass, float *g_h,
+                              hipStream_t s);
+// Hydro: like the density (every gas member, symmetric walk) after the
+// hydro prep of vh and aux; scratch up [n_gas].
+hipError_t launch_hydro_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                            const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                            const int32_t *active, float alpha, float gamma, const float *u,
+                            const float *omega, const float *g_acc, const float *g_dudt,
+                            float4 *up, float *g_pos, float *g_vel, float *g_mass, float *g_h,
+                            float *g_u, float *g_rho, float *g_omega, hipStream_t s);
+// Gravity over the active targets `gs`; scratch gsrc [n], gnode [nnodes],
+// pq [nnodes], rr [nnodes].
+hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_groups,
+                              const GravParams &gp, const float *g_acc, const float *g_pot,
+                              float4 *gsrc, float4 *gnode, double4 *pq, double *rr,
+                              float *g_pos, float *g_mass, hipStream_t s);
 
 // Walk lists: counts pass (list == nullptr) or fill pass.
 hipError_t launch_walk(const Octree &o, int kind, const Groups &gs, const int32_t *rows,

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
 # every symbol include/g3.h declares
 EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
            "g3_build_tree", "g3_build_forest", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
-           "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity")
+           "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
+           "g3_density_backward", "g3_hydro_force_backward", "g3_gravity_backward")
 
 
 class g3_params(ctypes.Structure):
@@ -73,6 +74,9 @@ def lib():
             "g3_density": ([P, P, i64, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
             "g3_hydro_force": ([P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_gravity": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
+            "g3_density_backward": ([P, P, i64, P, P] + [P] * 10, ctypes.c_int),
+            "g3_hydro_force_backward": ([P, P, i64, P, P] + [P] * 15, ctypes.c_int),
+            "g3_gravity_backward": ([P, P, i64, P, P] + [P] * 5, ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -185,3 +189,29 @@ def g3_gravity(ctx, tree, n_act, active, params, acc, pot, nterms, stream):
     st = lib().g3_gravity(ctx, tree, int(n_act), active or None, ctypes.byref(params),
                           acc or None, pot or None, nterms or None, stream)
     _check(ctx, st, "g3_gravity")
+
+
+def g3_density_backward(ctx, tree, n_act, active, params, h, rho, drho_dh, g_rho, g_drho_dh,
+                        g_omega, g_pos, g_mass, g_h, stream):
+    st = lib().g3_density_backward(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                                   h or None, rho or None, drho_dh or None, g_rho or None,
+                                   g_drho_dh or None, g_omega or None, g_pos or None,
+                                   g_mass or None, g_h or None, stream)
+    _check(ctx, st, "g3_density_backward")
+
+
+def g3_hydro_force_backward(ctx, tree, n_act, active, params, vel, u, h, rho, omega, g_acc,
+                            g_dudt, g_pos, g_vel, g_mass, g_h, g_u, g_rho, g_omega, stream):
+    st = lib().g3_hydro_force_backward(
+        ctx, tree, int(n_act), active or None, ctypes.byref(params), vel or None, u or None,
+        h or None, rho or None, omega or None, g_acc or None, g_dudt or None, g_pos or None,
+        g_vel or None, g_mass or None, g_h or None, g_u or None, g_rho or None, g_omega or None,
+        stream)
+    _check(ctx, st, "g3_hydro_force_backward")
+
+
+def g3_gravity_backward(ctx, tree, n_act, active, params, g_acc, g_pot, g_pos, g_mass, stream):
+    st = lib().g3_gravity_backward(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                                   g_acc or None, g_pot or None, g_pos or None, g_mass or None,
+                                   stream)
+    _check(ctx, st, "g3_gravity_backward")

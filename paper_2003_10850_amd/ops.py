@@ -199,3 +199,107 @@ def walk(tree: Tree, kind: int, params=None, h=None, active=None, capacity=None)
         st, total = g3.g3_walk(tree.ctx.handle, tree.handle, kind, na, ap, _ptr(h), p, total,
                                offsets.data_ptr(), lst.data_ptr(), _stream(dev))
     return offsets, lst[:total], st
+
+
+# ------------------------------------------------------------- autograd
+
+def _grad_buf(tree, *shape):
+    return torch.zeros(*shape, dtype=torch.float32, device=tree.ctx.device)
+
+
+class _DensityFn(torch.autograd.Function):
+    """rho, drho/dh, Omega at the given h (no solve) as a differentiable
+    function of (pos, mass, h); the backward is g3_density_backward."""
+
+    @staticmethod
+    def forward(fctx, tree, params, active, pos, mass, h):
+        d = density(tree, params, h=h, active=active, solve_h=False)
+        fctx.tree, fctx.params, fctx.active = tree, params, active
+        fctx.save_for_backward(h, d["rho"], d["drho_dh"])
+        return d["rho"], d["drho_dh"], d["omega"]
+
+    @staticmethod
+    def backward(fctx, g_rho, g_drho, g_omega):
+        tree = fctx.tree
+        h, rho, drho = fctx.saved_tensors
+        n = tree.n
+        gp, gm, gh = _grad_buf(tree, n, 3), _grad_buf(tree, n), _grad_buf(tree, n)
+        na, ap = _active(tree, fctx.active)
+        c = lambda t: None if t is None else t.contiguous()
+        g_rho, g_drho, g_omega = c(g_rho), c(g_drho), c(g_omega)
+        g3.g3_density_backward(tree.ctx.handle, tree.handle, na, ap,
+                               g3.g3_params.of(fctx.params or tree.params), _ptr(h), _ptr(rho),
+                               _ptr(drho), _ptr(g_rho), _ptr(g_drho), _ptr(g_omega), _ptr(gp),
+                               _ptr(gm), _ptr(gh), _stream(tree.ctx.device))
+        return None, None, None, gp, gm, gh
+
+
+class _HydroFn(torch.autograd.Function):
+    """acc, du/dt as a differentiable function of (pos, vel, mass, u, h, rho,
+    omega); the backward is g3_hydro_force_backward."""
+
+    @staticmethod
+    def forward(fctx, tree, params, active, pos, vel, mass, u, h, rho, omega):
+        r = hydro_force(tree, vel, u, h, rho, omega, params=params, active=active)
+        fctx.tree, fctx.params, fctx.active = tree, params, active
+        fctx.save_for_backward(vel, u, h, rho, omega)
+        return r["acc"], r["dudt"]
+
+    @staticmethod
+    def backward(fctx, g_acc, g_dudt):
+        tree = fctx.tree
+        vel, u, h, rho, omega = fctx.saved_tensors
+        n = tree.n
+        out = [_grad_buf(tree, n, 3), _grad_buf(tree, n, 3), _grad_buf(tree, n),
+               _grad_buf(tree, n), _grad_buf(tree, n), _grad_buf(tree, n), _grad_buf(tree, n)]
+        gpos, gvel, gmass, gh, gu, grho, gom = out
+        na, ap = _active(tree, fctx.active)
+        c = lambda t: None if t is None else t.contiguous()
+        g3.g3_hydro_force_backward(tree.ctx.handle, tree.handle, na, ap,
+                                   g3.g3_params.of(fctx.params or tree.params), _ptr(vel),
+                                   _ptr(u), _ptr(h), _ptr(rho), _ptr(omega), _ptr(c(g_acc)),
+                                   _ptr(c(g_dudt)), _ptr(gpos), _ptr(gvel), _ptr(gmass),
+                                   _ptr(gh), _ptr(gu), _ptr(grho), _ptr(gom),
+                                   _stream(tree.ctx.device))
+        return None, None, None, gpos, gvel, gmass, gu, gh, grho, gom
+
+
+class _GravityFn(torch.autograd.Function):
+    """acc, pot as a differentiable function of (pos, mass); the backward is
+    g3_gravity_backward (opening decisions of the forward held fixed)."""
+
+    @staticmethod
+    def forward(fctx, tree, params, active, pos, mass):
+        r = gravity(tree, params=params, active=active)
+        fctx.tree, fctx.params, fctx.active = tree, params, active
+        return r["acc"], r["pot"]
+
+    @staticmethod
+    def backward(fctx, g_acc, g_pot):
+        tree = fctx.tree
+        n = tree.n
+        gp, gm = _grad_buf(tree, n, 3), _grad_buf(tree, n)
+        na, ap = _active(tree, fctx.active)
+        c = lambda t: None if t is None else t.contiguous()
+        g3.g3_gravity_backward(tree.ctx.handle, tree.handle, na, ap,
+                               g3.g3_params.of(fctx.params or tree.params), _ptr(c(g_acc)),
+                               _ptr(c(g_pot)), _ptr(gp), _ptr(gm), _stream(tree.ctx.device))
+        return None, None, None, gp, gm
+
+
+def density_ad(tree: Tree, pos, mass, h, params=None, active=None):
+    """Differentiable (rho, drho_dh, omega) at the given h. pos and mass must
+    be the tensors `tree` was built from (the kernels read the tree's sorted
+    copies); gradients flow to pos, mass and h."""
+    _need(h, torch.float32, (tree.n,), "h", tree.ctx.device)
+    return _DensityFn.apply(tree, params, active, pos, mass, h)
+
+
+def hydro_force_ad(tree: Tree, pos, vel, mass, u, h, rho, omega, params=None, active=None):
+    """Differentiable (acc, dudt); gradients flow to every tensor argument."""
+    return _HydroFn.apply(tree, params, active, pos, vel, mass, u, h, rho, omega)
+
+
+def gravity_ad(tree: Tree, pos, mass, params=None, active=None):
+    """Differentiable (acc, pot); gradients flow to pos and mass."""
+    return _GravityFn.apply(tree, params, active, pos, mass)
