@@ -310,6 +310,55 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     }
 
 
+def run_differentiation(dev, steps: int, warmup: int, n: int = 1 << 20, seed: int = 4) -> dict:
+    """The differentiation workload: N = 2^20 clustered particles (as the
+    plain workload), loss = sum over gas of (log rho)^2 + total potential
+    energy, at h from the density solve. One step = the loss forward
+    (density at the given h, gravity) and its backward through the adjoint
+    kernels, which recompute the walks instead of storing lists."""
+    import torch
+    from paper_2003_10850_amd import inputs, ops
+
+    w = inputs.plummer(n=n, n_spheres=32, seed=seed)
+    pos32, _, m32, _ = w.as_f32()
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, mass, typ = T(pos32), T(m32), T(w.type)
+    ctx = ops.Context(dev)
+    tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
+    h = ops.density(tree)["h"].detach()
+    gas = T(w.type == 0)
+    pos.requires_grad_(True)
+    mass.requires_grad_(True)
+    h.requires_grad_(True)
+
+    def step():
+        pos.grad = mass.grad = h.grad = None
+        rho, _, _ = ops.density_ad(tree, pos, mass, h)
+        _, pot = ops.gravity_ad(tree, pos, mass)
+        L = (torch.log(rho[gas]) ** 2).sum() + 0.5 * (mass * pot).sum()
+        L.backward()
+        return L
+
+    for _ in range(max(warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ctx.nonconverged(reset=True)
+    print(f"bench: differentiation {ms:.3f} ms/step (loss {float(L):.6e})", file=sys.stderr,
+          flush=True)
+    return {
+        "workload": f"{w.name}: N={n} clustered as the plain workload, FP32; loss = sum_gas "
+                    "(log rho)^2 + (1/2) sum m phi at the solved h",
+        "ms_per_step": ms,
+        "step": "forward (density at h, gravity) + backward (density and gravity adjoints, "
+                "walks recomputed) for dL/dpos, dL/dmass, dL/dh",
+    }
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -332,6 +381,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched (forest of snapshots) measurement")
+    ap.add_argument("--no-differentiation", action="store_true",
+                    help="skip the loss forward + backward measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -455,6 +506,8 @@ def main() -> int:
     }
     if not args.no_batched:
         line["batched"] = run_batched(dev, args.steps, args.warmup)
+    if not args.no_differentiation:
+        line["differentiation"] = run_differentiation(dev, args.steps, args.warmup)
     if args.copy_calibration:
         copy_calibration(dev)
     if not args.no_cpu_baseline:

@@ -2,10 +2,14 @@
 torch.autograd) against the oracle's adjoints, and of the whole loss
 gradient against central finite differences of the FP64 oracle forward.
 
-Bar: every gradient entry within 1e-5 of the oracle's L1 sum of the
+Bar: every gradient entry within 1e-5 of the oracle's L1 sum S of the
 contributions to that entry (the same bar as the forward forces: FP32
-terms, compensated sums), on the same seeded inputs and the same neighbour
-and opening decisions (FP32 predicates on both sides).
+terms, compensated sums), plus a floor of 1e-7 of the median S of the
+array: an entry fed only by pairs at the very edge of the kernel support
+(values 1e-18 against typical 1e2) carries the FP32 conditioning of
+(1 - q)^k there, a relative error up to ~1e-3 on a value far below FP32
+resolution of the array. Same seeded inputs and the same neighbour and
+opening decisions (FP32 predicates on both sides).
 """
 import numpy as np
 import pytest
@@ -36,8 +40,9 @@ def host(t):
 
 def check(name, got, ref, S, tol=TOL):
     err = np.abs(got - ref)
+    floor = 1e-7 * np.median(S[S > 0]) if np.any(S > 0) else 0.0
+    bad = err > tol * S + floor
     S = np.maximum(S, 1e-300)
-    bad = err > tol * S + 1e-30
     worst = (err / S).max() if err.size else 0.0
     print(f"{name}: max |err|/S = {worst:.2e}", flush=True)
     assert not bad.any(), f"{name}: {bad.sum()} entries beyond {tol} S (worst {worst:.2e})"
@@ -70,12 +75,16 @@ def test_density_backward(ctx, frac):
     g_rho, g_dr, g_om = (rng.normal(size=w.n).astype(np.float32) for _ in range(3))
     gp, gm, gh = (torch.zeros(s, device="cuda:0") for s in ((w.n, 3), w.n, w.n))
     na = w.n if act is None else act.size
-    ap = 0 if act is None else dev_t(act).data_ptr()
+    # every device input stays referenced until the call has run
+    keep = dict(h=dev_t(h), g_rho=dev_t(g_rho), g_dr=dev_t(g_dr), g_om=dev_t(g_om),
+                act=None if act is None else dev_t(act))
+    ap = 0 if act is None else keep["act"].data_ptr()
     g3.g3_density_backward(ctx.handle, c.tree.handle, na, ap, g3.g3_params.of(w.params),
-                           dev_t(h).data_ptr(), d["rho"].data_ptr(), d["drho_dh"].data_ptr(),
-                           dev_t(g_rho).data_ptr(), dev_t(g_dr).data_ptr(),
-                           dev_t(g_om).data_ptr(), gp.data_ptr(), gm.data_ptr(), gh.data_ptr(),
+                           keep["h"].data_ptr(), d["rho"].data_ptr(), d["drho_dh"].data_ptr(),
+                           keep["g_rho"].data_ptr(), keep["g_dr"].data_ptr(),
+                           keep["g_om"].data_ptr(), gp.data_ptr(), gm.data_ptr(), gh.data_ptr(),
                            torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
     # the oracle's adjoint at the same (FP32) h, rho and drho/dh from the oracle
     z = lambda a: np.where(np.isin(np.arange(w.n), act_gas), a, 0.0)
     ref = oracle.density_backward(c.gt, w.params, h.astype(np.float64), z(g_rho), z(g_dr),
