@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -118,17 +119,20 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 namespace {
 
-// Group table of one launch (one workgroup): snapshot k's targets start at
-// tstart[k] (its sorted start soff[k] counted through the compaction scan
-// `slot`, or soff[k] itself when every member is a target) and form
-// ceil(T_k / 64) groups starting at gstart[k]. Also clears the work queue.
+// Group table of one launch with one segment per snapshot (one
+// workgroup): snapshot k's targets start at tstart[k] (its sorted start
+// soff[k] counted through the compaction scan `slot`, or soff[k] itself when
+// every member is a target) and form ceil(T_k / 64) groups starting at
+// gstart[k]. Also clears the work queue.
 constexpr int kTableBlock = 1024;
 __global__ __launch_bounds__(kTableBlock) void k_group_table(
     const int32_t *__restrict__ soff, int n_snap, const uint32_t *__restrict__ slot,
-    int32_t *__restrict__ tstart, int32_t *__restrict__ gstart, unsigned *__restrict__ queue) {
+    int32_t *__restrict__ tstart, int32_t *__restrict__ gstart, int32_t *__restrict__ seg_snap,
+    int32_t *__restrict__ nseg, unsigned *__restrict__ queue) {
   __shared__ int32_t part[kTableBlock];
   const int tid = (int)threadIdx.x;
   if (tid < 8) queue[tid] = 0u;
+  if (tid == 0) *nseg = n_snap;
   const int per = (n_snap + kTableBlock - 1) / kTableBlock;
   const int k0 = min(tid * per, n_snap), k1 = min(k0 + per, n_snap);
   auto first = [&](int k) { return slot ? (int32_t)slot[soff[k]] : soff[k]; };
@@ -147,6 +151,7 @@ __global__ __launch_bounds__(kTableBlock) void k_group_table(
     const int32_t f = first(k);
     tstart[k] = f;
     gstart[k] = base;
+    seg_snap[k] = k;
     base += (first(k + 1) - f + kWave - 1) / kWave;
   }
   if (tid == kTableBlock - 1) {
@@ -155,10 +160,64 @@ __global__ __launch_bounds__(kTableBlock) void k_group_table(
   }
 }
 
+// Split groups: target t starts a segment when it is the first target, or
+// its snapshot or its level-`level` key cell differs from target t-1's.
+// ntarg: device count of the targets (nullptr: max_t, every member).
+__global__ void k_seg_flags(const int32_t *__restrict__ targets,
+                            const uint32_t *__restrict__ ntarg, int64_t max_t,
+                            const uint64_t *__restrict__ keys, const int32_t *__restrict__ soff,
+                            int n_snap, int level, uint32_t *__restrict__ flags) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > max_t) return;
+  const int64_t T = ntarg ? (int64_t)*ntarg : max_t;
+  if (t >= T) {
+    flags[t] = 0u;
+    return;
+  }
+  if (t == 0) {
+    flags[t] = 1u;
+    return;
+  }
+  const int s = targets ? targets[t] : (int)t, p = targets ? targets[t - 1] : (int)(t - 1);
+  const int sh = 3 * (kMaxLevel - level);
+  const bool cut = segment_of(soff, n_snap, s) != segment_of(soff, n_snap, p) ||
+                   (keys[s] >> sh) != (keys[p] >> sh);
+  flags[t] = cut ? 1u : 0u;
+}
+
+__global__ void k_seg_starts(const uint32_t *__restrict__ flags,
+                             const uint32_t *__restrict__ segid,
+                             const int32_t *__restrict__ targets,
+                             const uint32_t *__restrict__ ntarg, int64_t max_t,
+                             const int32_t *__restrict__ soff, int n_snap,
+                             int32_t *__restrict__ tstart, int32_t *__restrict__ seg_snap,
+                             int32_t *__restrict__ nseg, unsigned *__restrict__ queue) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    const int32_t ns = (int32_t)segid[max_t];
+    const int64_t T = ntarg ? (int64_t)*ntarg : max_t;
+    *nseg = ns;
+    tstart[ns] = (int32_t)T;
+    for (int r = 0; r < 8; ++r) queue[r] = 0u;
+  }
+  if (t >= max_t || !flags[t]) return;
+  const uint32_t k = segid[t];
+  const int s = targets ? targets[t] : (int)t;
+  tstart[k] = (int32_t)t;
+  seg_snap[k] = segment_of(soff, n_snap, s);
+}
+
+__global__ void k_seg_groups(const int32_t *__restrict__ tstart, const int32_t *__restrict__ nseg,
+                             int64_t max_seg, uint32_t *__restrict__ gcnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > max_seg) return;
+  gcnt[k] = k < *nseg ? (uint32_t)((tstart[k + 1] - tstart[k] + kWave - 1) / kWave) : 0u;
+}
+
 }  // namespace
 
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
-                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s) {
+                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s, int split) {
   *w = Work();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
@@ -166,10 +225,10 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
   int32_t *tg = nullptr, *rw = nullptr;
   uint32_t *slot = nullptr;
   if (active) {
-    uint32_t *mark = (uint32_t *)scratch(c, kFlags, (m + 1) * sizeof(uint32_t));
+    uint32_t *mark = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
     slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
-    int32_t *rowp1 = (int32_t *)scratch(c, kCounts, (m + 1) * sizeof(int32_t));
-    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m) * sizeof(uint32_t));
+    int32_t *rowp1 = (int32_t *)scratch(c, kCounts, (m + 2) * sizeof(int32_t));
+    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m + 1) * sizeof(uint32_t));
     tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
     rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
     if (!mark || !slot || !rowp1 || !stmp || !tg || !rw)
@@ -181,22 +240,54 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
     if (e != hipSuccess) return hip_fail(c, e, "active-set scan");
     k_compact<<<nblk(m), 256, 0, s>>>(mark, slot, rowp1, m, tg, rw);
   }
-  int32_t *tab = (int32_t *)scratch(c, kGroups, (2 * ((size_t)n_snap + 1) + 8) * sizeof(int32_t));
+  const int64_t max_t = active ? std::min<int64_t>(n_act, m) : m;
+  const uint32_t *ntarg = active ? slot + m : nullptr;
+  const int64_t max_seg = split >= 0 ? std::max<int64_t>(max_t, 1) : n_snap;
+  // tstart, gstart [max_seg + 2] (a scan writes one past its n), seg_snap
+  // [max_seg + 1], nseg, queue [8]
+  const size_t tab_elems = 3 * ((size_t)max_seg + 2) + 1 + 8;
+  int32_t *tab = (int32_t *)scratch(c, kGroups, tab_elems * sizeof(int32_t));
   if (!tab) return fail(c, G3_ENOMEM, "device allocation of the group table failed");
-  int32_t *tstart = tab, *gstart = tab + n_snap + 1;
-  unsigned *queue = (unsigned *)(gstart + n_snap + 1);
-  k_group_table<<<1, kTableBlock, 0, s>>>(o.soff, n_snap, slot, tstart, gstart, queue);
+  int32_t *tstart = tab, *gstart = tab + max_seg + 2, *seg_snap = gstart + max_seg + 2;
+  int32_t *nseg = seg_snap + max_seg + 2;
+  unsigned *queue = (unsigned *)(nseg + 1);
+  if (split < 0) {
+    k_group_table<<<1, kTableBlock, 0, s>>>(o.soff, n_snap, slot, tstart, gstart, seg_snap, nseg,
+                                            queue);
+  } else {
+    // the compaction's scratch (mark, rowp1) is free again here
+    uint32_t *flags = (uint32_t *)scratch(c, kCounts, (m + 2) * sizeof(uint32_t));
+    uint32_t *segid = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
+    uint32_t *gcnt = (uint32_t *)scratch(c, kIds, (max_seg + 2) * sizeof(uint32_t));
+    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp,
+                                         scan_tmp_elems(std::max(max_t, max_seg) + 1) *
+                                             sizeof(uint32_t));
+    if (!flags || !segid || !gcnt || !stmp)
+      return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+    const int level = std::min(split, (int)kMaxLevel);
+    k_seg_flags<<<nblk(max_t + 1), 256, 0, s>>>(tg, ntarg, max_t, o.keys, o.soff, n_snap, level,
+                                               flags);
+    hipError_t e = scan_u32(flags, segid, max_t + 1, stmp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "group split scan");
+    k_seg_starts<<<nblk(max_t + 1), 256, 0, s>>>(flags, segid, tg, ntarg, max_t, o.soff, n_snap,
+                                                 tstart, seg_snap, nseg, queue);
+    k_seg_groups<<<nblk(max_seg + 1), 256, 0, s>>>(tstart, nseg, max_seg, gcnt);
+    e = scan_u32(gcnt, (uint32_t *)gstart, max_seg + 1, stmp, s);
+    if (e != hipSuccess) return hip_fail(c, e, "group split scan");
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "group table");
   w->gs.targets = tg;
   w->gs.tstart = tstart;
   w->gs.gstart = gstart;
+  w->gs.seg_snap = seg_snap;
+  w->gs.nseg = nseg;
   w->gs.nroot = o.nroot;
   w->gs.sbox = t->sbox;
   w->gs.queue = queue;
   w->gs.n_snap = n_snap;
   w->rows = rw;
-  w->max_groups = max_groups_of(active ? std::min<int64_t>(n_act, m) : m, n_snap);
+  w->max_groups = split >= 0 ? max_t : max_groups_of(max_t, n_snap);
   return G3_OK;
 }
 
@@ -478,25 +569,38 @@ static GravParams grav_params(const g3_params *p, const g3_tree *t) {
   return gp;
 }
 
-// Tuning knob (never result-defining): SPH walks stop descending at
-// subtrees of at most this many members and scan them whole.
-static int walk_leaf_from_env() {
-  static int v = [] {
-    const char *e = std::getenv("G3_WALK_LEAF");
-    int x = e ? std::atoi(e) : 64;
-    return x < 1 ? 1 : (x > 4096 ? 4096 : x);
-  }();
-  return v;
+static int size_class(int64_t n) {
+  int k = 0;
+  while (k < 62 && (int64_t(1) << (k + 1)) <= n) ++k;
+  return k;
 }
 
-static SphParams sph_params(const g3_params *p, const g3_tree *t) {
+// Launch tuning of a call of `kind` over n targets: the autotuned choice
+// of the same size class (floor(log2 n)), else of the nearest tuned class
+// of that kind, else the defaults.
+static Tuning tuning_for(const g3_ctx *c, int kind, int64_t n) {
+  const int cls = size_class(n);
+  const Tuning *best = nullptr;
+  int dist = 1 << 30;
+  for (const auto &kv : c->tuning) {
+    if (kv.first.first != kind) continue;
+    const int d = std::abs(kv.first.second - cls);
+    if (d < dist) {
+      dist = d;
+      best = &kv.second;
+    }
+  }
+  return best ? *best : Tuning();
+}
+
+static SphParams sph_params(const g3_params *p, const g3_tree *t, const Tuning &tu) {
   SphParams sp;
   sp.n_ngb = (float)p->n_ngb;
   sp.h_tol = (float)p->h_tol;
   sp.gamma = (float)p->gamma;
   sp.alpha = (float)p->alpha;
   sp.max_iter = 64;
-  sp.walk_leaf = walk_leaf_from_env();
+  sp.walk_leaf = tu.walk_leaf;
   sp.f64 = t->f64;
   sp.slack = t->slack;
   return sp;
@@ -582,11 +686,12 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const Octree &o = t->gas;
+  const Tuning tu = tuning_for(c, kTuneDensity, active ? std::min<int64_t>(n_act, o.n) : o.n);
   Work wk;
-  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s);
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
-  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(p, t), solve_h ? 1 : 0, h,
-                                rho, drho_dh, omega, nngb, c->counters, s);
+  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(p, t, tu), solve_h ? 1 : 0,
+                                h, rho, drho_dh, omega, nngb, c->counters, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
   return G3_OK;
@@ -608,12 +713,13 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   Octree &o = t->gas;
-  const SphParams sp = sph_params(p, t);
+  const Tuning tu = tuning_for(c, kTuneHydro, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  const SphParams sp = sph_params(p, t, tu);
   hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
   if (e == hipSuccess) e = refit_hmax(o, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
   Work wk;
-  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s);
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
   e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force");
@@ -633,13 +739,183 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const Octree &o = t->all;
+  const Tuning tu = tuning_for(c, kTuneGravity, active ? std::min<int64_t>(n_act, o.n) : o.n);
   Work wk;
-  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
+  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s, tu.split);
   if (st) return st;
   hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
   c->err.clear();
   return G3_OK;
+}
+
+int g3_tuning_get(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t *walk_leaf,
+                  int32_t *split) {
+  if (!c) return G3_EINVAL;
+  if (kind < 0 || kind >= kTuneKinds) return fail(c, G3_EINVAL, "g3_tuning_get: bad kind");
+  const Tuning tu = tuning_for(c, kind, n_targets);
+  if (walk_leaf) *walk_leaf = tu.walk_leaf;
+  if (split) *split = tu.split;
+  return G3_OK;
+}
+
+int g3_tuning_set(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t walk_leaf,
+                  int32_t split) {
+  if (!c) return G3_EINVAL;
+  if (kind < 0 || kind >= kTuneKinds || walk_leaf < 1 || walk_leaf > 4096 || split < -1 ||
+      split > kMaxLevel)
+    return fail(c, G3_EINVAL, "g3_tuning_set: bad arguments");
+  Tuning tu;
+  tu.walk_leaf = walk_leaf;
+  tu.split = split;
+  if (n_targets < 0) {  // every size class of this kind: one entry
+    for (auto it = c->tuning.begin(); it != c->tuning.end();)
+      it = it->first.first == kind ? c->tuning.erase(it) : std::next(it);
+    c->tuning[{kind, 0}] = tu;
+  } else {
+    c->tuning[{kind, size_class(n_targets)}] = tu;
+  }
+  return G3_OK;
+}
+
+// Time one candidate: `run` enqueues the kernel(s); the second of two runs
+// is timed with events on the stream.
+static int time_candidate(g3_ctx *c, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                          const std::function<hipError_t()> &run, float *ms) {
+  hipError_t e = run();
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = run();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_autotune");
+  return G3_OK;
+}
+
+int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, const g3_params *p,
+                const void *h, const float *vel, const float *u, const float *rho,
+                const float *omega, void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_autotune");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_autotune: bad params");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  static const int kLeaves[] = {16, 32, 64, 128};
+  static const int kSplits[] = {-1, 2, 3, 4, 5};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(c, G3_EHIP, "g3_autotune: event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, G3_EHIP, "g3_autotune: event");
+  }
+  // the tuning runs leave the solve counters as they were
+  unsigned long long saved[8];
+  hipError_t e = hipMemcpyAsync(saved, c->counters, sizeof(saved), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return hip_fail(c, e, "g3_autotune");
+  }
+  const size_t hsz = t->f64 ? sizeof(double) : sizeof(float);
+  auto finish = [&](int code) {
+    (void)hipMemcpyAsync(c->counters, saved, sizeof(saved), hipMemcpyHostToDevice, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return code;
+  };
+  Octree &gas = t->gas;
+  const int64_t ng = active ? std::min<int64_t>(n_act, gas.n) : gas.n;
+  // density, with the h solve on a copy of h
+  if (gas.n > 0 && h) {
+    void *hs = scratch(c, kAdjPQ, (size_t)t->n * hsz);
+    if (!hs) return finish(fail(c, G3_ENOMEM, "g3_autotune: allocation failed"));
+    Tuning best;
+    float best_ms = INFINITY;
+    for (int leaf : kLeaves)
+      for (int split : kSplits) {
+        Tuning tu;
+        tu.walk_leaf = leaf;
+        tu.split = split;
+        Work wk;
+        float ms = 0.f;
+        st = time_candidate(c, s, e0, e1, [&]() -> hipError_t {
+          hipError_t r = hipMemcpyAsync(hs, h, (size_t)t->n * hsz, hipMemcpyDeviceToDevice, s);
+          if (r != hipSuccess) return r;
+          if (prepare_work(c, t, gas, t->iperm_gas, n_act, active, &wk, s, tu.split))
+            return hipErrorUnknown;
+          return launch_density(gas, wk.gs, wk.max_groups, sph_params(p, t, tu), 1, hs, nullptr,
+                                nullptr, nullptr, nullptr, c->counters, s);
+        }, &ms);
+        if (st) return finish(st);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = tu;
+        }
+      }
+    c->tuning[{kTuneDensity, size_class(ng)}] = best;
+  }
+  // hydro, when its inputs are given
+  if (gas.n > 0 && h && vel && u && rho && omega) {
+    const SphParams base = sph_params(p, t, Tuning());
+    e = launch_hydro_prep(gas, vel, u, h, rho, omega, base.gamma, t->f64, s);
+    if (e == hipSuccess) e = refit_hmax(gas, s);
+    if (e != hipSuccess) return finish(hip_fail(c, e, "g3_autotune"));
+    Tuning best;
+    float best_ms = INFINITY;
+    for (int leaf : kLeaves)
+      for (int split : kSplits) {
+        Tuning tu;
+        tu.walk_leaf = leaf;
+        tu.split = split;
+        Work wk;
+        float ms = 0.f;
+        st = time_candidate(c, s, e0, e1, [&]() -> hipError_t {
+          if (prepare_work(c, t, gas, t->iperm_gas, n_act, active, &wk, s, tu.split))
+            return hipErrorUnknown;
+          return launch_hydro(gas, wk.gs, wk.max_groups, sph_params(p, t, tu), nullptr, nullptr,
+                              nullptr, nullptr, s);
+        }, &ms);
+        if (st) return finish(st);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = tu;
+        }
+      }
+    c->tuning[{kTuneHydro, size_class(ng)}] = best;
+  }
+  // gravity
+  const Octree &all = t->all;
+  if (all.n > 0) {
+    const int64_t na = active ? std::min<int64_t>(n_act, all.n) : all.n;
+    Tuning best;
+    float best_ms = INFINITY;
+    for (int split : kSplits) {
+      Tuning tu;
+      tu.split = split;
+      Work wk;
+      float ms = 0.f;
+      st = time_candidate(c, s, e0, e1, [&]() -> hipError_t {
+        if (prepare_work(c, t, all, t->iperm_all, n_act, active, &wk, s, tu.split))
+          return hipErrorUnknown;
+        return launch_gravity(all, wk.gs, wk.max_groups, grav_params(p, t), nullptr, nullptr,
+                              nullptr, s);
+      }, &ms);
+      if (st) return finish(st);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = tu;
+      }
+    }
+    c->tuning[{kTuneGravity, size_class(na)}] = best;
+  }
+  c->err.clear();
+  return finish(G3_OK);
 }
 
 int g3_density_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
@@ -694,7 +970,7 @@ int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
   c->last_stream = s;
   Octree &o = t->gas;
   if (o.n == 0) return G3_OK;
-  const SphParams sp = sph_params(p, t);
+  const SphParams sp = sph_params(p, t, Tuning());
   hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, 0, s);
   if (e == hipSuccess) e = refit_hmax(o, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_backward prep");

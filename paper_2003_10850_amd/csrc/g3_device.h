@@ -89,13 +89,13 @@ struct Group {
 
 __device__ __forceinline__ Group group_at(const Groups &gs, int g) {
   Group G;
-  const int k = segment_of(gs.gstart, gs.n_snap, g);
+  const int k = segment_of(gs.gstart, *gs.nseg, g);
   const int t1 = gs.tstart[k + 1];
   G.t0 = gs.tstart[k] + (g - gs.gstart[k]) * 64;
   G.count = min(64, t1 - G.t0);
-  G.snap = k;
-  G.root = gs.nroot[k];
-  G.end = gs.nroot[k + 1];
+  G.snap = gs.seg_snap[k];
+  G.root = gs.nroot[G.snap];
+  G.end = gs.nroot[G.snap + 1];
   return G;
 }
 
@@ -108,7 +108,7 @@ __device__ __forceinline__ Group group_at(const Groups &gs, int g) {
 // after at most (its groups + 8) atomic increments.
 __device__ __forceinline__ int next_group(const Groups &gs, int &range) {
   constexpr int kXcd = 8;
-  const int total = gs.gstart[gs.n_snap];
+  const int total = gs.gstart[*gs.nseg];
   const int home = (int)(blockIdx.x % kXcd);
   while (range < kXcd) {
     const int r = (home + range) % kXcd;

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "g3.h"
@@ -54,6 +56,15 @@ struct Octree {
   int64_t cap_snap = 0;
 };
 
+// Launch choices that never change a count or a decision (only the order in
+// which FP32 partial sums are formed): SPH walks take subtrees of at most
+// walk_leaf members whole; split >= 0 cuts groups at level-`split` cells.
+struct Tuning {
+  int walk_leaf = 64;
+  int split = -1;
+};
+enum TuneKind { kTuneDensity = 0, kTuneHydro = 1, kTuneGravity = 2, kTuneKinds = 3 };
+
 }  // namespace g3
 
 struct g3_tree {
@@ -86,6 +97,8 @@ struct g3_ctx {
     size_t bytes = 0;
   };
   Buf scratch[24];
+  // autotuned launch choices: (kind, floor(log2(targets))) -> choice
+  std::map<std::pair<int, int>, g3::Tuning> tuning;
   unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
   int64_t *pinned = nullptr;               // host pinned readback slots [8]
   hipStream_t last_stream = nullptr;
@@ -128,17 +141,22 @@ hipError_t refit_hmax(Octree &o, hipStream_t s);
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
 // Work of one interaction launch: groups of up to 64 Morton-consecutive
-// targets (one per lane) that never straddle two snapshots of a forest.
-// Snapshot k holds targets [tstart[k], tstart[k+1]) and groups
-// [gstart[k], gstart[k+1]); its octree is the node range
-// [nroot[k], nroot[k+1]).
+// targets (one per lane) that never straddle two segments. A segment is a
+// run of consecutive targets of one snapshot: the snapshot's whole active
+// set, or, when groups are split by a key level L, the run of its targets
+// that share one level-L octree cell. Segment k holds targets
+// [tstart[k], tstart[k+1]) and groups [gstart[k], gstart[k+1]) and belongs
+// to snapshot seg_snap[k], whose octree is the node range
+// [nroot[snap], nroot[snap+1]).
 struct Groups {
-  const int32_t *targets;  // compacted sorted positions; nullptr: every member
-  const int32_t *tstart;   // [n_snap + 1]
-  const int32_t *gstart;   // [n_snap + 1]
-  const int32_t *nroot;    // [n_snap + 1]
-  const double4 *sbox;     // [n_snap] snapshot box: lo xyz, side
-  unsigned *queue;         // [8] per-XCD counters, zero at launch
+  const int32_t *targets;   // compacted sorted positions; nullptr: every member
+  const int32_t *tstart;    // [nseg + 1]
+  const int32_t *gstart;    // [nseg + 1]
+  const int32_t *seg_snap;  // [nseg]
+  const int32_t *nseg;      // device scalar: number of segments
+  const int32_t *nroot;     // [n_snap + 1]
+  const double4 *sbox;      // [n_snap] snapshot box: lo xyz, side
+  unsigned *queue;          // [8] per-XCD counters, zero at launch
   int n_snap;
 };
 
@@ -146,6 +164,8 @@ struct Groups {
 inline int64_t max_groups_of(int64_t max_targets, int64_t n_snap) {
   return (max_targets + kWave - 1) / kWave + (n_snap < max_targets ? n_snap : max_targets);
 }
+
+
 
 // Active set -> group table of one octree (scratch owned by the ctx).
 // rows[t] is the index in `active` of target t (nullptr with every member
@@ -156,7 +176,8 @@ struct Work {
   int64_t max_groups;
 };
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
-                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s);
+                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s,
+                 int split = -1);
 
 // Grid of a persistent launch: the workgroups that can be resident at once
 // (occupancy of `kern` x compute units), or fewer if there are few groups.

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
 EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
            "g3_build_tree", "g3_build_forest", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
-           "g3_density_backward", "g3_hydro_force_backward", "g3_gravity_backward")
+           "g3_density_backward", "g3_hydro_force_backward", "g3_gravity_backward",
+           "g3_autotune", "g3_tuning_get", "g3_tuning_set")
 
 
 class g3_params(ctypes.Structure):
@@ -77,6 +78,9 @@ def lib():
             "g3_density_backward": ([P, P, i64, P, P] + [P] * 10, ctypes.c_int),
             "g3_hydro_force_backward": ([P, P, i64, P, P] + [P] * 15, ctypes.c_int),
             "g3_gravity_backward": ([P, P, i64, P, P] + [P] * 5, ctypes.c_int),
+            "g3_autotune": ([P, P, i64, P, P] + [P] * 6, ctypes.c_int),
+            "g3_tuning_get": ([P, i32, i64, P, P], ctypes.c_int),
+            "g3_tuning_set": ([P, i32, i64, i32, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -215,3 +219,25 @@ def g3_gravity_backward(ctx, tree, n_act, active, params, g_acc, g_pot, g_pos, g
                                    g_acc or None, g_pot or None, g_pos or None, g_mass or None,
                                    stream)
     _check(ctx, st, "g3_gravity_backward")
+
+
+G3_TUNE_DENSITY, G3_TUNE_HYDRO, G3_TUNE_GRAVITY = 0, 1, 2
+
+
+def g3_autotune(ctx, tree, n_act, active, params, h, vel, u, rho, omega, stream):
+    st = lib().g3_autotune(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                           h or None, vel or None, u or None, rho or None, omega or None, stream)
+    _check(ctx, st, "g3_autotune")
+
+
+def g3_tuning_get(ctx, kind, n_targets):
+    """(walk_leaf, split) a call of `kind` over n_targets targets uses."""
+    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = lib().g3_tuning_get(ctx, int(kind), int(n_targets), ctypes.byref(a), ctypes.byref(b))
+    _check(ctx, st, "g3_tuning_get")
+    return a.value, b.value
+
+
+def g3_tuning_set(ctx, kind, n_targets, walk_leaf, split):
+    st = lib().g3_tuning_set(ctx, int(kind), int(n_targets), int(walk_leaf), int(split))
+    _check(ctx, st, "g3_tuning_set")

@@ -45,6 +45,21 @@ class Context:
     def nonconverged(self, reset: bool = False) -> int:
         return self.stats(reset)[0]
 
+    def tuning(self, kind: int, n_targets: int):
+        """(walk_leaf, split) the calls of `kind` over n_targets use."""
+        return g3.g3_tuning_get(self.handle, kind, n_targets)
+
+    def set_tuning(self, kind: int, walk_leaf: int, split: int, n_targets: int = -1):
+        g3.g3_tuning_set(self.handle, kind, n_targets, walk_leaf, split)
+
+    def autotune(self, tree, h, vel=None, u=None, rho=None, omega=None, params=None,
+                 active=None):
+        """Time the launch choices on this tree and active set and keep the
+        fastest (g3_autotune); h is copied, not changed."""
+        na, ap = _active(tree, active)
+        g3.g3_autotune(self.handle, tree.handle, na, ap, g3.g3_params.of(params or tree.params),
+                       _ptr(h), _ptr(vel), _ptr(u), _ptr(rho), _ptr(omega), _stream(self.device))
+
     def close(self):
         if getattr(self, "handle", None):
             g3.g3_ctx_destroy(self.handle)
