@@ -222,6 +222,16 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
                                            "nterms": B["nterms"]})
 
+    # the autotuner picks candidate tile depth and group split per kernel
+    tt = time.perf_counter()
+    ctx.autotune(tree, h0, vel=vel, u=u, rho=rho_in, omega=om_in, active=act)
+    tune_s = time.perf_counter() - tt
+    from paper_2003_10850_amd import g3
+    nact = int(b.active.size)
+    tuned = {name: dict(zip(("walk_leaf", "split"), ctx.tuning(kind, nact)))
+             for name, kind in (("density", g3.G3_TUNE_DENSITY), ("hydro", g3.G3_TUNE_HYDRO),
+                                ("gravity", g3.G3_TUNE_GRAVITY))}
+    print(f"bench: autotuned in {tune_s:.2f} s: {tuned}", file=sys.stderr, flush=True)
     s = torch.cuda.Stream(dev)
     s.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(s):
@@ -255,7 +265,8 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     print(f"bench: batched graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms/step, "
           f"build {build_ms:.2f} ms; interactions {inter}", file=sys.stderr, flush=True)
 
-    # unbatched: one tree and three calls per snapshot
+    # unbatched: one tree and three calls per snapshot, default launch choices
+    ctx = ops.Context(dev)
     trees = []
     for k in range(b.n_snap):
         r0, r1 = int(b.snap_off[k]), int(b.snap_off[k + 1])
@@ -303,6 +314,8 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         "unbatched_ms_per_step": unbatched_ms,
         "unbatched_value": inter / (unbatched_ms * 1e-3),
         "forest_build_ms": build_ms,
+        "autotuned": tuned,
+        "autotune_s": tune_s,
         "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
         "h_nonconverged": nonconv,
         "step": "h solve + density, hydro force, gravity over every snapshot's active set: "
@@ -383,6 +396,8 @@ def main() -> int:
                     help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the loss forward + backward measurement")
+    ap.add_argument("--only", choices=("batched", "differentiation"),
+                    help="run just this leg and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -401,6 +416,10 @@ def main() -> int:
     from paper_2003_10850_amd import inputs, ops, g3
 
     dev = torch.device("cuda", 0)
+    if args.only:
+        leg = run_batched if args.only == "batched" else run_differentiation
+        print(json.dumps({args.only: leg(dev, args.steps, args.warmup)}), flush=True)
+        return 0
     w = inputs.plummer(n=args.n, n_spheres=args.spheres, seed=1)
     pos32, vel32, m32, u32 = w.as_f32()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
