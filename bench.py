@@ -265,6 +265,34 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     print(f"bench: batched graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms/step, "
           f"build {build_ms:.2f} ms; interactions {inter}", file=sys.stderr, flush=True)
 
+    # the mixed-precision forest: FP64 positions and h, the same step
+    tree64 = ops.Tree(ctx, T(b.pos), mass, typ, boxes, b.params, snap_off=b.snap_off)
+    h64 = h0.double()
+    H64 = torch.zeros(n, dtype=torch.float64, device=dev)
+
+    def step64():
+        H64.copy_(h64)
+        ops.density(tree64, active=act, out={"h": H64, **{k: B[k] for k in
+                                                         ("rho", "drho_dh", "omega", "nngb")}})
+        ops.hydro_force(tree64, vel, u, H64, rho_in, om_in, active=act,
+                        out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
+        ops.gravity(tree64, active=act, out={"acc": B["gacc"], "pot": B["pot"],
+                                             "nterms": B["nterms"]})
+
+    for _ in range(max(warmup, 1)):
+        step64()
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    for _ in range(steps):
+        step64()
+    torch.cuda.synchronize()
+    mixed_ms = 1e3 * (time.perf_counter() - t6) / steps
+    i64 = (int(B["nngb"][T(gas_act)].sum()) + int(B["npairs"][T(gas_act)].sum()) +
+           int(B["nterms"][act.long()].sum()))
+    tree64.close()
+    ctx.nonconverged(reset=True)
+    print(f"bench: batched mixed precision {mixed_ms:.3f} ms/step", file=sys.stderr, flush=True)
+
     # unbatched: one tree and three calls per snapshot, default launch choices
     ctx = ops.Context(dev)
     trees = []
@@ -316,6 +344,9 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         "forest_build_ms": build_ms,
         "autotuned": tuned,
         "autotune_s": tune_s,
+        "mixed_precision": {"ms_per_step": mixed_ms, "value": i64 / (mixed_ms * 1e-3),
+                            "path": "FP64 positions and h, FP32 offsets from each target, "
+                                    "FP64 decisions in the error band, eager calls"},
         "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
         "h_nonconverged": nonconv,
         "step": "h solve + density, hydro force, gravity over every snapshot's active set: "
@@ -372,6 +403,65 @@ def run_differentiation(dev, steps: int, warmup: int, n: int = 1 << 20, seed: in
     }
 
 
+def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int = 3) -> dict:
+    """The precision workload: N = 2e7 particles clustered as the plain
+    workload but in 256 Plummer spheres, FP64 stored positions, on the
+    mixed-precision path. One step = both octree builds, density with a
+    cold-start FP64 h solve, hydro, gravity, every particle active. (Its
+    errors against the FP64 oracle on a 1e4-particle subsample are checked
+    by the GPU test suite.)"""
+    import torch
+    from paper_2003_10850_amd import inputs, ops
+
+    w = inputs.plummer(n=n, n_spheres=256, seed=seed)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, mass, typ = T(w.pos), T(w.mass.astype(np.float32)), T(w.type)
+    vel, u = T(w.vel.astype(np.float32)), T(w.u.astype(np.float32))
+    ctx = ops.Context(dev)
+    tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
+    f32 = dict(dtype=torch.float32, device=dev)
+    h = torch.zeros(n, dtype=torch.float64, device=dev)
+    od = dict(h=h, rho=torch.zeros(n, **f32), drho_dh=torch.zeros(n, **f32),
+              omega=torch.zeros(n, **f32), nngb=torch.zeros(n, dtype=torch.int32, device=dev))
+    oh = dict(acc=torch.zeros(n, 3, **f32), dudt=torch.zeros(n, **f32), vsig=torch.zeros(n, **f32),
+              npairs=torch.zeros(n, dtype=torch.int32, device=dev))
+    og = dict(acc=torch.zeros(n, 3, **f32), pot=torch.zeros(n, **f32),
+              nterms=torch.zeros(n, dtype=torch.int32, device=dev))
+
+    def step():
+        tree.build(pos, mass, typ)
+        h.zero_()
+        ops.density(tree, out=od)
+        ops.hydro_force(tree, vel, u, h, od["rho"], od["omega"], out=oh)
+        ops.gravity(tree, out=og)
+
+    for _ in range(max(warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    gas = T(w.type == 0)
+    inter = (int(od["nngb"][gas].sum()) + int(oh["npairs"][gas].sum()) +
+             int(og["nterms"].sum()))
+    nonconv = ctx.nonconverged(reset=True)
+    print(f"bench: precision {ms:.3f} ms/step, {inter} interactions", file=sys.stderr,
+          flush=True)
+    return {
+        "workload": f"{w.name}: N={n} in 256 Plummer spheres + 20% background (half gas), "
+                    "FP64 stored positions, 295 neighbours, theta=0.5, eps=1e-3, all active",
+        "value": inter / (ms * 1e-3),
+        "unit": "interactions/s",
+        "ms_per_step": ms,
+        "interactions_per_step": inter,
+        "h_nonconverged": nonconv,
+        "path": "mixed precision: FP64 positions, FP32 offsets from each target, compensated "
+                "FP32 sums, FP64 moments and h solve, FP64 decisions in the error band",
+    }
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -396,7 +486,9 @@ def main() -> int:
                     help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the loss forward + backward measurement")
-    ap.add_argument("--only", choices=("batched", "differentiation"),
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 2e7-particle mixed-precision measurement")
+    ap.add_argument("--only", choices=("batched", "differentiation", "precision"),
                     help="run just this leg and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
@@ -417,7 +509,8 @@ def main() -> int:
 
     dev = torch.device("cuda", 0)
     if args.only:
-        leg = run_batched if args.only == "batched" else run_differentiation
+        leg = {"batched": run_batched, "differentiation": run_differentiation,
+               "precision": run_precision}[args.only]
         print(json.dumps({args.only: leg(dev, args.steps, args.warmup)}), flush=True)
         return 0
     w = inputs.plummer(n=args.n, n_spheres=args.spheres, seed=1)
@@ -527,6 +620,8 @@ def main() -> int:
         line["batched"] = run_batched(dev, args.steps, args.warmup)
     if not args.no_differentiation:
         line["differentiation"] = run_differentiation(dev, args.steps, args.warmup)
+    if not args.no_precision:
+        line["precision"] = run_precision(dev, args.steps, args.warmup)
     if args.copy_calibration:
         copy_calibration(dev)
     if not args.no_cpu_baseline:
