@@ -161,7 +161,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     for name in ("k_density", "k_hydro", "k_gravity"):
         per = {}
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
-            vals = [v for k, vs in data[counter].items() if f"::{name}(" in k for v in vs]
+            vals = [v for k, vs in data[counter].items()
+                    if f"::{name}(" in k or f"::{name}<false>(" in k for v in vs]
             per[counter] = float(np.mean(vals)) * 1024 / scale[counter] if vals else None
         if per["FETCH_SIZE"] is not None and per["WRITE_SIZE"] is not None:
             out["kernels"][name] = {"fetch_bytes": per["FETCH_SIZE"],
