@@ -39,11 +39,19 @@ HBM_TBS = 8.0
 
 
 def kernel_source_hash() -> str:
+    """Hash of the HIP sources with comments and blank space removed, so
+    that only a change of code (not of its comments) invalidates counter
+    figures taken earlier."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_10850_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

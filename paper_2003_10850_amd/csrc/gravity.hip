@@ -45,9 +45,9 @@ __device__ __forceinline__ bool open_accept64(double l, double theta, double4 c,
   return l * l < theta * theta * ((dx * dx + dy * dy) + dz * dz);
 }
 
-// Mixed precision (kF64): positions are stored in FP64 and a wave works on
-// FP32 offsets from a group centre (its first target); the node centres of
-// mass come from FP64 moments. Near the threshold, where the FP32 test on
+// Mixed precision (kF64): positions are stored in FP64 and every term works
+// on the FP32 rounding of its FP64 offset from the target; the node centres
+// of mass come from FP64 moments. Near the threshold, where the FP32 test on
 // offsets could disagree with the FP64 one, the FP64 test decides.
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_gravity(
