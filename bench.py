@@ -495,6 +495,8 @@ def main() -> int:
                     help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the loss forward + backward measurement")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="plain leg: keep the default launch choices")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 2e7-particle mixed-precision measurement")
     ap.add_argument("--only", choices=("batched", "differentiation", "precision"),
@@ -531,6 +533,18 @@ def main() -> int:
     tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), p)
     n = w.n
     h = torch.zeros(n, dtype=torch.float32, device=dev)
+    tune_s = None
+    if not args.no_autotune:
+        # launch choices for this workload (cold-start solve, model hydro fields)
+        tt = time.perf_counter()
+        ctx.autotune(tree, h, vel=vel, u=u, rho=T(inputs.model_gas_density(w).astype(np.float32)),
+                     omega=torch.ones(n, device=dev))
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - tt
+    tuned = {name: dict(zip(("walk_leaf", "split"), ctx.tuning(kind, n // 2 if kind < 2 else n)))
+             for name, kind in (("density", g3.G3_TUNE_DENSITY), ("hydro", g3.G3_TUNE_HYDRO),
+                                ("gravity", g3.G3_TUNE_GRAVITY))}
+    print(f"bench: launch choices {tuned} (autotune {tune_s} s)", file=sys.stderr, flush=True)
     outd = dict(rho=torch.zeros(n, device=dev), drho_dh=torch.zeros(n, device=dev),
                 omega=torch.zeros(n, device=dev),
                 nngb=torch.zeros(n, dtype=torch.int32, device=dev))
@@ -622,7 +636,8 @@ def main() -> int:
                    "n": n, "interactions_per_step": {"density": i_d, "hydro": i_h,
                                                      "gravity": i_g},
                    "h_nonconverged": nonconv,
-                   "h_passes_per_wave": passes / max(waves, 1), "path": "plain"},
+                   "h_passes_per_wave": passes / max(waves, 1), "path": "plain",
+                   "launch_choices": tuned, "autotune_s": tune_s},
         "roofline": roofline,
     }
     if not args.no_batched:

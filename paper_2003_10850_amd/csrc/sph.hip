@@ -188,32 +188,39 @@ __global__ __launch_bounds__(kBlock) void k_density(
       neumaier_add(swh, cswh, pwh);
       wave_sync();
     };
+    // The next node is either cur + 1 (descend) or the skip target: both
+    // are loaded while the current one is tested, so the walk waits for one
+    // load latency per step instead of a load after every decision.
+    const int last = grp.end - 1;
     int cur = grp.root;
+    Node nd = nodes[cur];
     while (cur < grp.end) {
-      const Node nd = nodes[cur];
+      const int next_a = cur + 1, next_b = nd.meta.x;
+      const Node nda = nodes[min(next_a, last)];
+      const Node ndb = nodes[min(next_b, last)];
       const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < hw2;
-      if (__ballot(want) == 0ull) {
-        cur = nd.meta.x;
-        continue;
-      }
-      // a small subtree is taken whole: its members are one contiguous run
-      if (!(nd.meta.w & kLeafBit) && nd.meta.z > walk_leaf) {
-        ++cur;
-        continue;
-      }
-      int st = nd.meta.y, c = nd.meta.z;
-      while (c > 0) {
-        const int take = min(c, kTile - tc);
-        if (lane >= tc && lane < tc + take) cand = st + lane - tc;
-        tc += take;
-        st += take;
-        c -= take;
-        if (tc == kTile) {
-          flush(kTile);
-          tc = 0;
+      bool descend = false;
+      if (__ballot(want) != 0ull) {
+        // a small subtree is taken whole: its members are one contiguous run
+        if (!(nd.meta.w & kLeafBit) && nd.meta.z > walk_leaf) {
+          descend = true;
+        } else {
+          int st = nd.meta.y, c = nd.meta.z;
+          while (c > 0) {
+            const int take = min(c, kTile - tc);
+            if (lane >= tc && lane < tc + take) cand = st + lane - tc;
+            tc += take;
+            st += take;
+            c -= take;
+            if (tc == kTile) {
+              flush(kTile);
+              tc = 0;
+            }
+          }
         }
       }
-      cur = nd.meta.x;
+      cur = descend ? next_a : next_b;
+      nd = descend ? nda : ndb;
     }
     if (tc > 0) flush(tc);
     sw += csw;
