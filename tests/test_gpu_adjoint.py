@@ -211,3 +211,56 @@ def test_loss_gradient_vs_oracle_and_finite_differences(ctx):
                 (k, ax, fd, gpos[k, ax])
             checked += 1
     assert checked >= 18
+
+
+def test_adjoints_on_a_forest(ctx):
+    """Every snapshot of a forest gets the gradients its own tree gives:
+    density and gravity adjoints over a three-snapshot forest with boxes
+    at different places, against the oracle per snapshot."""
+    from paper_2003_10850_amd import ops
+    snaps, boxes = [], []
+    for k, n in enumerate((3000, 700, 5000)):
+        w = inputs.plummer(n=n, n_spheres=2, seed=90 + k, n_ngb=40.0)
+        side = 1.0 + 0.5 * k
+        w.pos = w.pos * side + np.array([5.0 * k, 0.0, 0.0])
+        w.box = np.array([5.0 * k, 0.0, 0.0, side])
+        snaps.append(w)
+        boxes.append(tuple(w.box))
+    off = np.concatenate([[0], np.cumsum([w.n for w in snaps])])
+    pos32 = np.concatenate([w.pos for w in snaps]).astype(np.float32)
+    m32 = np.concatenate([w.mass for w in snaps]).astype(np.float32)
+    typ = np.concatenate([w.type for w in snaps])
+    p = inputs.Params(n_ngb=40.0, eps=1e-3)
+    tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(typ), boxes, p, snap_off=off)
+    h = np.zeros(len(m32), np.float32)
+    for k, w in enumerate(snaps):
+        side = w.box[3]
+        w2 = inputs.Workload(w.name, (w.pos - w.box[:3]) / side, w.vel, w.mass, w.u, w.type,
+                             np.array([0, 0, 0, 1.0]), w.params)
+        w2.model = w.model
+        h[off[k]:off[k + 1]] = inputs.model_smoothing(w2, 40.0) * side
+    pos = dev_t(pos32).requires_grad_(True)
+    mass = dev_t(m32).requires_grad_(True)
+    hh = dev_t(h).requires_grad_(True)
+    rho, _, om = ops.density_ad(tree, pos, mass, hh)
+    acc, pot = ops.gravity_ad(tree, pos, mass)
+    rng = np.random.default_rng(12)
+    a, b = rng.normal(size=len(m32)).astype(np.float32), rng.normal(size=len(m32)).astype(np.float32)
+    gA = rng.normal(size=(len(m32), 3)).astype(np.float32)
+    L = (rho * dev_t(a)).sum() + (om * dev_t(b)).sum() + (acc * dev_t(gA)).sum() + pot.sum()
+    L.backward()
+    gp, gm, gh = host(pos.grad), host(mass.grad), host(hh.grad)
+    for k, w in enumerate(snaps):
+        r = slice(off[k], off[k + 1])
+        P, M = pos32[r].astype(np.float64), m32[r].astype(np.float64)
+        gt = oracle.Tree(P, M, w.box, type=w.type, gas_only=True)
+        at = oracle.Tree(P, M, w.box, type=w.type)
+        gas = np.nonzero(w.type == 0)[0]
+        z = lambda v: np.where(w.type == 0, v, 0.0)
+        rd = oracle.density_backward(gt, p, h[r].astype(np.float64), g_rho=z(a[r]),
+                                     g_omega=z(b[r]), active=gas)
+        rg = oracle.gravity_backward(at, p, g_acc=gA[r], g_pot=np.ones(w.n))
+        check(f"forest {k} g_pos", gp[r], rd["pos"] + rg["pos"], rd["S"]["pos"] + rg["S"]["pos"])
+        check(f"forest {k} g_mass", gm[r], rd["mass"] + rg["mass"],
+              rd["S"]["mass"] + rg["S"]["mass"])
+        check(f"forest {k} g_h", gh[r], rd["h"], rd["S"]["h"])
