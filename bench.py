@@ -495,8 +495,9 @@ def main() -> int:
                     help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the loss forward + backward measurement")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="plain leg: keep the default launch choices")
+    ap.add_argument("--autotune", action="store_true",
+                    help="plain leg: run the autotuner first (its candidate runs then appear "
+                         "in kernel traces of this command); default launch choices otherwise")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 2e7-particle mixed-precision measurement")
     ap.add_argument("--only", choices=("batched", "differentiation", "precision"),
@@ -534,7 +535,7 @@ def main() -> int:
     n = w.n
     h = torch.zeros(n, dtype=torch.float32, device=dev)
     tune_s = None
-    if not args.no_autotune:
+    if args.autotune:
         # launch choices for this workload (cold-start solve, model hydro fields)
         tt = time.perf_counter()
         ctx.autotune(tree, h, vel=vel, u=u, rho=T(inputs.model_gas_density(w).astype(np.float32)),
