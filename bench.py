@@ -353,6 +353,10 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         "forest_build_ms": build_ms,
         "autotuned": tuned,
         "autotune_s": tune_s,
+        "realised_active_fraction": float(b.active.size) / b.n,
+        "snapshots_below_1e3_active": int(sum(
+            int(((b.active >= b.snap_off[k]) & (b.active < b.snap_off[k + 1])).sum()) < 1000
+            for k in range(b.n_snap))),
         "mixed_precision": {"ms_per_step": mixed_ms, "value": i64 / (mixed_ms * 1e-3),
                             "path": "FP64 positions and h, FP32 offsets from each target, "
                                     "FP64 decisions in the error band, eager calls"},

@@ -26,6 +26,13 @@
  *  - Every call returns a g3_status and never aborts; an asynchronous device
  *    error surfaces as G3_EHIP on a later call. g3_last_error() gives text.
  *  - One g3_ctx per host thread. A g3_tree belongs to the ctx that built it.
+ *  - Graph capture: g3_density, g3_hydro_force, g3_gravity and the
+ *    _backward calls neither wait on the host nor use memset nodes; they
+ *    allocate ctx scratch only when a call needs more than an earlier one.
+ *    Run each call once outside capture with the same sizes, then capture
+ *    it (hipStreamBeginCapture or torch.cuda.graph); replays reproduce the
+ *    eager results. Builds, g3_walk, g3_autotune and g3_ctx_stats SYNC and
+ *    cannot be captured.
  *
  * Physics (the paper prints no formula; these are the published methods
  * Gadget builds on): Wendland C6 kernel with support radius h (Dehnen & Aly
