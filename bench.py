@@ -475,6 +475,45 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
     }
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "GRBM_GUI_ACTIVE",
+                 "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+                 "SQ_INSTS_VALU_TRANS_F32")
+
+
+def summarize_valu(csv_path: str, out_json: str, n_cu: int = 256) -> dict:
+    """Per-kernel vector-ALU figures from one rocprofv3 --pmc run of
+    VALU_COUNTERS: VALU busy (rocprof's VALUBusy expression), lane
+    utilisation (VALUUtilization), VALU instructions per dispatch and the
+    FP32 operations the hardware executed (FMA counted 2, all lanes that
+    were active), per dispatch and per second of kernel time."""
+    import csv
+    import collections
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        name = r["Kernel_Name"]
+        for k in ("k_density", "k_hydro", "k_gravity"):
+            if f"::{k}<false>(" in name or f"::{k}(" in name:
+                acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    out = {"counters": list(VALU_COUNTERS), "cu": n_cu, "kernels": {}}
+    for k, c in acc.items():
+        m = {n: float(np.mean(v)) for n, v in c.items()}
+        util = m["SQ_THREAD_CYCLES_VALU"] / (m["SQ_ACTIVE_INST_VALU"] * 64.0)
+        busy = 100.0 * m["SQ_ACTIVE_INST_VALU"] / n_cu / m["GRBM_GUI_ACTIVE"]
+        ops = 64.0 * util * (2.0 * m["SQ_INSTS_VALU_FMA_F32"] + m["SQ_INSTS_VALU_ADD_F32"] +
+                             m["SQ_INSTS_VALU_MUL_F32"] + m["SQ_INSTS_VALU_TRANS_F32"])
+        t = float(np.mean(list(dur[k].values())))
+        out["kernels"][k] = {"valu_busy_pct": busy, "valu_lane_utilisation": util,
+                             "valu_insts_per_dispatch": m["SQ_INSTS_VALU"],
+                             "fp32_ops_executed_per_dispatch": ops,
+                             "dispatch_s_under_counters": t,
+                             "fp32_tflops_executed": ops / t / 1e12}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -508,9 +547,15 @@ def main() -> int:
                     help="run just this leg and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
+    ap.add_argument("--summarize-valu", nargs=2, metavar=("CSV", "OUT_JSON"),
+                    help="write per-kernel VALU figures from a rocprofv3 --pmc run of the "
+                         "VALU counters and exit")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="write per-kernel HBM bytes from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_valu:
+        print(json.dumps(summarize_valu(*args.summarize_valu), indent=1))
+        return 0
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc), indent=1))
         return 0

@@ -111,7 +111,6 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       py += mr3 * dy;
       pz += mr3 * dz;
       pp -= mr;
-      nt += use ? 1 : 0;
     }
     neumaier_add(ax, cax, px);
     neumaier_add(ay, cay, py);
@@ -150,7 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     }
     const uint64_t amask = __ballot(accept);
     const uint64_t omask = __ballot(act && !accept);
-    if (accept) resume = nd.meta.x;
+    if (accept) {
+      resume = nd.meta.x;
+      ++nt;  // terms are counted here, not in the tile loop
+    }
     if (amask) {
       if (tc == kTile) {
         flush(kTile);
@@ -174,6 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       continue;
     }
     int st = nd.meta.y, c = nd.meta.z;
+    // an opening lane interacts with every member but itself
+    if (act && !accept) nt += c - ((s >= st && s < st + c) ? 1 : 0);
     while (c > 0) {
       if (tc == kTile) {
         flush(kTile);
