@@ -482,10 +482,10 @@ VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU"
 
 def summarize_valu(csv_path: str, out_json: str, n_cu: int = 256) -> dict:
     """Per-kernel vector-ALU figures from one rocprofv3 --pmc run of
-    VALU_COUNTERS: VALU busy (rocprof's VALUBusy expression), lane
-    utilisation (VALUUtilization), VALU instructions per dispatch and the
-    FP32 operations the hardware executed (FMA counted 2, all lanes that
-    were active), per dispatch and per second of kernel time."""
+    VALU_COUNTERS: VALU wave-instructions per dispatch and per second of
+    kernel time, lane utilisation (active lanes per VALU instruction, the
+    VALUUtilization expression) and the FP32 operations the hardware
+    executed (FMA counted 2, on the lanes that were active)."""
     import csv
     import collections
     acc = collections.defaultdict(lambda: collections.defaultdict(list))
@@ -500,12 +500,12 @@ def summarize_valu(csv_path: str, out_json: str, n_cu: int = 256) -> dict:
     for k, c in acc.items():
         m = {n: float(np.mean(v)) for n, v in c.items()}
         util = m["SQ_THREAD_CYCLES_VALU"] / (m["SQ_ACTIVE_INST_VALU"] * 64.0)
-        busy = 100.0 * m["SQ_ACTIVE_INST_VALU"] / n_cu / m["GRBM_GUI_ACTIVE"]
+        t = float(np.mean(list(dur[k].values())))
         ops = 64.0 * util * (2.0 * m["SQ_INSTS_VALU_FMA_F32"] + m["SQ_INSTS_VALU_ADD_F32"] +
                              m["SQ_INSTS_VALU_MUL_F32"] + m["SQ_INSTS_VALU_TRANS_F32"])
-        t = float(np.mean(list(dur[k].values())))
-        out["kernels"][k] = {"valu_busy_pct": busy, "valu_lane_utilisation": util,
+        out["kernels"][k] = {"valu_lane_utilisation": util,
                              "valu_insts_per_dispatch": m["SQ_INSTS_VALU"],
+                             "valu_insts_per_s": m["SQ_INSTS_VALU"] / t,
                              "fp32_ops_executed_per_dispatch": ops,
                              "dispatch_s_under_counters": t,
                              "fp32_tflops_executed": ops / t / 1e12}

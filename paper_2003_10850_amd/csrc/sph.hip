@@ -159,29 +159,45 @@ __global__ __launch_bounds__(kBlock) void k_density(
       // each lane's entries first and then visiting only its own measured
       // slower: it costs occupancy and per-lane LDS addressing.)
       float pw = 0.0f, pwh = 0.0f;
-      for (int k = 0; k < nc; ++k) {
-        float r2, mj;
-        bool in;
-        if constexpr (kF64) {
+      auto pair = [&](float r2, float mj) {
+        const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
+        float wv, whv;
+        wc6_w_wh(u, wv, whv);
+        pw += mj * wv;
+        pwh += mj * whv;
+        ++cnt;
+      };
+      if constexpr (kF64) {
+        for (int k = 0; k < nc; ++k) {
           // offset from this target: the FP64 difference rounded to FP32
           const double4 q = tile64[k];
-          r2 = dist2_exact((float)(q.x - p64.x), (float)(q.y - p64.y), (float)(q.z - p64.z));
-          mj = (float)q.w;
-          in = r2 < h2;
+          const float r2 =
+              dist2_exact((float)(q.x - p64.x), (float)(q.y - p64.y), (float)(q.z - p64.z));
+          bool in = r2 < h2;
           if (fabsf(r2 - h2) <= band) in = within64(p64, q, (double)hcur);
-        } else {
-          const float4 q = tile[k];
-          r2 = dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y), sub_exact(q.z, xi.z));
-          mj = q.w;
-          in = r2 < h2;
+          if (in) pair(r2, (float)q.w);
         }
-        if (in) {
-          const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
-          float wv, whv;
-          wc6_w_wh(u, wv, whv);
-          pw += mj * wv;
-          pwh += mj * whv;
-          ++cnt;
+      } else {
+        // entries are read four at a time, one group ahead of their tests,
+        // so the LDS latency overlaps the previous group's arithmetic (the
+        // slots past nc hold infinity and fail every test)
+        const int ngr = (nc + 3) >> 2;
+        float4 a0 = tile[0], a1 = tile[1], a2 = tile[2], a3 = tile[3];
+        for (int gq = 0; gq < ngr; ++gq) {
+          const float4 q0 = a0, q1 = a1, q2 = a2, q3 = a3;
+          const int nx = min(4 * gq + 4, kTile - 4);
+          a0 = tile[nx];
+          a1 = tile[nx + 1];
+          a2 = tile[nx + 2];
+          a3 = tile[nx + 3];
+          const float4 qs[4] = {q0, q1, q2, q3};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float4 q = qs[e];
+            const float r2 =
+                dist2_exact(sub_exact(q.x, xi.x), sub_exact(q.y, xi.y), sub_exact(q.z, xi.z));
+            if (r2 < h2) pair(r2, q.w);
+          }
         }
       }
       neumaier_add(sw, csw, pw);
