@@ -494,7 +494,7 @@ int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t 
   if (st) return st;
   e = fill_i32(t->iperm_gas, -1, n, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest");
-  st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s);
+  st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s, type);
   if (st) return st;
   c->err.clear();
   return G3_OK;

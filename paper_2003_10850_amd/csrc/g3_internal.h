@@ -111,8 +111,11 @@ enum Slot {
   kSortKeys = 0, kSortVals, kSortTmp, kScanTmp, kCounts, kOffsets,
   kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
   kSnapKeys, kSnapKeysAlt, kGroups, kAdjSrc, kAdjNode, kAdjPQ, kAdjR,
+  kGasFlags, kGasSlot, kGasScan,
   kNumSlots
 };
+static_assert(kNumSlots <= (int)(sizeof(g3_ctx::scratch) / sizeof(g3_ctx::Buf)),
+              "more scratch slots than the ctx holds");
 
 void *scratch(g3_ctx *c, int slot, size_t bytes);  // nullptr on failure
 
@@ -134,8 +137,10 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
                             uint32_t *vals_alt, int64_t n, int bits, void *tmp, hipStream_t s);
 
 // Tree build of one octree (members already selected in `ids`/`keys`).
+// The gas octree (o == t->gas) takes its members from the all-particle
+// octree built before it, filtered by `type` (nullptr: all gas).
 int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
-                 const float *mass, int64_t m, hipStream_t s);
+                 const float *mass, int64_t m, hipStream_t s, const uint8_t *type = nullptr);
 hipError_t refit_hmax(Octree &o, hipStream_t s);
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

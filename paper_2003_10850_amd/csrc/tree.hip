@@ -110,11 +110,24 @@ __global__ void k_gas_flags(const uint8_t *__restrict__ type, int64_t n,
   if (i < n) flags[i] = (type == nullptr || type[i] == 0) ? 1u : 0u;
 }
 
-__global__ void k_gas_compact(const uint32_t *__restrict__ flags,
-                              const uint32_t *__restrict__ slot, int64_t n,
-                              int32_t *__restrict__ ids) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && flags[i]) ids[slot[i]] = (int32_t)i;
+// The gas octree's members in sorted order come from the all-particle
+// octree's: filtering its (snapshot, key, caller id) order keeps that order,
+// which is exactly the order a sort of the gas members would give.
+__global__ void k_gas_of_sorted(const int32_t *__restrict__ perm_all, int64_t n,
+                                const uint8_t *__restrict__ type, uint32_t *__restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) flags[s] = (type == nullptr || type[perm_all[s]] == 0) ? 1u : 0u;
+}
+
+__global__ void k_compact_sorted(const uint32_t *__restrict__ flags,
+                                 const uint32_t *__restrict__ slot, int64_t n,
+                                 const uint64_t *__restrict__ keys_all,
+                                 const int32_t *__restrict__ perm_all,
+                                 uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n || !flags[s]) return;
+  keys[slot[s]] = keys_all[s];
+  vals[slot[s]] = (uint32_t)perm_all[s];
 }
 
 // Sorted copies: FP32 (x, y, z, m) always; for FP64 positions also the
@@ -152,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restri
                                                         int32_t *__restrict__ maxlev) {
   // the block's keys with B neighbours on each side, staged in LDS
   __shared__ uint64_t win[kBlock + 2 * kMaxLeaf];
+  __shared__ int32_t block_max;  // deepest leaf level of the block
+  if (threadIdx.x == 0) block_max = 0;
   const int64_t b0 = (int64_t)blockIdx.x * kBlock;
   for (int k = threadIdx.x; k < kBlock + 2 * B; k += kBlock) {
     const int64_t q = b0 - B + k;
@@ -159,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restri
   }
   __syncthreads();
   const int64_t p = b0 + threadIdx.x;
-  if (p >= m) return;
+  if (p < m) {
   const uint64_t *kw = win + B + threadIdx.x;  // kw[d] = key of member p + d
   const uint64_t kp = kw[0];
   // members of other snapshots count as missing: each snapshot is a tree
@@ -187,7 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_node_counts(const uint64_t *__restri
   cnt[p] = (d >= delta) ? (uint32_t)(d - delta + 1) : 0u;
   lev[2 * p] = (uint8_t)delta;
   lev[2 * p + 1] = (uint8_t)d;
-  if (d >= delta) atomicMax(maxlev, d);
+  // one device atomic per block: many members start nodes, and atomics on
+  // a single address serialise
+  if (d >= delta) atomicMax(&block_max, d);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && block_max > 0) atomicMax(maxlev, block_max);
 }
 
 __global__ void k_nodes(const uint64_t *__restrict__ keys, int64_t m,
@@ -324,7 +344,7 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 // Selects the members (gas only for the gas octree), sorts them and builds
 // the topology and moments. SYNCS once to read the node count.
 int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
-                 const float *mass, int64_t m, hipStream_t s) {
+                 const float *mass, int64_t m, hipStream_t s, const uint8_t *type) {
   o.n = m;
   o.nnodes = 0;
   o.max_level = 0;
@@ -373,32 +393,45 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
     return G3_ENOMEM;
   }
   const bool gas = (&o == &t->gas);
-  const int32_t *sel = nullptr;
-  if (gas && m != t->n) sel = (const int32_t *)scratch(c, kFlags, 0);  // filled by caller
-  if (f64)
-    k_keys<double><<<nblk(m), kBlock, 0, s>>>((const double *)pos, sel, m, t->coff, t->sbox,
-                                              t->n_snap, o.keys, vals);
-  else
-    k_keys<float><<<nblk(m), kBlock, 0, s>>>((const float *)pos, sel, m, t->coff, t->sbox,
-                                             t->n_snap, o.keys, vals);
-  hipError_t e = radix_sort_pairs(o.keys, vals, kalt, valt, m, 64, rtmp, s);
-  if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
-  if (t->n_snap > 1) {
-    // stable sort of the key-sorted members by snapshot: (snapshot, key) order
-    uint64_t *skey = (uint64_t *)scratch(c, kSnapKeys, 2 * m * sizeof(uint64_t));
-    uint64_t *skey_alt = (uint64_t *)scratch(c, kSnapKeysAlt, m * sizeof(uint64_t));
-    if (!skey || !skey_alt) { c->err = "device allocation of build scratch failed"; return G3_ENOMEM; }
-    uint32_t *sidx = (uint32_t *)(skey + m);
-    int bits = 8;
-    while (bits < 32 && (int64_t(1) << bits) < t->n_snap) bits += 8;
-    k_snap_keys<<<nblk(m), kBlock, 0, s>>>(vals, m, t->coff, t->n_snap, skey, sidx);
-    e = radix_sort_pairs(skey, sidx, skey_alt, cnt, m, bits, rtmp, s);
+  hipError_t e;
+  if (gas) {
+    // filter the all-particle octree's sorted members (built just before)
+    const int64_t n = t->n;
+    uint32_t *flags = (uint32_t *)scratch(c, kGasFlags, (n + 1) * sizeof(uint32_t));
+    uint32_t *slot = (uint32_t *)scratch(c, kGasSlot, (n + 1) * sizeof(uint32_t));
+    uint32_t *stmp2 = (uint32_t *)scratch(c, kGasScan, scan_tmp_elems(n) * sizeof(uint32_t));
+    if (!flags || !slot || !stmp2) { c->err = "device allocation of build scratch failed"; return G3_ENOMEM; }
+    k_gas_of_sorted<<<nblk(n), kBlock, 0, s>>>(t->all.perm, n, type, flags);
+    e = scan_u32(flags, slot, n, stmp2, s);
+    if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
+    k_compact_sorted<<<nblk(n), kBlock, 0, s>>>(flags, slot, n, t->all.keys, t->all.perm, o.keys,
+                                                 vals);
+  } else {
+    if (f64)
+      k_keys<double><<<nblk(m), kBlock, 0, s>>>((const double *)pos, nullptr, m, t->coff, t->sbox,
+                                                t->n_snap, o.keys, vals);
+    else
+      k_keys<float><<<nblk(m), kBlock, 0, s>>>((const float *)pos, nullptr, m, t->coff, t->sbox,
+                                               t->n_snap, o.keys, vals);
+    e = radix_sort_pairs(o.keys, vals, kalt, valt, m, 64, rtmp, s);
     if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
-    k_gather_sorted<<<nblk(m), kBlock, 0, s>>>(sidx, m, o.keys, vals, kalt, valt);
-    e = hipMemcpyAsync(o.keys, kalt, m * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(vals, valt, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) { c->err = "snapshot sort copy failed"; return G3_EHIP; }
+    if (t->n_snap > 1) {
+      // stable sort of the key-sorted members by snapshot: (snapshot, key) order
+      uint64_t *skey = (uint64_t *)scratch(c, kSnapKeys, 2 * m * sizeof(uint64_t));
+      uint64_t *skey_alt = (uint64_t *)scratch(c, kSnapKeysAlt, m * sizeof(uint64_t));
+      if (!skey || !skey_alt) { c->err = "device allocation of build scratch failed"; return G3_ENOMEM; }
+      uint32_t *sidx = (uint32_t *)(skey + m);
+      int bits = 8;
+      while (bits < 32 && (int64_t(1) << bits) < t->n_snap) bits += 8;
+      k_snap_keys<<<nblk(m), kBlock, 0, s>>>(vals, m, t->coff, t->n_snap, skey, sidx);
+      e = radix_sort_pairs(skey, sidx, skey_alt, cnt, m, bits, rtmp, s);
+      if (e != hipSuccess) { c->err = "radix sort launch failed"; return G3_EHIP; }
+      k_gather_sorted<<<nblk(m), kBlock, 0, s>>>(sidx, m, o.keys, vals, kalt, valt);
+      e = hipMemcpyAsync(o.keys, kalt, m * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(vals, valt, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) { c->err = "snapshot sort copy failed"; return G3_EHIP; }
+    }
   }
   int32_t *iperm = gas ? t->iperm_gas : t->iperm_all;
   if (f64)
@@ -465,9 +498,8 @@ hipError_t refit_hmax(Octree &o, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Gas member selection for the gas octree: ids of the gas particles in
-// caller order, written to the kFlags scratch slot, and the sorted start of
-// each snapshot in the gas octree; returns their number (SYNCS to read it).
+// Gas member count and the sorted start of each snapshot in the gas
+// octree; returns the count (SYNCS to read it).
 // The all-particle octree's snapshot starts are the caller offsets.
 int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, hipStream_t s) {
   const int64_t n = t->n;
@@ -481,12 +513,10 @@ int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, h
   uint32_t *flags = (uint32_t *)scratch(c, kCounts, (n + 1) * sizeof(uint32_t));
   uint32_t *slot = (uint32_t *)scratch(c, kOffsets, (n + 1) * sizeof(uint32_t));
   uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(n) * sizeof(uint32_t));
-  int32_t *ids = (int32_t *)scratch(c, kFlags, (n + 1) * sizeof(int32_t));
-  if (!flags || !slot || !stmp || !ids) { c->err = "device allocation failed"; return G3_ENOMEM; }
+  if (!flags || !slot || !stmp) { c->err = "device allocation failed"; return G3_ENOMEM; }
   k_gas_flags<<<nblk(n), kBlock, 0, s>>>(type, n, flags);
   hipError_t e = scan_u32(flags, slot, n, stmp, s);
   if (e != hipSuccess) { c->err = "scan launch failed"; return G3_EHIP; }
-  k_gas_compact<<<nblk(n), kBlock, 0, s>>>(flags, slot, n, ids);
   k_soff<<<sb, kBlock, 0, s>>>(t->coff, t->n_snap, slot, t->gas.soff);
   e = hipMemcpyAsync(&c->pinned[2], slot + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
