@@ -237,7 +237,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     tune_s = time.perf_counter() - tt
     from paper_2003_10850_amd import g3
     nact = int(b.active.size)
-    tuned = {name: dict(zip(("walk_leaf", "split"), ctx.tuning(kind, nact)))
+    tuned = {name: dict(zip(("walk_leaf", "split", "streams"), ctx.tuning(kind, nact)))
              for name, kind in (("density", g3.G3_TUNE_DENSITY), ("hydro", g3.G3_TUNE_HYDRO),
                                 ("gravity", g3.G3_TUNE_GRAVITY))}
     print(f"bench: autotuned in {tune_s:.2f} s: {tuned}", file=sys.stderr, flush=True)
@@ -591,7 +591,7 @@ def main() -> int:
                      omega=torch.ones(n, device=dev))
         torch.cuda.synchronize()
         tune_s = time.perf_counter() - tt
-    tuned = {name: dict(zip(("walk_leaf", "split"), ctx.tuning(kind, n // 2 if kind < 2 else n)))
+    tuned = {name: dict(zip(("walk_leaf", "split", "streams"), ctx.tuning(kind, n // 2 if kind < 2 else n)))
              for name, kind in (("density", g3.G3_TUNE_DENSITY), ("hydro", g3.G3_TUNE_HYDRO),
                                 ("gravity", g3.G3_TUNE_GRAVITY))}
     print(f"bench: launch choices {tuned} (autotune {tune_s} s)", file=sys.stderr, flush=True)

@@ -252,14 +252,19 @@ int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
  *   split      -1: a group is up to 64 consecutive targets of one snapshot
  *              (default); L >= 0: groups also break where consecutive
  *              targets leave a level-L octree cell, so a sparse active set
- *              gives compact groups instead of wide ones.
+ *              gives compact groups instead of wide ones;
+ *   streams    density on FP32 trees: 1 (default) or 4 candidate streams
+ *              per wavefront; with 4, each quarter of the 64 lanes scans
+ *              only the candidates some lane of its quarter can reach
+ *              (other kinds and FP64 trees ignore it).
  * Choices are kept per ctx for each kind (G3_TUNE_*) and size class
  * floor(log2(number of targets)); a call uses its class's choice, else the
  * nearest tuned class's, else the defaults. */
 enum { G3_TUNE_DENSITY = 0, G3_TUNE_HYDRO = 1, G3_TUNE_GRAVITY = 2 };
 /* Time every candidate (walk_leaf 16, 32, 64, 128 x split -1, 2, 3, 4, 5
- * for the SPH kernels; split for gravity) on this tree and active set, and
- * keep the fastest per kind for this size class. The density runs its h
+ * for the SPH kernels, times streams 1, 4 for the density; split for
+ * gravity) on this tree and active set, and keep the fastest per kind for
+ * this size class. The density runs its h
  * solve on a copy of h (tree dtype; h[i] > 0 is a first guess); hydro is
  * tuned only when vel, u, rho and omega are given. Writes no output, and
  * leaves the ctx statistics unchanged. SYNCS. */
@@ -270,11 +275,11 @@ int g3_autotune(g3_ctx *ctx, g3_tree *tree, int64_t n_act, const int32_t *active
 /* The choice a call of `kind` over n_targets targets would use (host
  * outputs, nullable). */
 int g3_tuning_get(g3_ctx *ctx, int32_t kind, int64_t n_targets,
-                  int32_t *walk_leaf, int32_t *split);
+                  int32_t *walk_leaf, int32_t *split, int32_t *streams);
 /* Set the choice for n_targets' size class; n_targets < 0 replaces every
  * class of `kind` by this one choice. */
 int g3_tuning_set(g3_ctx *ctx, int32_t kind, int64_t n_targets,
-                  int32_t walk_leaf, int32_t split);
+                  int32_t walk_leaf, int32_t split, int32_t streams);
 
 /*
  * Adjoints (the _backward twins). The paper stops at the forward modules;

@@ -601,6 +601,8 @@ static SphParams sph_params(const g3_params *p, const g3_tree *t, const Tuning &
   sp.alpha = (float)p->alpha;
   sp.max_iter = 64;
   sp.walk_leaf = tu.walk_leaf;
+  // candidate streams exist for the FP32 density only
+  sp.streams = (!t->f64 && tu.streams == 4) ? 4 : 1;
   sp.f64 = t->f64;
   sp.slack = t->slack;
   return sp;
@@ -750,24 +752,26 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
 }
 
 int g3_tuning_get(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t *walk_leaf,
-                  int32_t *split) {
+                  int32_t *split, int32_t *streams) {
   if (!c) return G3_EINVAL;
   if (kind < 0 || kind >= kTuneKinds) return fail(c, G3_EINVAL, "g3_tuning_get: bad kind");
   const Tuning tu = tuning_for(c, kind, n_targets);
   if (walk_leaf) *walk_leaf = tu.walk_leaf;
   if (split) *split = tu.split;
+  if (streams) *streams = tu.streams;
   return G3_OK;
 }
 
 int g3_tuning_set(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t walk_leaf,
-                  int32_t split) {
+                  int32_t split, int32_t streams) {
   if (!c) return G3_EINVAL;
   if (kind < 0 || kind >= kTuneKinds || walk_leaf < 1 || walk_leaf > 4096 || split < -1 ||
-      split > kMaxLevel)
+      split > kMaxLevel || (streams != 1 && streams != 4))
     return fail(c, G3_EINVAL, "g3_tuning_set: bad arguments");
   Tuning tu;
   tu.walk_leaf = walk_leaf;
   tu.split = split;
+  tu.streams = kind == kTuneDensity ? streams : 1;
   if (n_targets < 0) {  // every size class of this kind: one entry
     for (auto it = c->tuning.begin(); it != c->tuning.end();)
       it = it->first.first == kind ? c->tuning.erase(it) : std::next(it);
@@ -837,11 +841,14 @@ int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, con
     if (!hs) return finish(fail(c, G3_ENOMEM, "g3_autotune: allocation failed"));
     Tuning best;
     float best_ms = INFINITY;
+    for (int streams : {1, 4})
     for (int leaf : kLeaves)
       for (int split : kSplits) {
+        if (streams > 1 && t->f64) continue;
         Tuning tu;
         tu.walk_leaf = leaf;
         tu.split = split;
+        tu.streams = streams;
         Work wk;
         float ms = 0.f;
         st = time_candidate(c, s, e0, e1, [&]() -> hipError_t {

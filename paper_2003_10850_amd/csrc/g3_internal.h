@@ -62,6 +62,7 @@ struct Octree {
 struct Tuning {
   int walk_leaf = 64;
   int split = -1;
+  int streams = 1;  // density: candidate streams per wave (1 or 4)
 };
 enum TuneKind { kTuneDensity = 0, kTuneHydro = 1, kTuneGravity = 2, kTuneKinds = 3 };
 
@@ -192,6 +193,7 @@ struct SphParams {
   float n_ngb, h_tol, gamma, alpha;
   int max_iter;
   int walk_leaf;  // SPH walks take subtrees of at most this many members whole
+  int streams;    // density candidate streams per wave (1 or 4; FP32 trees)
   int f64;        // FP64 positions and h: mixed-precision kernels
   float slack;    // walk pruning pad for FP32 copies of FP64 positions (0 if FP32)
 };

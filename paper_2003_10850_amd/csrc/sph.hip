@@ -30,11 +30,15 @@ constexpr float kC = 6.7889530412636603f;        // 1365 / (64 pi)
 constexpr float kNeffSelf = 28.4375f;            // (4 pi / 3) C = 1365 / 48
 constexpr float kF = -22.0f * 6.7889530412636603f;
 
-__device__ __forceinline__ void wc6_w_wh(float q, float &w, float &wh) {
+// With s = ln h and q = r/h: w(q), wh = -3 w - q w' (so that d(h^-3 w)/ds =
+// h^-3 wh), and wss = q w' + q^2 w'' = d(-q w')/ds, the curvature term of
+// the h solve.
+__device__ __forceinline__ void wc6_w_wh(float q, float &w, float &wh, float &wss) {
   const float t = 1.0f - q;
-  const float t2 = t * t, t4 = t2 * t2, t7 = t4 * t2 * t;
+  const float t2 = t * t, t4 = t2 * t2, t6 = t4 * t2, t7 = t6 * t;
   w = t7 * t * (1.0f + q * (8.0f + q * (25.0f + q * 32.0f)));
   wh = t7 * (-3.0f + q * (-21.0f + q * (-29.0f + q * (133.0f + q * 448.0f))));
+  wss = (q * q) * t6 * (-44.0f + q * (-264.0f + q * (132.0f + q * 3872.0f)));
 }
 
 // (1-q)^7 (1 + 7q + 16q^2), zero at and beyond the support
@@ -44,11 +48,13 @@ __device__ __forceinline__ float wc6_f(float q) {
   return t4 * t2 * t * (1.0f + q * (7.0f + q * 16.0f));
 }
 
-// First guess of h for a group: descend from the root along the group's
-// first member while the child still holds >= n_ngb members, then take the
-// mean density of that node's bounding box (of its cube if the box is flat).
-__device__ float group_density_guess(const Node *__restrict__ nodes, int root, int s0,
-                                     float n_ngb) {
+// First guess of h: descend from the root along target s while the child
+// still holds at least `least` members, then take that node's mean mass
+// density over its cube. (Against the converged h of clustered workloads,
+// a quarter of N_ngb over the cube gives a median error near 10 % where the
+// group-wide density of an N_ngb node gives 15 % with a heavier tail.)
+__device__ float node_density_guess(const Node *__restrict__ nodes, int root, int s,
+                                    float least) {
   int cur = root;
   for (;;) {
     const int4 meta = nodes[cur].meta;
@@ -56,20 +62,18 @@ __device__ float group_density_guess(const Node *__restrict__ nodes, int root, i
     int c = cur + 1, found = -1;
     while (c < meta.x) {
       const int4 cm = nodes[c].meta;
-      if (s0 >= cm.y && s0 < cm.y + cm.z) {
+      if (s >= cm.y && s < cm.y + cm.z) {
         found = c;
         break;
       }
       c = cm.x;
     }
-    if (found < 0 || (float)nodes[found].meta.z < n_ngb) break;
+    if (found < 0 || (float)nodes[found].meta.z < least) break;
     cur = found;
   }
   const Node nd = nodes[cur];
   const float l = nd.hi_l.w;
-  float V = (nd.hi_l.x - nd.lo_h.x) * (nd.hi_l.y - nd.lo_h.y) * (nd.hi_l.z - nd.lo_h.z);
-  if (!(V > 1e-3f * l * l * l)) V = l * l * l;
-  return nd.com_m.w / V;  // mass density
+  return nd.com_m.w / (l * l * l);
 }
 
 // FP64 neighbour test on the stored FP64 positions, the same expression as
@@ -87,7 +91,15 @@ __device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
 // test decides, which keeps every decision exact.
 constexpr float kBand64 = 1.9073486e-6f;  // 2^-19
 
-template <bool kF64>
+// Candidate streams per wave (kQ > 1, FP32 path): the lanes are split into
+// kQ quarters of 64/kQ targets, and a leaf or small subtree the walk accepts
+// is queued only for the quarters that have a lane reaching its box. A round
+// loads up to 64 queued candidates of every quarter into that quarter's
+// tile and each lane scans its own quarter's tile, so a lane tests the union
+// of its quarter's candidates instead of the whole wave's.
+constexpr int kRing = 256;  // queued candidate indices per quarter
+
+template <bool kF64, int kQ>
 __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, const float4 *__restrict__ xm,
     const double4 *__restrict__ x64, const int32_t *__restrict__ perm, const Groups gs,
@@ -97,8 +109,11 @@ __global__ __launch_bounds__(kBlock) void k_density(
     unsigned long long *__restrict__ counters) {
   using HT = typename std::conditional<kF64, double, float>::type;
   HT *h = (HT *)hptr;
-  __shared__ float4 tiles[kWpb][kF64 ? 1 : kTile];
+  static_assert(kQ == 1 || !kF64, "candidate streams are for the FP32 path");
+  __shared__ float4 tiles[kWpb][(kF64 || kQ > 1) ? 1 : kTile];
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
+  __shared__ int32_t ring[kWpb][kQ > 1 ? kQ : 1][kQ > 1 ? kRing : 1];
+  __shared__ float4 qtile[kWpb][kQ > 1 ? kQ : 1][kQ > 1 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   int range = 0;
   for (int g; (g = next_group(gs, range)) >= 0;) {
@@ -106,7 +121,6 @@ __global__ __launch_bounds__(kBlock) void k_density(
   const int64_t t = grp.t0 + lane;
   const bool valid = lane < grp.count;
   const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
-  const int s0 = uniform(gs.targets ? gs.targets[grp.t0] : grp.t0);
   // h_hi is capped at twice the diagonal of the snapshot's box
   const float hcap = (float)(3.4641016151377544 * gs.sbox[grp.snap].w);
   const float4 me = xm[s];
@@ -118,10 +132,10 @@ __global__ __launch_bounds__(kBlock) void k_density(
 
   HT hcur = valid ? h[cid] : HT(1);
   if (solve) {
-    if (__ballot(valid && !(hcur > HT(0)))) {
-      const float rho_g = group_density_guess(nodes, grp.root, s0, n_ngb);
+    if (valid && !(hcur > HT(0))) {
+      const float rho_g = node_density_guess(nodes, grp.root, s, 0.25f * n_ngb);
       const float guess = cbrtf(3.0f * n_ngb * me.w / (4.0f * 3.14159265f * rho_g));
-      if (!(hcur > HT(0))) hcur = (HT)fminf(guess, hcap);
+      hcur = (HT)fminf(guess, hcap);
     }
   }
   HT lo = HT(0), hi = HT(INFINITY);
@@ -143,8 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(hf + slack) : h2);
     const float band = kF64 ? h2 * kBand64 : 0.0f;
     const float hinv = 1.0f / hf;
-    // sums of m w and m wh: plain per tile, compensated across tiles
-    float sw = 0.0f, swh = 0.0f, csw = 0.0f, cswh = 0.0f;
+    // sums of m w, m wh and m wss: plain per tile, compensated across tiles
+    float sw = 0.0f, swh = 0.0f, sss = 0.0f, csw = 0.0f, cswh = 0.0f, csss = 0.0f;
     int cnt = 0;
     int tc = 0, cand = 0;
     auto flush = [&](int nc) {
@@ -158,13 +172,14 @@ __global__ __launch_bounds__(kBlock) void k_density(
       // under the lanes that pass, and is skipped when none does. (Marking
       // each lane's entries first and then visiting only its own measured
       // slower: it costs occupancy and per-lane LDS addressing.)
-      float pw = 0.0f, pwh = 0.0f;
+      float pw = 0.0f, pwh = 0.0f, pss = 0.0f;
       auto pair = [&](float r2, float mj) {
         const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
-        float wv, whv;
-        wc6_w_wh(u, wv, whv);
+        float wv, whv, wsv;
+        wc6_w_wh(u, wv, whv, wsv);
         pw += mj * wv;
         pwh += mj * whv;
+        pss += mj * wsv;
         ++cnt;
       };
       if constexpr (kF64) {
@@ -202,7 +217,63 @@ __global__ __launch_bounds__(kBlock) void k_density(
       }
       neumaier_add(sw, csw, pw);
       neumaier_add(swh, cswh, pwh);
+      neumaier_add(sss, csss, pss);
       wave_sync();
+    };
+    // candidate streams: queue positions (wave-uniform, monotone) and one
+    // round of evaluation over up to 64 queued candidates of every quarter
+    constexpr int kQl = kWave / kQ;
+    constexpr uint64_t kQmask = kQ > 1 ? ((1ull << kQl) - 1ull) : ~0ull;
+    int qhead[kQ], qtail[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) qhead[q] = qtail[q] = 0;
+    auto qround = [&]() {
+      if constexpr (kQ > 1) {
+        wave_sync();  // the queued indices are visible
+        int mx = 0;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const int nq = min(kTile, qtail[q] - qhead[q]);
+          mx = max(mx, nq);
+          float4 v = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+          if (lane < nq) v = xm[ring[w][q][(qhead[q] + lane) & (kRing - 1)]];
+          qtile[w][q][lane] = v;
+          qhead[q] += nq;
+        }
+        wave_sync();
+        const float4 *tq = qtile[w][lane / kQl];
+        float pw = 0.0f, pwh = 0.0f, pss = 0.0f;
+        const int ngr = (mx + 3) >> 2;
+        float4 a0 = tq[0], a1 = tq[1], a2 = tq[2], a3 = tq[3];
+        for (int gq = 0; gq < ngr; ++gq) {
+          const float4 q0 = a0, q1 = a1, q2 = a2, q3 = a3;
+          const int nx = min(4 * gq + 4, kTile - 4);
+          a0 = tq[nx];
+          a1 = tq[nx + 1];
+          a2 = tq[nx + 2];
+          a3 = tq[nx + 3];
+          const float4 qs[4] = {q0, q1, q2, q3};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float4 qq = qs[e];
+            const float r2 = dist2_exact(sub_exact(qq.x, xi.x), sub_exact(qq.y, xi.y),
+                                         sub_exact(qq.z, xi.z));
+            if (r2 < h2) {
+              const float u = __builtin_amdgcn_sqrtf(r2) * hinv;
+              float wv, whv, wsv;
+              wc6_w_wh(u, wv, whv, wsv);
+              pw += qq.w * wv;
+              pwh += qq.w * whv;
+              pss += qq.w * wsv;
+              ++cnt;
+            }
+          }
+        }
+        neumaier_add(sw, csw, pw);
+        neumaier_add(swh, cswh, pwh);
+        neumaier_add(sss, csss, pss);
+        wave_sync();
+      }
     };
     // The next node is either cur + 1 (descend) or the skip target: both
     // are loaded while the current one is tested, so the walk waits for one
@@ -216,10 +287,33 @@ __global__ __launch_bounds__(kBlock) void k_density(
       const Node ndb = nodes[min(next_b, last)];
       const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < hw2;
       bool descend = false;
-      if (__ballot(want) != 0ull) {
+      const uint64_t wm = __ballot(want);
+      if (wm != 0ull) {
         // a small subtree is taken whole: its members are one contiguous run
         if (!(nd.meta.w & kLeafBit) && nd.meta.z > walk_leaf) {
           descend = true;
+        } else if constexpr (kQ > 1) {
+          const int st = nd.meta.y, c = nd.meta.z;
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            if (((wm >> (q * kQl)) & kQmask) == 0ull) continue;
+            // appended a tile at a time: a leaf of coincident particles can
+            // hold more than the ring, and a round frees up to a tile
+            for (int off = 0; off < c; off += kTile) {
+              const int take = min(kTile, c - off);
+              while (qtail[q] - qhead[q] + take > kRing) qround();
+              if (lane < take) ring[w][q][(qtail[q] + lane) & (kRing - 1)] = st + off + lane;
+              qtail[q] += take;
+            }
+          }
+          // a round once every quarter has a full tile waiting
+          for (;;) {
+            bool full = true;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) full = full && qtail[q] - qhead[q] >= kTile;
+            if (!full) break;
+            qround();
+          }
         } else {
           int st = nd.meta.y, c = nd.meta.z;
           while (c > 0) {
@@ -238,30 +332,51 @@ __global__ __launch_bounds__(kBlock) void k_density(
       cur = descend ? next_a : next_b;
       nd = descend ? nda : ndb;
     }
-    if (tc > 0) flush(tc);
+    if constexpr (kQ > 1) {
+      for (;;) {  // drain
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) any = any || qtail[q] > qhead[q];
+        if (!any) break;
+        qround();
+      }
+    } else if (tc > 0) {
+      flush(tc);
+    }
     sw += csw;
     swh += cswh;
+    sss += csss;
 
     if (live) {
       if (!solve) {
         done = true;
         res_h = hcur; res_sw = sw; res_swh = swh; res_n = cnt;
       } else {
-        // N_eff(h) = (4 pi/3) h^3 rho / m_i = (1365/48) sum_j (m_j / m_i) w(q_j);
-        // its log-slope is 3 + h rho'/rho = 3 + sum m wh / sum m w.
+        // N_eff(h) = (4 pi/3) h^3 rho / m_i = (1365/48) sum_j (m_j / m_i) w(q_j).
+        // With A = sum m w as a function of s = ln h: A' = sum m (-q w') =
+        // 3 A + sum m wh and A'' = sum m wss, so ln N_eff has the slope
+        // f' = 3 + sum m wh / A and the curvature f'' = sum m wss / A - f'^2.
         const float N = kNeffSelf * sw / me.w;
         const bool below = N < n_ngb;
         if (below) lo = lo > hcur ? lo : hcur;
         else hi = hi < hcur ? hi : hcur;
         const float slope = 3.0f + swh / sw;
-        // Newton step on ln N_eff(ln h), in the precision of h; the log of
-        // the ratio (not a difference of logs) keeps the step accurate to a
-        // few 1e-8 near the root, well inside the convergence test below
+        // Halley step on f(s) = ln(N_eff / N_ngb) (cubic convergence: about
+        // one walk pass fewer than Newton from the node-density first
+        // guess), in the precision of h; the log of the ratio (not a
+        // difference of logs) keeps the step accurate to a few 1e-8 near the
+        // root, well inside the convergence test below. Far from the root,
+        // where the curvature factor leaves [1/2, 2], it is a Newton step.
         HT hn;
         if (N == n_ngb) hn = hcur;
-        else if (slope > 0.05f)
-          hn = hcur * (HT)exp((HT)log((HT)n_ngb / (HT)N) / (HT)slope);
-        else hn = below ? HT(2) * hcur : HT(0.5) * hcur;
+        else if (slope > 0.05f) {
+          const HT f = (HT)log((HT)N / (HT)n_ngb);
+          const float curv = sss / sw - slope * slope;
+          const HT den = HT(1) - f * (HT)(curv / (2.0f * slope * slope));
+          HT d = -f / (HT)slope;
+          if (den > HT(0.5) && den < HT(2)) d /= den;
+          hn = hcur * (HT)exp(d);
+        } else hn = below ? HT(2) * hcur : HT(0.5) * hcur;
         // converged when the Newton correction itself is below half the
         // tolerance (h then lies within it of the root), or the bracket has
         // closed; tested before any safeguard replaces the step
@@ -508,7 +623,8 @@ hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_group
                           float *drho_dh, float *omega, int32_t *nngb,
                           unsigned long long *counters, hipStream_t s) {
   if (max_groups <= 0 || gas.nnodes == 0) return hipSuccess;
-  auto kern = sp.f64 ? k_density<true> : k_density<false>;
+  auto kern = sp.f64 ? k_density<true, 1>
+                     : (sp.streams == 4 ? k_density<false, 4> : k_density<false, 1>);
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
       gas.nodes, gas.xm, gas.x64, gas.perm, gs, sp.n_ngb, sp.h_tol, solve_h, sp.max_iter,
       sp.walk_leaf, sp.slack, h, rho, drho_dh, omega, nngb, counters);

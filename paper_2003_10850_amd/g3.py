@@ -79,8 +79,8 @@ def lib():
             "g3_hydro_force_backward": ([P, P, i64, P, P] + [P] * 15, ctypes.c_int),
             "g3_gravity_backward": ([P, P, i64, P, P] + [P] * 5, ctypes.c_int),
             "g3_autotune": ([P, P, i64, P, P] + [P] * 6, ctypes.c_int),
-            "g3_tuning_get": ([P, i32, i64, P, P], ctypes.c_int),
-            "g3_tuning_set": ([P, i32, i64, i32, i32], ctypes.c_int),
+            "g3_tuning_get": ([P, i32, i64, P, P, P], ctypes.c_int),
+            "g3_tuning_set": ([P, i32, i64, i32, i32, i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -231,13 +231,15 @@ def g3_autotune(ctx, tree, n_act, active, params, h, vel, u, rho, omega, stream)
 
 
 def g3_tuning_get(ctx, kind, n_targets):
-    """(walk_leaf, split) a call of `kind` over n_targets targets uses."""
-    a, b = ctypes.c_int32(0), ctypes.c_int32(0)
-    st = lib().g3_tuning_get(ctx, int(kind), int(n_targets), ctypes.byref(a), ctypes.byref(b))
+    """(walk_leaf, split, streams) a call of `kind` over n_targets targets uses."""
+    a, b, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    st = lib().g3_tuning_get(ctx, int(kind), int(n_targets), ctypes.byref(a), ctypes.byref(b),
+                             ctypes.byref(c))
     _check(ctx, st, "g3_tuning_get")
-    return a.value, b.value
+    return a.value, b.value, c.value
 
 
-def g3_tuning_set(ctx, kind, n_targets, walk_leaf, split):
-    st = lib().g3_tuning_set(ctx, int(kind), int(n_targets), int(walk_leaf), int(split))
+def g3_tuning_set(ctx, kind, n_targets, walk_leaf, split, streams=1):
+    st = lib().g3_tuning_set(ctx, int(kind), int(n_targets), int(walk_leaf), int(split),
+                             int(streams))
     _check(ctx, st, "g3_tuning_set")

@@ -46,11 +46,12 @@ class Context:
         return self.stats(reset)[0]
 
     def tuning(self, kind: int, n_targets: int):
-        """(walk_leaf, split) the calls of `kind` over n_targets use."""
+        """(walk_leaf, split, streams) the calls of `kind` over n_targets use."""
         return g3.g3_tuning_get(self.handle, kind, n_targets)
 
-    def set_tuning(self, kind: int, walk_leaf: int, split: int, n_targets: int = -1):
-        g3.g3_tuning_set(self.handle, kind, n_targets, walk_leaf, split)
+    def set_tuning(self, kind: int, walk_leaf: int, split: int, n_targets: int = -1,
+                   streams: int = 1):
+        g3.g3_tuning_set(self.handle, kind, n_targets, walk_leaf, split, streams)
 
     def autotune(self, tree, h, vel=None, u=None, rho=None, omega=None, params=None,
                  active=None):

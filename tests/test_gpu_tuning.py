@@ -63,18 +63,20 @@ def run_step(ctx, b, tree, h0):
                                           nterms=g["nterms"]).items()}
 
 
-def set_all(ctx, leaf, split):
+def set_all(ctx, leaf, split, streams=1):
     from paper_2003_10850_amd import g3
     for kind in (g3.G3_TUNE_DENSITY, g3.G3_TUNE_HYDRO, g3.G3_TUNE_GRAVITY):
-        ctx.set_tuning(kind, leaf, split)
+        ctx.set_tuning(kind, leaf, split, streams=streams)
 
 
-@pytest.mark.parametrize("leaf,split", [(16, -1), (128, -1), (64, 2), (32, 4), (16, 6)])
-def test_choices_change_no_count(setup, leaf, split):
+@pytest.mark.parametrize("leaf,split,streams", [(16, -1, 1), (128, -1, 1), (64, 2, 1),
+                                                (32, 4, 1), (16, 6, 1), (64, -1, 4),
+                                                (128, 3, 4), (16, -1, 4)])
+def test_choices_change_no_count(setup, leaf, split, streams):
     ctx, b, tree, h0 = setup
     set_all(ctx, 64, -1)
     ref = run_step(ctx, b, tree, h0)
-    set_all(ctx, leaf, split)
+    set_all(ctx, leaf, split, streams)
     got = run_step(ctx, b, tree, h0)
     set_all(ctx, 64, -1)
     a = b.active
@@ -90,9 +92,10 @@ def test_choices_change_no_count(setup, leaf, split):
         assert np.abs(got[k][rows] - ref[k][rows]).max() <= 1e-4 * scale, k
 
 
-def test_split_groups_against_oracle(setup):
+@pytest.mark.parametrize("streams", [1, 4])
+def test_split_groups_against_oracle(setup, streams):
     ctx, b, tree, h0 = setup
-    set_all(ctx, 32, 3)
+    set_all(ctx, 32, 3, streams)
     got = run_step(ctx, b, tree, h0)
     set_all(ctx, 64, -1)
     for k, w in enumerate(b.snaps):
@@ -125,9 +128,9 @@ def test_autotune_picks_candidates(setup):
     ctx.autotune(tree, dev_t(h0), active=dev_t(b.active))
     assert ctx.stats() == before  # the tuning runs leave the statistics alone
     n = b.active.size
-    leaf, split = ctx.tuning(g3.G3_TUNE_DENSITY, n)
-    assert leaf in (16, 32, 64, 128) and split in (-1, 2, 3, 4, 5)
-    _, gsplit = ctx.tuning(g3.G3_TUNE_GRAVITY, n)
+    leaf, split, streams = ctx.tuning(g3.G3_TUNE_DENSITY, n)
+    assert leaf in (16, 32, 64, 128) and split in (-1, 2, 3, 4, 5) and streams in (1, 4)
+    _, gsplit, _ = ctx.tuning(g3.G3_TUNE_GRAVITY, n)
     assert gsplit in (-1, 2, 3, 4, 5)
     print(f"autotuned: density leaf {leaf} split {split}, gravity split {gsplit}")
     got = run_step(ctx, b, tree, h0)
