@@ -247,33 +247,39 @@ int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
  * change neither a count nor a decision, only the order in which FP32
  * partial sums are formed (so results agree to rounding):
  *   walk_leaf  SPH walks take octree subtrees of at most this many members
- *              whole into a candidate tile instead of descending (1..4096;
- *              default 64);
- *   split      -1: a group is up to 64 consecutive targets of one snapshot
- *              (default); L >= 0: groups also break where consecutive
- *              targets leave a level-L octree cell, so a sparse active set
- *              gives compact groups instead of wide ones;
- *   streams    density on FP32 trees: 1 (default) or 4 candidate streams
- *              per wavefront; with 4, each quarter of the 64 lanes scans
- *              only the candidates some lane of its quarter can reach
- *              (other kinds and FP64 trees ignore it).
+ *              whole into a candidate tile instead of descending (1..4096);
+ *   split      -1: a group is up to 64 consecutive targets of one snapshot;
+ *              L >= 0: groups also break where consecutive targets leave a
+ *              level-L octree cell, so a sparse active set gives compact
+ *              groups instead of wide ones; G3_SPLIT_AUTO: L is taken per
+ *              snapshot from its member count m as floor(log8(m / 128)),
+ *              the level whose cells hold about 128 members (no level
+ *              break where that is below 1);
+ *   streams    density on FP32 trees: 1 or 4 candidate streams per
+ *              wavefront; with 4, each quarter of the 64 lanes scans only
+ *              the candidates some lane of its quarter can reach (other
+ *              kinds and FP64 trees ignore it).
  * Choices are kept per ctx for each kind (G3_TUNE_*) and size class
  * floor(log2(number of targets)); a call uses its class's choice, else the
- * nearest tuned class's, else the defaults. */
+ * nearest tuned class's, else the defaults: density walk_leaf 128, split
+ * G3_SPLIT_AUTO; hydro and gravity walk_leaf 64, split -1; streams 1.
+ * Every default depends on per-snapshot quantities only, so a snapshot in a
+ * forest forms the same groups as on its own tree. */
 enum { G3_TUNE_DENSITY = 0, G3_TUNE_HYDRO = 1, G3_TUNE_GRAVITY = 2 };
-/* Time every candidate (walk_leaf 16, 32, 64, 128 x split -1, 2, 3, 4, 5
- * for the SPH kernels, times streams 1, 4 for the density; split for
- * gravity) on this tree and active set, and keep the fastest per kind for
- * this size class. The density runs its h
- * solve on a copy of h (tree dtype; h[i] > 0 is a first guess); hydro is
- * tuned only when vel, u, rho and omega are given. Writes no output, and
- * leaves the ctx statistics unchanged. SYNCS. */
+enum { G3_SPLIT_AUTO = -2 };
+/* Time every candidate (walk_leaf 16, 32, 64, 128 x split -1,
+ * G3_SPLIT_AUTO, 2, 3, 4, 5 for the SPH kernels, times streams 1, 4 for the
+ * density; split for gravity) on this tree and active set, and keep the
+ * fastest per kind for this size class. The density runs its h solve on a
+ * copy of h (tree dtype; h[i] > 0 is a first guess); hydro is tuned only
+ * when vel, u, rho and omega are given. Writes no output, and leaves the
+ * ctx statistics unchanged. SYNCS. */
 int g3_autotune(g3_ctx *ctx, g3_tree *tree, int64_t n_act, const int32_t *active,
                 const g3_params *p, const void *h, const float *vel,
                 const float *u, const float *rho, const float *omega,
                 void *stream);
-/* The choice a call of `kind` over n_targets targets would use (host
- * outputs, nullable). */
+/* The choice a call of `kind` over n_targets targets of one snapshot would
+ * use (host outputs, nullable). */
 int g3_tuning_get(g3_ctx *ctx, int32_t kind, int64_t n_targets,
                   int32_t *walk_leaf, int32_t *split, int32_t *streams);
 /* Set the choice for n_targets' size class; n_targets < 0 replaces every

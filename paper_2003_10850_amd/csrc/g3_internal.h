@@ -59,9 +59,14 @@ struct Octree {
 // Launch choices that never change a count or a decision (only the order in
 // which FP32 partial sums are formed): SPH walks take subtrees of at most
 // walk_leaf members whole; split >= 0 cuts groups at level-`split` cells.
+// Group split level chosen per snapshot from its member count m:
+// floor(log8(m / 128)), the level whose cells hold about 128 members on
+// average (no level cut below 1).
+constexpr int kSplitAuto = -2;
+
 struct Tuning {
   int walk_leaf = 64;
-  int split = -1;
+  int split = -1;  // -1 none, kSplitAuto, or a level
   int streams = 1;  // density: candidate streams per wave (1 or 4)
 };
 enum TuneKind { kTuneDensity = 0, kTuneHydro = 1, kTuneGravity = 2, kTuneKinds = 3 };

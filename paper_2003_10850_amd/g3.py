@@ -222,6 +222,7 @@ def g3_gravity_backward(ctx, tree, n_act, active, params, g_acc, g_pot, g_pos, g
 
 
 G3_TUNE_DENSITY, G3_TUNE_HYDRO, G3_TUNE_GRAVITY = 0, 1, 2
+G3_SPLIT_AUTO = -2
 
 
 def g3_autotune(ctx, tree, n_act, active, params, h, vel, u, rho, omega, stream):

@@ -1,6 +1,7 @@
 """GPU tests of the launch tuning: the autotuner's choices (candidate tile
-depth walk_leaf, group split level) may change only the order of FP32
-partial sums, never a count or a decision.
+depth walk_leaf, group split level, fixed or per snapshot (-2), candidate
+streams) may change only the order of FP32 partial sums, never a count or a
+decision.
 
 Every choice is run on a forest with time-bin (sparse, clustered) active
 sets; neighbour, pair and term counts must equal those of the default
@@ -71,7 +72,8 @@ def set_all(ctx, leaf, split, streams=1):
 
 @pytest.mark.parametrize("leaf,split,streams", [(16, -1, 1), (128, -1, 1), (64, 2, 1),
                                                 (32, 4, 1), (16, 6, 1), (64, -1, 4),
-                                                (128, 3, 4), (16, -1, 4)])
+                                                (128, 3, 4), (16, -1, 4), (128, -2, 1),
+                                                (64, -2, 4)])
 def test_choices_change_no_count(setup, leaf, split, streams):
     ctx, b, tree, h0 = setup
     set_all(ctx, 64, -1)
@@ -129,9 +131,9 @@ def test_autotune_picks_candidates(setup):
     assert ctx.stats() == before  # the tuning runs leave the statistics alone
     n = b.active.size
     leaf, split, streams = ctx.tuning(g3.G3_TUNE_DENSITY, n)
-    assert leaf in (16, 32, 64, 128) and split in (-1, 2, 3, 4, 5) and streams in (1, 4)
+    assert leaf in (16, 32, 64, 128) and split in (-1, -2, 2, 3, 4, 5) and streams in (1, 4)
     _, gsplit, _ = ctx.tuning(g3.G3_TUNE_GRAVITY, n)
-    assert gsplit in (-1, 2, 3, 4, 5)
+    assert gsplit in (-1, -2, 2, 3, 4, 5)
     print(f"autotuned: density leaf {leaf} split {split}, gravity split {gsplit}")
     got = run_step(ctx, b, tree, h0)
     a = b.active
