@@ -28,6 +28,10 @@ struct __align__(16) Entry {
   float4 p;       // source position, mass
   int4 meta;      // source sorted index (-1: node), mask low, mask high, unused
 };
+// A lane's mask word is meta.y (lanes 0..31) or meta.z (lanes 32..63); the
+// bit of a lane whose own target is the source is cleared when the entry is
+// made, so the tile loop needs no self test.
+constexpr int kMaskWord = 5;  // meta.y as the 32-bit word index within Entry
 
 // The opening test, exact in FP32: fl(l * l) < fl(theta2 * r2).
 __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
@@ -84,14 +88,17 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   // this lane's bit in an entry's mask: word (low or high half) and offset
   const bool hiword = lane >= 32;
   const uint32_t bitpos = (uint32_t)lane & 31u;
+  // this lane's mask word of entry k sits at word kMaskWord + hiword of it
+  const uint32_t *maskw = (const uint32_t *)tile + kMaskWord + (hiword ? 1 : 0);
   auto flush = [&](int nc) {
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
     for (int k = 0; k < nc; ++k) {
-      const Entry e = tile[k];
-      // branch-free use test: the lane's mask bit, and not the target itself
-      const uint32_t word = (uint32_t)(hiword ? e.meta.z : e.meta.y);
-      const bool use = (__builtin_amdgcn_ubfe(word, bitpos, 1u) != 0u) & (e.meta.x != s);
+      const float4 ep = tile[k].p;
+      // branch-free use: the signed extract of the lane's bit is 0 or all
+      // ones, and masks the source mass
+      const int32_t use = __builtin_amdgcn_sbfe((int32_t)maskw[k * (int)(sizeof(Entry) / 4)],
+                                                bitpos, 1u);
       float dx, dy, dz;
       if constexpr (kF64) {
         const double4 q = tile64[k];
@@ -99,13 +106,13 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
         dy = (float)(q.y - p64.y);
         dz = (float)(q.z - p64.z);
       } else {
-        dx = e.p.x - xi.x;
-        dy = e.p.y - xi.y;
-        dz = e.p.z - xi.z;
+        dx = ep.x - xi.x;
+        dy = ep.y - xi.y;
+        dz = ep.z - xi.z;
       }
       const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
       const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float mr = (use ? e.p.w : 0.0f) * rinv;
+      const float mr = __int_as_float(__float_as_int(ep.w) & use) * rinv;
       const float mr3 = mr * rinv * rinv;
       px += mr3 * dx;
       py += mr3 * dy;
@@ -190,6 +197,14 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
         if constexpr (kF64) tile64[tc + lane] = x64[st + lane];
         e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
         tile[tc + lane] = e;
+      }
+      wave_sync();
+      // an opening lane whose own target is among these members clears its
+      // bit in that member's entry (one lane per entry)
+      const int rel = s - st;
+      if (act && !accept && rel >= 0 && rel < take) {
+        uint32_t *wd = (uint32_t *)&tile[tc + rel] + kMaskWord + (hiword ? 1 : 0);
+        *wd &= ~(1u << bitpos);
       }
       tc += take;
       st += take;
