@@ -140,6 +140,13 @@ def copy_calibration(dev) -> None:
     torch.cuda.synchronize()
 
 
+def is_plain_kernel(full_name: str, k: str) -> bool:
+    """Whether a profiler kernel name is the FP32 (plain) instance of g3 kernel k:
+    k(...), k<false>(...) or k<false, streams>(...)."""
+    import re
+    return re.search(rf"::{k}(<false(, \d+)?>)?\(", full_name) is not None
+
+
 def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     """HBM bytes per launch of each g3 kernel from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the same
@@ -169,8 +176,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     for name in ("k_density", "k_hydro", "k_gravity"):
         per = {}
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
-            vals = [v for k, vs in data[counter].items()
-                    if f"::{name}(" in k or f"::{name}<false>(" in k for v in vs]
+            vals = [v for k, vs in data[counter].items() if is_plain_kernel(k, name) for v in vs]
             per[counter] = float(np.mean(vals)) * 1024 / scale[counter] if vals else None
         if per["FETCH_SIZE"] is not None and per["WRITE_SIZE"] is not None:
             out["kernels"][name] = {"fetch_bytes": per["FETCH_SIZE"],
@@ -493,7 +499,7 @@ def summarize_valu(csv_path: str, out_json: str, n_cu: int = 256) -> dict:
     for r in csv.DictReader(open(csv_path)):
         name = r["Kernel_Name"]
         for k in ("k_density", "k_hydro", "k_gravity"):
-            if f"::{k}<false>(" in name or f"::{k}(" in name:
+            if is_plain_kernel(name, k):
                 acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
                 dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     out = {"counters": list(VALU_COUNTERS), "cu": n_cu, "kernels": {}}
