@@ -473,6 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
   const double hi64 = kF64 ? h64[s] : 0.0;
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
+  const float hi2 = valid ? sq_exact(hi) : -1.0f;
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
   const float ki = kF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
   // totals with Neumaier compensation terms; per-tile partials are plain
@@ -519,7 +520,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           const float wneg = fminf(wv, 0.0f);
           const float vsig_ij = ci + qa.y - 3.0f * wneg;
           vs = fmaxf(vs, vsig_ij);
-          const float Pi = alpha * vsig_ij * (-wneg) / (rhoi + qa.z);
+          // the hardware reciprocal (1 ulp) in place of an IEEE division
+          const float Pi = alpha * vsig_ij * (-wneg) * __builtin_amdgcn_rcpf(rhoi + qa.z);
           const float gbar = 0.5f * (gi + gj);
           const float mj = q.w;
           const float coef = mj * (Ai * gi + qa.x * gj + Pi * gbar);  // a_i -= coef x_ij
@@ -547,10 +549,12 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
         dz = sub_exact(q.z, xi.z);
       }
       const float r2 = dist2_exact(dx, dy, dz);
-      const float H = fmaxf(hi, qv.w);
-      const float H2 = sq_exact(H);
-      bool in = r2 < H2;
+      // r2 < fl(max(h_i, h_j)^2) taken as r2 < fl(h_i^2) or r2 < fl(h_j^2)
+      // (the same decision: rounding is monotone), without a max
+      const float hj2 = sq_exact(qv.w);
+      bool in = r2 < hi2 || r2 < hj2;
       if constexpr (kF64) {
+        const float H2 = fmaxf(hi2, hj2);
         if (valid && fabsf(r2 - H2) <= H2 * kBand64)
           in = within64(p64, tiles64[w][k], fmax(hi64, th64[w][k]));
       }
