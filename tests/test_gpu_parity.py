@@ -94,6 +94,23 @@ def test_tree_with_coincident_chain(ctx):
     tree_matches(c, 1)
 
 
+@pytest.mark.parametrize("streams", [1, 4])
+def test_density_leaf_larger_than_the_queues(ctx, streams):
+    """601 coincident gas particles make one level-21 leaf of 601 members,
+    more than a candidate tile (64) and a candidate-stream queue (256)."""
+    from paper_2003_10850_amd import g3
+    w = inputs.plummer(n=8000, n_spheres=3, seed=5, n_ngb=64.0)
+    gas = np.nonzero(w.type == 0)[0]
+    w.pos[gas[:600]] = w.pos[gas[600]]
+    c = Case(ctx, w)
+    ctx.set_tuning(g3.G3_TUNE_DENSITY, 16, -1, streams=streams)
+    try:
+        d, _ = density_check(c, solve=False)
+    finally:
+        ctx.set_tuning(g3.G3_TUNE_DENSITY, 128, -2)
+    assert host(d["nngb"])[gas[:601]].min() >= 601
+
+
 def density_check(c, active=None, solve=True):
     from paper_2003_10850_amd import ops
     act_gas = c.gas if active is None else np.intersect1d(active, c.gas)
