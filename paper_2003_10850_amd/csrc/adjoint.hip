@@ -201,31 +201,69 @@ __global__ __launch_bounds__(kBlock) void k_density_bwd(
 
 // ---------------------------------------------------------------- gravity
 
-// v shifted by a DPP row operation; lanes without a source read 0
-template <int kCtrl, int kRowMask = 0xf>
-__device__ __forceinline__ float dpp_or_zero(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf,
+// v from the lane paired with this one by a DPP permutation (every lane
+// active, every lane a source)
+template <int kCtrl>
+__device__ __forceinline__ float dpp_from(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf,
                                                     false));
 }
 
-// Sum of v over the 64 lanes, left in lane 63: an inclusive scan within
-// each row of 16 lanes (row_shr 1, 2, 4, 8), then the last lane of rows 0
-// and 2 added to rows 1 and 3 (row_bcast 15) and lane 31 to rows 2 and 3
-// (row_bcast 31). Every lane must be active.
-__device__ __forceinline__ float wave_total_in_lane63(float v) {
-  v += dpp_or_zero<0x111>(v);
-  v += dpp_or_zero<0x112>(v);
-  v += dpp_or_zero<0x114>(v);
-  v += dpp_or_zero<0x118>(v);
-  v += dpp_or_zero<0x142, 0xa>(v);
-  v += dpp_or_zero<0x143, 0xc>(v);
-  return v;
+// Sums over the 64 lanes of v[0..15], spread so that lane l ends with the
+// total of value (l >> 2) & 15, by recursive halving: at each of four steps
+// the lanes pair off across one lane bit (5, 4, 3, 2), and each keeps the
+// half of its values that its bit selects plus its partner's copy of that
+// half; two pairwise exchanges (bits 1, 0) then complete the quads' sums.
+// Lane pairs: xor 32 and xor 16 by LDS permute, then the DPP row mirror
+// (xor 15), half-row mirror (xor 7) and the quad permutations xor 3, xor 1;
+// each pairs lanes that differ in the step's bit and agree in the bits
+// above it. Every lane must be active.
+__device__ __forceinline__ float wave_reduce_scatter16(float (&v)[16], int lane) {
+  {
+    const bool up = (lane & 32) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float send = up ? v[i] : v[i + 8];
+      const float keep = up ? v[i + 8] : v[i];
+      v[i] = keep + __shfl_xor(send, 32);
+    }
+  }
+  {
+    const bool up = (lane & 16) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = up ? v[i] : v[i + 4];
+      const float keep = up ? v[i + 4] : v[i];
+      v[i] = keep + __shfl_xor(send, 16);
+    }
+  }
+  {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + dpp_from<0x140>(send);  // row mirror: lane ^ 15 in its row
+    }
+  }
+  {
+    const bool up = (lane & 4) != 0;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + dpp_from<0x141>(send);  // half-row mirror: lane ^ 7
+  }
+  v[0] += dpp_from<0x1b>(v[0]);  // quad permutation (3, 2, 1, 0): lane ^ 3
+  v[0] += dpp_from<0xb1>(v[0]);  // quad permutation (1, 0, 3, 2): lane ^ 1
+  return v[0];
 }
 
 struct __align__(16) GEntry {
   float4 p;   // source position, mass
   int4 meta;  // sorted source index, or -(node + 1); mask low, mask high; unused
 };
+// a lane's mask word: meta.y (lanes 0..31) or meta.z (lanes 32..63), the
+// 32-bit words 5 and 6 of an entry
+constexpr int kGMaskWord = 5;
 
 __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
 #pragma clang fp contract(off)
@@ -266,38 +304,55 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
     int tc = 0;
     const bool hiword = lane >= 32;
     const uint32_t bitpos = (uint32_t)lane & 31u;
+    const uint32_t *maskw = (const uint32_t *)tile + kGMaskWord + (hiword ? 1 : 0);
     auto flush = [&](int nc) {
+      // padded to a multiple of four with entries no lane uses
+      const int n4 = (nc + 3) & ~3;
+      if (lane >= nc && lane < n4) {
+        tile[lane].p = make_float4(0.f, 0.f, 0.f, 0.f);
+        tile[lane].meta = make_int4(0, 0, 0, 0);
+      }
       wave_sync();
       float px = 0.f, py = 0.f, pz = 0.f;
-      for (int k = 0; k < nc; ++k) {
-        const GEntry e = tile[k];
-        const uint32_t word = (uint32_t)(hiword ? e.meta.z : e.meta.y);
-        const bool use = (__builtin_amdgcn_ubfe(word, bitpos, 1u) != 0u) & (e.meta.x != s);
-        const float dx = e.p.x - me.x, dy = e.p.y - me.y, dz = e.p.z - me.z;  // x_s - x_i
-        const float S = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-        const float inv = __builtin_amdgcn_rsqf(S);
-        const float inv3 = inv * inv * inv;
-        const float Gm = use ? G * e.p.w : 0.0f;
-        const float gx_ = -(gax * dx + gay * dy + gaz * dz);  // ga . x, x = x_i - x_s
-        const float c3 = 3.0f * gx_ * inv3 * inv * inv;
-        // dL/dx with x = -(dx, dy, dz)
-        const float Dx = Gm * (-gax * inv3 - c3 * dx - gpp * dx * inv3);
-        const float Dy = Gm * (-gay * inv3 - c3 * dy - gpp * dy * inv3);
-        const float Dz = Gm * (-gaz * inv3 - c3 * dz - gpp * dz * inv3);
-        const float Dm = use ? -G * (gx_ * inv3 + gpp * inv) : 0.0f;
-        px += Dx;
-        py += Dy;
-        pz += Dz;
-        const float sx = wave_total_in_lane63(-Dx);
-        const float sy = wave_total_in_lane63(-Dy);
-        const float sz = wave_total_in_lane63(-Dz);
-        const float sm = wave_total_in_lane63(Dm);
-        if (lane == 63) {
-          float4 *dst = e.meta.x >= 0 ? &gsrc[e.meta.x] : &gnode[-e.meta.x - 1];
-          atomicAdd(&dst->x, sx);
-          atomicAdd(&dst->y, sy);
-          atomicAdd(&dst->z, sz);
-          atomicAdd(&dst->w, sm);
+      for (int k0 = 0; k0 < n4; k0 += 4) {
+        // the source sides of four entries: (-dL/dx_i, dL/dm_s) per entry
+        float v[16];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + e;
+          const float4 ep = tile[k].p;
+          // 0 or all ones: the lane's bit (its own target's bit is clear)
+          const int32_t use = __builtin_amdgcn_sbfe(
+              (int32_t)maskw[k * (int)(sizeof(GEntry) / 4)], bitpos, 1u);
+          const float dx = ep.x - me.x, dy = ep.y - me.y, dz = ep.z - me.z;  // x_s - x_i
+          const float S =
+              __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+          // masked here, so that an unused entry adds exact zeros even at S = 0
+          const float inv = __int_as_float(__float_as_int(__builtin_amdgcn_rsqf(S)) & use);
+          const float inv3 = inv * inv * inv;
+          const float Gm = G * ep.w;
+          const float gx_ = -(gax * dx + gay * dy + gaz * dz);  // ga . x, x = x_i - x_s
+          const float c3 = 3.0f * gx_ * inv3 * inv * inv;
+          // dL/dx with x = -(dx, dy, dz)
+          const float Dx = Gm * (-gax * inv3 - c3 * dx - gpp * dx * inv3);
+          const float Dy = Gm * (-gay * inv3 - c3 * dy - gpp * dy * inv3);
+          const float Dz = Gm * (-gaz * inv3 - c3 * dz - gpp * dz * inv3);
+          const float Dm = -G * (gx_ * inv3 + gpp * inv);
+          px += Dx;
+          py += Dy;
+          pz += Dz;
+          v[4 * e] = -Dx;
+          v[4 * e + 1] = -Dy;
+          v[4 * e + 2] = -Dz;
+          v[4 * e + 3] = Dm;
+        }
+        // lane l holds the wave's total of entry l >> 4, component (l >> 2) & 3
+        const float tot = wave_reduce_scatter16(v, lane);
+        const int e = lane >> 4, comp = (lane >> 2) & 3;
+        if ((lane & 3) == 0 && k0 + e < nc) {
+          const int src = tile[k0 + e].meta.x;
+          float *dst = src >= 0 ? (float *)&gsrc[src] : (float *)&gnode[-src - 1];
+          atomicAdd(dst + comp, tot);
         }
       }
       neumaier_add(ox, cox, px);
@@ -354,6 +409,14 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
           e.p = xm[st + lane];
           e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
           tile[tc + lane] = e;
+        }
+        wave_sync();
+        // an opening lane whose own target is among these members clears
+        // its bit in that member's entry (one lane per entry)
+        const int rel = s - st;
+        if (act && !accept && rel >= 0 && rel < take) {
+          uint32_t *wd = (uint32_t *)&tile[tc + rel] + kGMaskWord + (hiword ? 1 : 0);
+          *wd &= ~(1u << bitpos);
         }
         tc += take;
         st += take;

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     for (int k = 0; k < nc; ++k) {
       const float4 ep = tile[k].p;
       // branch-free use: the signed extract of the lane's bit is 0 or all
-      // ones, and masks the source mass
+      // ones, and masks the inverse distance
       const int32_t use = __builtin_amdgcn_sbfe((int32_t)maskw[k * (int)(sizeof(Entry) / 4)],
                                                 bitpos, 1u);
       float dx, dy, dz;
@@ -111,8 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
         dz = ep.z - xi.z;
       }
       const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-      const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float mr = __int_as_float(__float_as_int(ep.w) & use) * rinv;
+      // masked here (not the mass), so that an unused entry adds exact
+      // zeros even at r2 = 0 (the own entry with zero softening)
+      const float rinv = __int_as_float(__float_as_int(__builtin_amdgcn_rsqf(r2)) & use);
+      const float mr = ep.w * rinv;
       const float mr3 = mr * rinv * rinv;
       px += mr3 * dx;
       py += mr3 * dy;

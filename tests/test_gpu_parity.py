@@ -227,6 +227,14 @@ def test_gravity_clustered(ctx, theta):
     gravity_check(c, inputs.Params(theta=theta, eps=1e-3))
 
 
+def test_gravity_unsoftened(ctx):
+    """eps = 0: the own entry of every target (r = 0) must add exact zeros."""
+    w = inputs.plummer(n=6000, n_spheres=4, seed=16)
+    c = Case(ctx, w)
+    assert len(np.unique(c.pos32, axis=0)) == w.n  # distinct positions
+    gravity_check(c, inputs.Params(theta=0.5, eps=0.0))
+
+
 def test_gravity_active_subset(ctx):
     w = inputs.plummer(n=40000, n_spheres=6, seed=15)
     c = Case(ctx, w)
