@@ -187,6 +187,15 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:
     return out
 
 
+def step_roofline(counts, ms: float) -> dict:
+    """Whole-step FP32 roofline position: (density, hydro, gravity)
+    interaction counts times their algorithmic FLOP, over the step time."""
+    flop = FLOP_DENSITY * counts[0] + FLOP_HYDRO * counts[1] + FLOP_GRAVITY * counts[2]
+    achieved = flop / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS}
+
+
 def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -> dict:
     """The batching workload: a forest of n_snap Plummer snapshots (sizes
     log-uniform in [1e3, 1e6]) with time-bin active sets. One step = the
@@ -302,8 +311,9 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         step64()
     torch.cuda.synchronize()
     mixed_ms = 1e3 * (time.perf_counter() - t6) / steps
-    i64 = (int(B["nngb"][T(gas_act)].sum()) + int(B["npairs"][T(gas_act)].sum()) +
+    k64 = (int(B["nngb"][T(gas_act)].sum()), int(B["npairs"][T(gas_act)].sum()),
            int(B["nterms"][act.long()].sum()))
+    i64 = sum(k64)
     tree64.close()
     ctx.nonconverged(reset=True)
     print(f"bench: batched mixed precision {mixed_ms:.3f} ms/step", file=sys.stderr, flush=True)
@@ -363,7 +373,11 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
         "snapshots_below_1e3_active": int(sum(
             int(((b.active >= b.snap_off[k]) & (b.active < b.snap_off[k + 1])).sum()) < 1000
             for k in range(b.n_snap))),
+        # algorithmic FP32 work of the step (per-interaction operation counts)
+        # over its time, against the FP32 vector peak
+        "fp32_roofline": step_roofline((i_d, i_h, i_g), graph_ms),
         "mixed_precision": {"ms_per_step": mixed_ms, "value": i64 / (mixed_ms * 1e-3),
+                            "fp32_roofline": step_roofline(k64, mixed_ms),
                             "path": "FP64 positions and h, FP32 offsets from each target, "
                                     "FP64 decisions in the error band, eager calls"},
         "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
@@ -463,8 +477,8 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
     gas = T(w.type == 0)
-    inter = (int(od["nngb"][gas].sum()) + int(oh["npairs"][gas].sum()) +
-             int(og["nterms"].sum()))
+    kinds = (int(od["nngb"][gas].sum()), int(oh["npairs"][gas].sum()), int(og["nterms"].sum()))
+    inter = sum(kinds)
     nonconv = ctx.nonconverged(reset=True)
     print(f"bench: precision {ms:.3f} ms/step, {inter} interactions", file=sys.stderr,
           flush=True)
@@ -475,6 +489,7 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
         "unit": "interactions/s",
         "ms_per_step": ms,
         "interactions_per_step": inter,
+        "fp32_roofline": step_roofline(kinds, ms),
         "h_nonconverged": nonconv,
         "path": "mixed precision: FP64 positions, FP32 offsets from each target, compensated "
                 "FP32 sums, FP64 moments and h solve, FP64 decisions in the error band",
@@ -695,6 +710,8 @@ def main() -> int:
                    "h_passes_per_wave": passes / max(waves, 1), "path": "plain",
                    "launch_choices": tuned, "autotune_s": tune_s},
         "roofline": roofline,
+        # the whole plain step's algorithmic FP32 work against the same peak
+        "step_fp32_roofline": step_roofline((i_d, i_h, i_g), ms),
     }
     if not args.no_batched:
         line["batched"] = run_batched(dev, args.steps, args.warmup)
