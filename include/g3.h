@@ -146,6 +146,21 @@ int g3_build_forest(g3_ctx *ctx, int32_t n_snap, const int64_t *snap_off,
                     int32_t pos_t, const void *pos, const float *mass,
                     const uint8_t *type, const double *box, const g3_params *p,
                     g3_tree **tree, void *stream);
+/* Refit a built tree to moved particles without rebuilding it: the drift
+ * update a code makes between rebuilds, when particles have moved little
+ * since the build (the paper's tree is rebuilt only from time to time, §1).
+ * The member order, octree topology, Morton keys and node cube sides of the
+ * build stay; the members' positions and masses are re-read and every
+ * node's centre of mass, mass and tight bounding box is recomputed, so SPH
+ * neighbour sums stay exact at any drift. Barnes-Hut decisions use the
+ * build's cube sides (and, for theta^2 >= 1/3, its cells for the
+ * containment test), so their accuracy degrades as particles leave their
+ * cells: rebuild when they have moved by a fair part of a leaf.
+ *   pos   [n][3] in the tree's dtype (as built), caller order
+ *   mass  [n] FP32
+ * Asynchronous on `stream` (no host wait, no allocation). */
+int g3_refit_tree(g3_ctx *ctx, g3_tree *tree, const void *pos, const float *mass,
+                  void *stream);
 /* Release a tree (also released by g3_ctx_destroy). NULL is ignored. */
 void g3_tree_destroy(g3_ctx *ctx, g3_tree *tree);
 /* Sizes of one of the tree's octrees: which = 0 all particles, 1 gas.
@@ -286,6 +301,15 @@ int g3_tuning_get(g3_ctx *ctx, int32_t kind, int64_t n_targets,
  * class of `kind` by this one choice. */
 int g3_tuning_set(g3_ctx *ctx, int32_t kind, int64_t n_targets,
                   int32_t walk_leaf, int32_t split, int32_t streams);
+/* Keep the tuned choices across processes: save writes every tuned class
+ * of the ctx to the text file `path` (host string; a header line
+ * "g3-tuning 1", then one line "kind class walk_leaf split streams" per
+ * class); load replaces the ctx's choices with a file's, after checking
+ * every line as g3_tuning_set would (G3_EINVAL, and the ctx unchanged, for
+ * an unreadable or malformed file). Choices never change results beyond
+ * rounding, so a file from another device is safe, only perhaps slower. */
+int g3_tuning_save(g3_ctx *ctx, const char *path);
+int g3_tuning_load(g3_ctx *ctx, const char *path);
 
 /*
  * Adjoints (the _backward twins). The paper stops at the forward modules;

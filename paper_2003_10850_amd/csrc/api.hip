@@ -2,6 +2,7 @@
 // selection, scratch management and the order of the launches of each call.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -523,6 +524,24 @@ int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const fl
   return g3_build_forest(c, 1, off, pos_t, pos, mass, type, box, p, tree, stream);
 }
 
+int g3_refit_tree(g3_ctx *c, g3_tree *t, const void *pos, const float *mass, void *stream) {
+  if (!c) return G3_EINVAL;
+  if (!t) return fail(c, G3_EINVAL, "g3_refit_tree: null tree");
+  if (t->owner != c) return fail(c, G3_ESTATE, "g3_refit_tree: tree of another ctx");
+  if (t->n > 0 && (!pos || !mass)) return fail(c, G3_EINVAL, "g3_refit_tree: null pos/mass");
+  DeviceGuard g(c->device);
+  int st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  st = refit_octree(c, t, t->all, pos, mass, s);
+  if (st) return st;
+  st = refit_octree(c, t, t->gas, pos, mass, s);
+  if (st) return st;
+  c->err.clear();
+  return G3_OK;
+}
+
 void g3_tree_destroy(g3_ctx *c, g3_tree *t) {
   if (!c || !t) return;
   DeviceGuard g(c->device);
@@ -778,6 +797,12 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   return G3_OK;
 }
 
+static bool tuning_ok(int kind, int walk_leaf, int split, int streams) {
+  return kind >= 0 && kind < kTuneKinds && walk_leaf >= 1 && walk_leaf <= 4096 &&
+         (split >= -1 || split == kSplitAuto) && split <= kMaxLevel &&
+         (streams == 1 || streams == 4);
+}
+
 int g3_tuning_get(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t *walk_leaf,
                   int32_t *split, int32_t *streams) {
   if (!c) return G3_EINVAL;
@@ -792,9 +817,7 @@ int g3_tuning_get(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t *walk_leaf
 int g3_tuning_set(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t walk_leaf,
                   int32_t split, int32_t streams) {
   if (!c) return G3_EINVAL;
-  if (kind < 0 || kind >= kTuneKinds || walk_leaf < 1 || walk_leaf > 4096 ||
-      (split < -1 && split != kSplitAuto) ||
-      split > kMaxLevel || (streams != 1 && streams != 4))
+  if (!tuning_ok(kind, walk_leaf, split, streams))
     return fail(c, G3_EINVAL, "g3_tuning_set: bad arguments");
   Tuning tu;
   tu.walk_leaf = walk_leaf;
@@ -807,6 +830,46 @@ int g3_tuning_set(g3_ctx *c, int32_t kind, int64_t n_targets, int32_t walk_leaf,
   } else {
     c->tuning[{kind, size_class(n_targets)}] = tu;
   }
+  return G3_OK;
+}
+
+int g3_tuning_save(g3_ctx *c, const char *path) {
+  if (!c || !path) return fail(c, G3_EINVAL, "g3_tuning_save: null argument");
+  FILE *f = std::fopen(path, "w");
+  if (!f) return fail(c, G3_EINVAL, std::string("g3_tuning_save: cannot write ") + path);
+  bool ok = std::fprintf(f, "g3-tuning 1\n") > 0;
+  for (const auto &kv : c->tuning)
+    ok = ok && std::fprintf(f, "%d %d %d %d %d\n", kv.first.first, kv.first.second,
+                            kv.second.walk_leaf, kv.second.split, kv.second.streams) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, G3_EINVAL, std::string("g3_tuning_save: write failed: ") + path);
+  return G3_OK;
+}
+
+int g3_tuning_load(g3_ctx *c, const char *path) {
+  if (!c || !path) return fail(c, G3_EINVAL, "g3_tuning_load: null argument");
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(c, G3_EINVAL, std::string("g3_tuning_load: cannot read ") + path);
+  std::map<std::pair<int, int>, Tuning> table;
+  int version = 0;
+  bool ok = std::fscanf(f, "g3-tuning %d", &version) == 1 && version == 1;
+  int kind, cls, leaf, split, streams;
+  while (ok) {
+    const int got = std::fscanf(f, "%d %d %d %d %d", &kind, &cls, &leaf, &split, &streams);
+    if (got == EOF) break;
+    if (got != 5 || cls < 0 || cls > 62 || !tuning_ok(kind, leaf, split, streams)) {
+      ok = false;
+      break;
+    }
+    Tuning tu;
+    tu.walk_leaf = leaf;
+    tu.split = split;
+    tu.streams = kind == kTuneDensity ? streams : 1;
+    table[{kind, cls}] = tu;
+  }
+  std::fclose(f);
+  if (!ok) return fail(c, G3_EINVAL, std::string("g3_tuning_load: malformed file ") + path);
+  c->tuning = table;
   return G3_OK;
 }
 

@@ -147,6 +147,10 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
 // octree built before it, filtered by `type` (nullptr: all gas).
 int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
                  const float *mass, int64_t m, hipStream_t s, const uint8_t *type = nullptr);
+// Keep the octree's order, topology, keys and cube sides; re-read the
+// members' positions and masses and recompute every node's moments and box.
+int refit_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, const float *mass,
+                 hipStream_t s);
 hipError_t refit_hmax(Octree &o, hipStream_t s);
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -492,6 +492,30 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   return G3_OK;
 }
 
+int refit_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, const float *mass,
+                 hipStream_t s) {
+  if (o.n == 0 || o.nnodes == 0) return G3_OK;
+  const bool gas = (&o == &t->gas);
+  int32_t *iperm = gas ? t->iperm_gas : t->iperm_all;
+  const uint32_t *order = (const uint32_t *)o.perm;
+  if (t->f64)
+    k_permute<double><<<nblk(o.n), kBlock, 0, s>>>(order, o.n, (const double *)pos, mass, o.xm,
+                                                   o.x64, iperm);
+  else
+    k_permute<float><<<nblk(o.n), kBlock, 0, s>>>(order, o.n, (const float *)pos, mass, o.xm,
+                                                  nullptr, iperm);
+  for (int l = o.max_level; l >= 0; --l)
+    k_moments_level<<<nblk(o.nnodes), kBlock, 0, s>>>(o.nodes, o.mom, t->f64 ? o.c64 : nullptr,
+                                                       o.nnodes, o.xm, t->f64 ? o.x64 : nullptr,
+                                                       l);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string("tree refit launch: ") + hipGetErrorString(e);
+    return G3_EHIP;
+  }
+  return G3_OK;
+}
+
 hipError_t refit_hmax(Octree &o, hipStream_t s) {
   for (int l = o.max_level; l >= 0 && o.nnodes > 0; --l)
     k_hmax_level<<<nblk(o.nnodes), kBlock, 0, s>>>(o.nodes, o.nnodes, o.vh, l);

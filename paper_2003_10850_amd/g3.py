@@ -23,10 +23,11 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
 
 # every symbol include/g3.h declares
 EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
-           "g3_build_tree", "g3_build_forest", "g3_tree_destroy", "g3_tree_info", "g3_tree_export",
+           "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
+           "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
            "g3_density_backward", "g3_hydro_force_backward", "g3_gravity_backward",
-           "g3_autotune", "g3_tuning_get", "g3_tuning_set")
+           "g3_autotune", "g3_tuning_get", "g3_tuning_set", "g3_tuning_save", "g3_tuning_load")
 
 
 class g3_params(ctypes.Structure):
@@ -68,6 +69,7 @@ def lib():
             "g3_ctx_stats": ([P, P, i32], ctypes.c_int),
             "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_build_forest": ([P, i32, P, i32, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_refit_tree": ([P, P, P, P, P], ctypes.c_int),
             "g3_tree_destroy": ([P, P], None),
             "g3_tree_info": ([P, i32, P, P], ctypes.c_int),
             "g3_tree_export": ([P, P, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -81,6 +83,8 @@ def lib():
             "g3_autotune": ([P, P, i64, P, P] + [P] * 6, ctypes.c_int),
             "g3_tuning_get": ([P, i32, i64, P, P, P], ctypes.c_int),
             "g3_tuning_set": ([P, i32, i64, i32, i32, i32], ctypes.c_int),
+            "g3_tuning_save": ([P, ctypes.c_char_p], ctypes.c_int),
+            "g3_tuning_load": ([P, ctypes.c_char_p], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -144,6 +148,10 @@ def g3_build_forest(ctx, snap_off, pos_t, pos, mass, type_, boxes, params, tree,
                                ctypes.byref(params), ctypes.byref(h), stream)
     _check(ctx, st, "g3_build_forest")
     return h.value
+
+
+def g3_refit_tree(ctx, tree, pos, mass, stream) -> None:
+    _check(ctx, lib().g3_refit_tree(ctx, tree, pos, mass, stream), "g3_refit_tree")
 
 
 def g3_tree_destroy(ctx, tree) -> None:
@@ -244,3 +252,11 @@ def g3_tuning_set(ctx, kind, n_targets, walk_leaf, split, streams=1):
     st = lib().g3_tuning_set(ctx, int(kind), int(n_targets), int(walk_leaf), int(split),
                              int(streams))
     _check(ctx, st, "g3_tuning_set")
+
+
+def g3_tuning_save(ctx, path: str) -> None:
+    _check(ctx, lib().g3_tuning_save(ctx, os.fsencode(path)), "g3_tuning_save")
+
+
+def g3_tuning_load(ctx, path: str) -> None:
+    _check(ctx, lib().g3_tuning_load(ctx, os.fsencode(path)), "g3_tuning_load")

@@ -53,6 +53,14 @@ class Context:
                    streams: int = 1):
         g3.g3_tuning_set(self.handle, kind, n_targets, walk_leaf, split, streams)
 
+    def save_tuning(self, path: str) -> None:
+        """Write the tuned launch choices to a text file (see g3_tuning_save)."""
+        g3.g3_tuning_save(self.handle, path)
+
+    def load_tuning(self, path: str) -> None:
+        """Replace the launch choices with a saved file's (see g3_tuning_load)."""
+        g3.g3_tuning_load(self.handle, path)
+
     def autotune(self, tree, h, vel=None, u=None, rho=None, omega=None, params=None,
                  active=None):
         """Time the launch choices on this tree and active set and keep the
@@ -108,6 +116,15 @@ class Tree:
         self.handle = g3.g3_build_forest(self.ctx.handle, self.snap_off, pt, _ptr(pos),
                                          _ptr(mass), _ptr(type), self.box,
                                          g3.g3_params.of(self.params), self.handle, _stream(dev))
+        return self
+
+    def refit(self, pos, mass):
+        """Move the built tree to new positions and masses (same dtype as
+        built) without rebuilding it: see g3_refit_tree."""
+        dev = self.ctx.device
+        _need(pos, self.hdtype, (self.n, 3), "pos", dev)
+        _need(mass, torch.float32, (self.n,), "mass", dev)
+        g3.g3_refit_tree(self.ctx.handle, self.handle, _ptr(pos), _ptr(mass), _stream(dev))
         return self
 
     def info(self, which: int):

@@ -139,3 +139,25 @@ def test_autotune_picks_candidates(setup):
     a = b.active
     np.testing.assert_array_equal(got["nterms"][a], ref["nterms"][a])
     set_all(ctx, 64, -1)
+
+
+def test_tuning_file_round_trip(setup, tmp_path):
+    from paper_2003_10850_amd import g3, ops
+    ctx, b, tree, h0 = setup
+    ctx.set_tuning(g3.G3_TUNE_DENSITY, 32, 3, n_targets=5000, streams=4)
+    ctx.set_tuning(g3.G3_TUNE_HYDRO, 16, -2, n_targets=70000)
+    ctx.set_tuning(g3.G3_TUNE_GRAVITY, 64, 5, n_targets=300)
+    path = str(tmp_path / "tuning.txt")
+    ctx.save_tuning(path)
+    fresh = ops.Context(torch.device("cuda", 0))
+    fresh.load_tuning(path)
+    for kind, n in ((g3.G3_TUNE_DENSITY, 5000), (g3.G3_TUNE_HYDRO, 70000),
+                    (g3.G3_TUNE_GRAVITY, 300), (g3.G3_TUNE_DENSITY, 70000)):
+        assert fresh.tuning(kind, n) == ctx.tuning(kind, n)
+    # a malformed file is refused and leaves the choices as they were
+    bad = tmp_path / "bad.txt"
+    bad.write_text("g3-tuning 1\n0 12 64 99 1\n")
+    with pytest.raises(g3.G3Error):
+        fresh.load_tuning(str(bad))
+    assert fresh.tuning(g3.G3_TUNE_DENSITY, 5000) == (32, 3, 4)
+    set_all(ctx, 64, -1)
