@@ -1,0 +1,116 @@
+"""The batching workload at full size, in the benchmark's launch
+configuration: a forest of 64 Plummer snapshots (sizes log-uniform in
+[1e3, 1e6], 8.0e6 particles) with time-bin active sets, autotuned, the step
+(h solve and density, hydro, gravity over every snapshot's active set)
+captured in a HIP graph and replayed. Checked per snapshot against the FP64
+oracle on up to 48 random active particles of each snapshot.
+
+Both sides read the same synthetic inputs: the generating model's h (the
+first guess of the solve, and the hydro h), gas density and Omega = 1 for
+the hydro force; the density is also checked at the GPU's solved h after
+that h is compared with the oracle's own solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_10850_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev_t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def test_batched_workload_full_size_samples():
+    from paper_2003_10850_amd import ops
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    b = inputs.batch(n_snap=64, seed=2)
+    print(f"C2 workload {b.name} n={b.n} active={b.active.size}", flush=True)
+    dev = torch.device("cuda", 0)
+    pos32, m32 = b.pos.astype(np.float32), b.mass.astype(np.float32)
+    vel32, u32 = b.vel.astype(np.float32), b.u.astype(np.float32)
+    hm = np.concatenate([inputs.model_smoothing(w) for w in b.snaps]).astype(np.float32)
+    rm = np.concatenate([inputs.model_gas_density(w) for w in b.snaps]).astype(np.float32)
+    om = np.ones(b.n, np.float32)
+    ctx = ops.Context(dev)
+    tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(b.type), [tuple(x) for x in b.boxes],
+                    b.params, snap_off=b.snap_off)
+    vel, u, act = dev_t(vel32), dev_t(u32), dev_t(b.active)
+    h0, rho_in, om_in = dev_t(hm), dev_t(rm), dev_t(om)
+    ctx.autotune(tree, h0, vel=vel, u=u, rho=rho_in, omega=om_in, active=act)
+    n = b.n
+    f32 = dict(dtype=torch.float32, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    B = dict(h=torch.zeros(n, **f32), rho=torch.zeros(n, **f32), drho_dh=torch.zeros(n, **f32),
+             omega=torch.zeros(n, **f32), nngb=torch.zeros(n, **i32),
+             acc=torch.zeros(n, 3, **f32), dudt=torch.zeros(n, **f32), vsig=torch.zeros(n, **f32),
+             npairs=torch.zeros(n, **i32), gacc=torch.zeros(n, 3, **f32),
+             pot=torch.zeros(n, **f32), nterms=torch.zeros(n, **i32))
+
+    def step():
+        B["h"].copy_(h0)
+        ops.density(tree, active=act, out={k: B[k] for k in
+                                           ("h", "rho", "drho_dh", "omega", "nngb")})
+        ops.hydro_force(tree, vel, u, h0, rho_in, om_in, active=act,
+                        out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
+        ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
+                                           "nterms": B["nterms"]})
+
+    step()  # eager: allocates the scratch the captured calls reuse
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    assert ctx.nonconverged(reset=True) == 0
+    R = {k: host(v) for k, v in B.items()}
+    print("C2 GPU step done; oracle per snapshot", flush=True)
+
+    rng = np.random.default_rng(13)
+    worst = dict(h=0.0, rho=0.0, hyd=0.0, grav=0.0, pot=0.0)
+    for k, w in enumerate(b.snaps):
+        r0, r1 = int(b.snap_off[k]), int(b.snap_off[k + 1])
+        a = b.active[(b.active >= r0) & (b.active < r1)] - r0
+        if a.size == 0:
+            continue
+        s = np.sort(rng.choice(a, min(48, a.size), replace=False))
+        sg = s[w.type[s] == 0]
+        P, M = pos32[r0:r1].astype(np.float64), m32[r0:r1].astype(np.float64)
+        at = oracle.Tree(P, M, b.boxes[k], type=w.type)
+        rg = oracle.gravity(at, b.params, active=s)
+        np.testing.assert_array_equal(R["nterms"][s + r0], rg["nterms"][s], err_msg=f"snap {k}")
+        ea = np.linalg.norm(R["gacc"][s + r0] - rg["acc"][s], axis=1) / rg["S"][s]
+        ep = np.abs(R["pot"][s + r0] - rg["pot"][s]) / np.abs(rg["pot"][s])
+        worst["grav"] = max(worst["grav"], ea.max())
+        worst["pot"] = max(worst["pot"], ep.max())
+        del at
+        if sg.size == 0:
+            continue
+        gt = oracle.Tree(P, M, b.boxes[k], type=w.type, gas_only=True)
+        ref = oracle.density(gt, b.params, active=sg, h=hm[r0:r1].astype(np.float64))
+        hk = R["h"][r0:r1].astype(np.float64)
+        eh = np.abs(hk[sg] - ref["h"][sg]) / ref["h"][sg]
+        worst["h"] = max(worst["h"], eh.max())
+        at_h = oracle.density(gt, b.params, active=sg, h=hk, solve_h=False)
+        np.testing.assert_array_equal(R["nngb"][sg + r0], at_h["nngb"][sg], err_msg=f"snap {k}")
+        er = np.abs(R["rho"][sg + r0] - at_h["rho"][sg]) / at_h["rho"][sg]
+        worst["rho"] = max(worst["rho"], er.max())
+        rh = oracle.hydro(gt, b.params, vel32[r0:r1], u32[r0:r1], hm[r0:r1], rm[r0:r1],
+                          om[r0:r1], active=sg)
+        np.testing.assert_array_equal(R["npairs"][sg + r0], rh["npairs"][sg],
+                                      err_msg=f"snap {k}")
+        eh2 = np.linalg.norm(R["acc"][sg + r0] - rh["acc"][sg], axis=1) / rh["S"][sg]
+        worst["hyd"] = max(worst["hyd"], eh2.max())
+    print("C2 worst: " + ", ".join(f"{k} {v:.3e}" for k, v in worst.items()), flush=True)
+    assert worst["h"] < 2e-6
+    assert worst["rho"] < 1e-5 and worst["hyd"] < 1e-5
+    assert worst["grav"] < 1e-5 and worst["pot"] < 1e-5

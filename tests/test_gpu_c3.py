@@ -6,7 +6,10 @@ oracle (FP64 decisions) on a random subsample of 1e4 particles.
 
 Reported: h, rho, hydro and gravity accelerations and potential errors
 (max and median, relative to the value or to the L1 sum S of the terms);
-counts must be exact.
+counts must be exact. The hydro force is checked at synthetic inputs both
+sides read (h and gas density from a gas mass histogram, Omega = 1), so that
+no oracle input comes from the GPU; the density at the GPU's solved h, after
+that h is compared with the oracle's own solve.
 """
 import dataclasses
 
@@ -43,10 +46,17 @@ def test_precision_workload_full_size_subsample():
     d = ops.density(tree)
     assert ctx.nonconverged(reset=True) == 0
     v32, u32 = w.vel.astype(np.float32), w.u.astype(np.float32)
-    hy = ops.hydro_force(tree, dev_t(v32), dev_t(u32), d["h"], d["rho"], d["omega"])
+    # the hydro force at synthetic inputs both sides read: h (FP64, the
+    # tree's dtype) and gas density from a 128^3 gas mass histogram, Omega = 1
+    rm64 = inputs.grid_gas_density(w, cells=128)
+    hm = (3.0 * w.params.n_ngb * w.mass / (4.0 * np.pi * rm64)) ** (1.0 / 3.0)
+    rm = rm64.astype(np.float32)
+    del rm64
+    om1 = np.ones(w.n, np.float32)
+    hy = ops.hydro_force(tree, dev_t(v32), dev_t(u32), dev_t(hm), dev_t(rm), dev_t(om1))
     g = ops.gravity(tree)
     torch.cuda.synchronize()
-    h, rho, om = host(d["h"]), host(d["rho"]), host(d["omega"])
+    h, rho = host(d["h"]), host(d["rho"])
     nngb, acc, npairs = host(d["nngb"]), host(hy["acc"]), host(hy["npairs"])
     gacc, pot, nterms = host(g["acc"]), host(g["pot"]), host(g["nterms"])
     del d, hy, g, tree
@@ -69,8 +79,7 @@ def test_precision_workload_full_size_subsample():
     e = np.abs(rho[sg] - at_h["rho"][sg]) / at_h["rho"][sg]
     report("rho rel", e)
     assert e.max() < 1e-5
-    r = oracle.hydro(gt, p, v32, u32, h, rho.astype(np.float64), om.astype(np.float64),
-                     active=sg)
+    r = oracle.hydro(gt, p, v32, u32, hm, rm, om1, active=sg)
     np.testing.assert_array_equal(npairs[sg], r["npairs"][sg])
     e = np.linalg.norm(acc[sg] - r["acc"][sg], axis=1) / r["S"][sg]
     report("hydro acc |da|/S", e)
