@@ -3,9 +3,9 @@
  * Gadget3 method (Ragagnin et al., "Gadget3 on GPUs with OpenACC",
  * arXiv 2003.10850).
  *
- * The paper's modules all compute, for a list of active particles, a sum over
- * particles found by a tree walk over groups of active particles
- * (section 1, fifth paragraph): the SPH density found by iterating the
+ * Each of the paper's modules evaluates, for the particles active at a step,
+ * a sum over the particles that a tree walk, made once per group of active
+ * particles, finds (section 1, fifth paragraph): the SPH density found by iterating the
  * smoothing length, the SPH hydrodynamic force, and Barnes-Hut gravity whose
  * node and particle interactions are evaluated inside the walk
  * (section 2.4). Each module receives only the properties it needs, with
@@ -202,8 +202,8 @@ int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
             void *stream);
 
 /*
- * SPH density of the active gas particles (section 1: "computes particle
- * densities by multiple iterations"):
+ * SPH density of the active gas particles (section 1: the density is
+ * evaluated repeatedly while each smoothing length is adjusted):
  *   rho_i   = sum_j m_j W(|x_ij|, h_i)     (gas j, self included)
  *   drho_dh = sum_j m_j dW/dh(|x_ij|, h_i)
  *   omega_i = 1 + h_i / (3 rho_i) drho_dh  (grad-h correction)

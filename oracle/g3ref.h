@@ -7,9 +7,10 @@
  *
  * Method: the paper (Ragagnin et al., "Gadget3 on GPUs with OpenACC",
  * arXiv 2003.10850) names the physics but prints no formula: Barnes-Hut
- * gravity, SPH density found "by multiple iterations" and the SPH
- * hydrodynamic force, all computed for a list of active particles by a tree
- * walk over groups that finds neighbours within a distance (section 1,
+ * gravity, the SPH density (evaluated repeatedly while the smoothing length
+ * is adjusted) and the SPH hydrodynamic force, each evaluated for the
+ * particles active at a step through tree walks made per group of active
+ * particles, which collect the neighbours inside a search radius (section 1,
  * fifth paragraph). The formulas below are the published methods Gadget
  * builds on, each cited where it is implemented in g3ref.cpp:
  *   - Wendland C6 kernel, support radius h (Dehnen & Aly 2012, table 1);
