@@ -252,6 +252,43 @@ def density_backward(tree: Tree, params, h, g_rho=None, g_drho_dh=None, g_omega=
     return out
 
 
+def density_solve_backward(tree: Tree, params, h, rho, drho_dh, g_h, active=None,
+                           gate: float = 1e-3) -> dict:
+    """Gradients (pos [n,3], mass [n]) of sum_i g_h_i h_i, where each active gas
+    h_i is the root of the density iteration's constraint
+    F_i = N_eff(h_i) - N_ngb = 0 with N_eff = (4 pi/3) h^3 rho / m_i (the
+    mass-weighted neighbour number, Springel & Hernquist 2002, eq. 6).
+
+    The paper does not differentiate the iteration; this is the implicit
+    function theorem on F_i, with rho, drho/dh the module's outputs at the
+    root:
+        dh_i/dtheta = -(dF_i/dtheta) / (dF_i/dh_i)
+        dF_i/dh_i   = (4 pi/3) (3 h_i^2 rho_i + h_i^3 drho_i/dh) / m_i
+        dF_i/dtheta = (4 pi/3) h_i^3 / m_i  drho_i/dtheta
+                      - [theta = m_i] N_eff_i / m_i
+    The drho/dtheta terms are the oracle's density adjoint seeded with
+    g_rho_i = -lambda_i (4 pi/3) h_i^3 / m_i, lambda_i = g_h_i / (dF_i/dh_i).
+    A row whose N_eff misses N_ngb by more than `gate` (relative: an h that
+    did not converge) has no constraint and passes nothing."""
+    act = _active(tree.n, active)
+    n = tree.n
+    h, rho, drho_dh, g_h = _f64(h), _f64(rho), _f64(drho_dh), _f64(g_h)
+    m = tree.mass
+    sel = np.zeros(n, bool)
+    sel[act] = True
+    if tree.type is not None:
+        sel &= tree.type == 0
+    c = 4.0 * np.pi / 3.0 * h ** 3 / m
+    N = c * rho
+    sel &= np.abs(N / params.n_ngb - 1.0) <= gate
+    dFdh = 4.0 * np.pi / 3.0 * (3.0 * h ** 2 * rho + h ** 3 * drho_dh) / m
+    lam = np.where(sel, g_h / np.where(sel, dFdh, 1.0), 0.0)
+    seed = -lam * c
+    g = density_backward(tree, params, h, g_rho=seed, active=np.nonzero(sel)[0])
+    mass = g["mass"] + lam * N / m
+    return dict(pos=g["pos"], mass=mass)
+
+
 def hydro_backward(tree: Tree, params, vel, u, h, rho, omega, g_acc=None, g_dudt=None,
                    active=None) -> dict:
     """Gradients (pos, vel, mass, h, u, rho, omega) of

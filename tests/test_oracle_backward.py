@@ -94,6 +94,79 @@ def test_density_backward_identities():
     assert abs(euler + 3 * L) < 1e-9 * abs(L)
 
 
+# ------------------------------------------- through the smoothing-length solve
+
+def tight(p):
+    """FP64 decisions and a bisection closed to 1e-13 of h, so that finite
+    differences of the solved h resolve its derivative."""
+    return dataclasses.replace(p, flags=oracle.FLAG_FP64_DECISIONS, h_tol=1e-13)
+
+
+def solved_h(w, pos, mass, act):
+    t = oracle.Tree(pos, mass, w.box, type=w.type, gas_only=True)
+    d = oracle.density(t, tight(w.params), active=act, solve_h=True)
+    assert d["nonconv"] == 0
+    return t, d
+
+
+def solve_setup(seed):
+    w = clustered(400, seed)
+    rng = np.random.default_rng(seed)
+    coef = rng.normal(size=w.n)
+    act = np.sort(rng.choice(w.n, size=w.n // 2, replace=False))
+    return w, coef, act
+
+
+def test_solve_backward_matches_finite_differences():
+    w, coef, act = solve_setup(3)
+    t, d = solved_h(w, w.pos, w.mass, act)
+    g = oracle.density_solve_backward(t, w.params, d["h"], d["rho"], d["drho_dh"], coef,
+                                      active=act)
+    L = lambda P, M: float((coef * solved_h(w, P, M, act)[1]["h"])[act].sum())
+    rng = np.random.default_rng(6)
+    # moved particles both inside and outside the active set
+    for k in list(rng.choice(act, 3, replace=False)) + list(
+            rng.choice(np.setdiff1d(np.arange(w.n), act), 3, replace=False)):
+        for c in range(3):
+            dx = 1e-6
+            P1, P2 = w.pos.copy(), w.pos.copy()
+            P1[k, c] += dx
+            P2[k, c] -= dx
+            fd = (L(P1, w.mass) - L(P2, w.mass)) / (2 * dx)
+            assert abs(fd - g["pos"][k, c]) <= 1e-6 * np.abs(g["pos"]).max(), (k, c, fd)
+        dm = 1e-6 * w.mass[k]
+        M1, M2 = w.mass.copy(), w.mass.copy()
+        M1[k] += dm
+        M2[k] -= dm
+        fd = (L(w.pos, M1) - L(w.pos, M2)) / (2 * dm)
+        assert abs(fd - g["mass"][k]) <= 1e-6 * np.abs(g["mass"]).max(), (k, fd)
+
+
+def test_solve_backward_identities():
+    w, coef, act = solve_setup(4)
+    t, d = solved_h(w, w.pos, w.mass, act)
+    g = oracle.density_solve_backward(t, w.params, d["h"], d["rho"], d["drho_dh"], coef,
+                                      active=act)
+    L = float((coef * d["h"])[act].sum())
+    # h depends on position differences only
+    assert np.abs(g["pos"].sum(0)).max() < 1e-10 * np.abs(g["pos"]).sum()
+    # and on the masses only through ratios m_j / m_i: scaling every mass
+    # leaves h unchanged (this needs the explicit 1/m_i of N_eff)
+    mg = w.mass * g["mass"]
+    assert abs(mg.sum()) < 1e-9 * np.abs(mg).sum()
+    # h(lambda x) = lambda h(x)
+    assert abs((w.pos * g["pos"]).sum() - L) < 1e-9 * abs(L)
+    # an h that did not converge has no constraint and passes nothing
+    bad = d["rho"].copy()
+    bad[act[0]] *= 0.5
+    g2 = oracle.density_solve_backward(t, w.params, d["h"], bad, d["drho_dh"], coef, active=act)
+    only = np.zeros(w.n)
+    only[act[0]] = coef[act[0]]
+    g1 = oracle.density_solve_backward(t, w.params, d["h"], d["rho"], d["drho_dh"], only,
+                                       active=act)
+    assert np.allclose(g2["pos"], g["pos"] - g1["pos"], rtol=0, atol=1e-12 * np.abs(g["pos"]).max())
+
+
 # ------------------------------------------------------------------- hydro
 
 def hydro_fields(w, seed):
