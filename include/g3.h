@@ -317,8 +317,9 @@ int g3_tuning_load(g3_ctx *ctx, const char *path);
  * inputs, from the gradients of L with respect to their outputs at the
  * active rows (upstream gradients; NULL means zero). Neighbour sets and
  * Barnes-Hut decisions are those the forward call takes at the same inputs
- * (the forward maps are piecewise smooth in them), and h is an input: there
- * is no derivative through the h solve. Gradients are ADDED (+=) to the
+ * (the forward maps are piecewise smooth in them), and h is an input of
+ * each; g3_density_solve_backward adds the derivative through the h solve
+ * where h came from it. Gradients are ADDED (+=) to the
  * caller's [n] / [n][3] arrays in caller order, each nullable; inactive
  * particles receive what the active particles' sums owe them. FP32 trees
  * only (G3_EINVAL otherwise). Density and hydro adjoints are gathered per
@@ -335,6 +336,26 @@ int g3_density_backward(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
                         const float *g_rho, const float *g_drho_dh,
                         const float *g_omega, float *g_pos, float *g_mass,
                         float *g_h, void *stream);
+/* Through the smoothing-length solve (the iterations of the paper's SPH
+ * density module, section 1): g_h [n] is the upstream gradient of the
+ * SOLVED h at the active rows, and h, rho, drho_dh are g3_density's outputs
+ * there (solve_h = 1). Each such h_i is the root of
+ * N_eff(h_i) = (4 pi/3) h_i^3 rho_i / m_i = N_ngb, so by the implicit
+ * function theorem
+ *   dL/dtheta = -sum_i lambda_i dN_eff_i/dtheta,
+ *   lambda_i  = g_h_i / (dN_eff_i/dh_i) at fixed positions and masses,
+ * which is the density adjoint seeded with
+ * g_rho_i = -g_h_i h_i / (3 rho_i + h_i drho_i/dh), plus the explicit 1/m_i
+ * of N_eff: dL/dm_i += g_h_i h_i rho_i / (m_i (3 rho_i + h_i drho_i/dh)).
+ * A row whose N_eff misses p->n_ngb by more than 1e-3 (relative: a solve
+ * that did not converge, or an h held at the cap) passes nothing. Outputs
+ * dL/dpos [n][3] and dL/dmass [n], added; the gradients of rho, drho_dh and
+ * Omega at fixed h are g3_density_backward's (its dL/dh is part of g_h). */
+int g3_density_solve_backward(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                              const int32_t *active, const g3_params *p,
+                              const float *h, const float *rho,
+                              const float *drho_dh, const float *g_h,
+                              float *g_pos, float *g_mass, void *stream);
 /* Hydro force: upstream g_acc [n][3], g_dudt [n] (the signal velocity is
  * not differentiated); inputs as g3_hydro_force. Outputs dL/dpos, dL/dvel,
  * dL/dmass, dL/dh, dL/du, dL/drho, dL/domega. */

@@ -286,7 +286,9 @@ def density_solve_backward(tree: Tree, params, h, rho, drho_dh, g_h, active=None
     seed = -lam * c
     g = density_backward(tree, params, h, g_rho=seed, active=np.nonzero(sel)[0])
     mass = g["mass"] + lam * N / m
-    return dict(pos=g["pos"], mass=mass)
+    # S: the L1 sums of the contributions to each entry
+    S = dict(pos=g["S"]["pos"], mass=g["S"]["mass"] + np.abs(lam * N / m))
+    return dict(pos=g["pos"], mass=mass, S=S)
 
 
 def hydro_backward(tree: Tree, params, vel, u, h, rho, omega, g_acc=None, g_dudt=None,

@@ -3,7 +3,8 @@
 // lengths (and the hydro inputs), given its gradients with respect to the
 // module outputs at the active particles. Neighbour sets and Barnes-Hut
 // decisions are those of the forward call (the forward map is piecewise
-// smooth in them) and h is an input.
+// smooth in them) and h is an input; the derivative through the h solve is
+// the density adjoint with a seed derived from the solve's constraint.
 //
 // SPH adjoints are gathered: every gas particle walks its symmetric
 // neighbourhood r < max(h_p, h_q) once and adds both what its own sums owe
@@ -85,6 +86,35 @@ __global__ void k_density_bwd_init(const int32_t *__restrict__ perm, int64_t m,
                                    const float *__restrict__ h, float4 *__restrict__ bw) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s < m) bw[s] = make_float4(h[perm[s]], 0.0f, 0.0f, 0.0f);
+}
+
+// Adjoint of the smoothing-length solve. Each active gas h_i is the root of
+// F_i = N_eff(h_i) - N_ngb with N_eff = (4 pi/3) h^3 rho / m_i. By the
+// implicit function theorem an upstream g_h_i reaches the positions and
+// masses as the density adjoint seeded with
+//   gbar_rho_i = -g_h_i h_i / (3 rho_i + h_i drho_i/dh)
+// plus the explicit 1/m_i of N_eff:
+//   dL/dm_i += g_h_i h_i rho_i / (m_i (3 rho_i + h_i drho_i/dh)).
+// A row whose N_eff misses N_ngb by more than 1e-3 (relative: an h that did
+// not converge, or one held at the cap) has no constraint and passes nothing.
+__global__ void k_hsolve_bwd_prep(const int32_t *__restrict__ active, int64_t n_act,
+                                  const int32_t *__restrict__ iperm, int64_t n_caller,
+                                  const float *__restrict__ h, const float *__restrict__ rho,
+                                  const float *__restrict__ drho, const float *__restrict__ g_h,
+                                  const float4 *__restrict__ xm, float n_ngb,
+                                  float4 *__restrict__ bw, float *__restrict__ g_mass) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_act) return;
+  const int32_t id = active ? active[a] : (int32_t)a;
+  if (id < 0 || (int64_t)id >= n_caller) return;
+  const int32_t s = iperm[id];
+  if (s < 0) return;
+  const float hi = h[id], r = rho[id], rp = drho[id], mi = xm[s].w, gh = g_h[id];
+  const float N = 4.18879020f * hi * hi * hi * r / mi;  // (4 pi/3) h^3 rho / m
+  const float den = 3.0f * r + hi * rp;                 // 3 rho Omega
+  if (!(fabsf(N / n_ngb - 1.0f) <= 1e-3f) || !(den > 0.0f) || gh == 0.0f) return;
+  bw[s] = make_float4(hi, -gh * hi / den, 0.0f, 0.0f);
+  if (g_mass) g_mass[id] += gh * hi * r / (mi * den);
 }
 
 // One lane per gas particle p, over every q with r < max(h_p, h_q):
@@ -810,6 +840,26 @@ hipError_t launch_density_bwd(Octree &gas, const int32_t *iperm, int64_t n_calle
   if (e != hipSuccess) return e;
   k_density_bwd<<<persistent_grid((const void *)k_density_bwd, kBlock, max_groups), kBlock, 0,
                   s>>>(gas.nodes, gas.xm, bw, gas.perm, all_gas, g_pos, g_mass, g_h);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_solve_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                                    const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                                    const int32_t *active, float n_ngb, const float *h,
+                                    const float *rho, const float *drho, const float *g_h,
+                                    float *g_pos, float *g_mass, hipStream_t s) {
+  const int64_t m = gas.n;
+  if (m == 0) return hipSuccess;
+  float4 *bw = gas.aux;  // (h, gbar_rho, 0, 0) per sorted gas member
+  k_density_bwd_init<<<nblk(m), kBlock, 0, s>>>(gas.perm, m, h, bw);
+  const int64_t na = active ? n_act : n_caller;
+  if (na > 0)
+    k_hsolve_bwd_prep<<<nblk(na), kBlock, 0, s>>>(active, na, iperm, n_caller, h, rho, drho, g_h,
+                                                   gas.xm, n_ngb, bw, g_mass);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_density_bwd<<<persistent_grid((const void *)k_density_bwd, kBlock, max_groups), kBlock, 0,
+                  s>>>(gas.nodes, gas.xm, bw, gas.perm, all_gas, g_pos, g_mass, nullptr);
   return hipGetLastError();
 }
 

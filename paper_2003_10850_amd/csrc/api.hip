@@ -1048,6 +1048,37 @@ int g3_density_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *act
   return G3_OK;
 }
 
+int g3_density_solve_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                              const g3_params *p, const float *h, const float *rho,
+                              const float *drho_dh, const float *g_h, float *g_pos,
+                              float *g_mass, void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_density_solve_backward");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_density_solve_backward: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_density_solve_backward: FP32 trees only");
+  if (t->gas.n > 0 && (!h || !rho || !drho_dh || !g_h))
+    return fail(c, G3_EINVAL, "g3_density_solve_backward: h, rho, drho_dh and g_h are required");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  if (o.n == 0) return G3_OK;
+  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_solve_backward prep");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
+  if (st) return st;
+  e = launch_density_solve_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active,
+                               (float)p->n_ngb, h, rho, drho_dh, g_h, g_pos, g_mass, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_solve_backward");
+  c->err.clear();
+  return G3_OK;
+}
+
 int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
                             const g3_params *p, const float *vel, const float *u,
                             const float *h, const float *rho, const float *omega,

@@ -237,6 +237,14 @@ hipError_t launch_density_bwd(Octree &gas, const int32_t *iperm, int64_t n_calle
                               const float *drho, const float *g_rho, const float *g_drho,
                               const float *g_omega, float *g_pos, float *g_mass, float *g_h,
                               hipStream_t s);
+// Through the smoothing-length solve: the density adjoint seeded from g_h
+// by the implicit function theorem on N_eff(h) = N_ngb (rows that did not
+// converge pass nothing); hmax refit from h as above.
+hipError_t launch_density_solve_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
+                                    const Groups &all_gas, int64_t max_groups, int64_t n_act,
+                                    const int32_t *active, float n_ngb, const float *h,
+                                    const float *rho, const float *drho, const float *g_h,
+                                    float *g_pos, float *g_mass, hipStream_t s);
 // Hydro: like the density (every gas member, symmetric walk) after the
 // hydro prep of vh and aux; scratch up [n_gas].
 hipError_t launch_hydro_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,

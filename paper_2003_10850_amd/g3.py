@@ -26,7 +26,8 @@ EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
            "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
            "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
-           "g3_density_backward", "g3_hydro_force_backward", "g3_gravity_backward",
+           "g3_density_backward", "g3_density_solve_backward", "g3_hydro_force_backward",
+           "g3_gravity_backward",
            "g3_autotune", "g3_tuning_get", "g3_tuning_set", "g3_tuning_save", "g3_tuning_load")
 
 
@@ -78,6 +79,7 @@ def lib():
             "g3_hydro_force": ([P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_gravity": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
             "g3_density_backward": ([P, P, i64, P, P] + [P] * 10, ctypes.c_int),
+            "g3_density_solve_backward": ([P, P, i64, P, P] + [P] * 7, ctypes.c_int),
             "g3_hydro_force_backward": ([P, P, i64, P, P] + [P] * 15, ctypes.c_int),
             "g3_gravity_backward": ([P, P, i64, P, P] + [P] * 5, ctypes.c_int),
             "g3_autotune": ([P, P, i64, P, P] + [P] * 6, ctypes.c_int),
@@ -210,6 +212,15 @@ def g3_density_backward(ctx, tree, n_act, active, params, h, rho, drho_dh, g_rho
                                    g_drho_dh or None, g_omega or None, g_pos or None,
                                    g_mass or None, g_h or None, stream)
     _check(ctx, st, "g3_density_backward")
+
+
+def g3_density_solve_backward(ctx, tree, n_act, active, params, h, rho, drho_dh, g_h, g_pos,
+                              g_mass, stream):
+    st = lib().g3_density_solve_backward(ctx, tree, int(n_act), active or None,
+                                         ctypes.byref(params), h or None, rho or None,
+                                         drho_dh or None, g_h or None, g_pos or None,
+                                         g_mass or None, stream)
+    _check(ctx, st, "g3_density_solve_backward")
 
 
 def g3_hydro_force_backward(ctx, tree, n_act, active, params, vel, u, h, rho, omega, g_acc,

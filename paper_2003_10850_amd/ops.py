@@ -267,6 +267,43 @@ class _DensityFn(torch.autograd.Function):
         return None, None, None, gp, gm, gh
 
 
+class _DensitySolveFn(torch.autograd.Function):
+    """h solved from N_eff(h) = N_ngb, and rho, drho/dh, Omega at that h, as
+    differentiable functions of (pos, mass): the fixed-h part of the backward
+    is g3_density_backward, and its dL/dh joins the upstream gradient of h in
+    g3_density_solve_backward (the implicit derivative of the solve)."""
+
+    @staticmethod
+    def forward(fctx, tree, params, active, h0, pos, mass):
+        d = density(tree, params, h=h0, active=active, solve_h=True)
+        fctx.tree, fctx.params, fctx.active = tree, params, active
+        fctx.set_materialize_grads(False)
+        fctx.save_for_backward(d["h"], d["rho"], d["drho_dh"])
+        return d["h"], d["rho"], d["drho_dh"], d["omega"]
+
+    @staticmethod
+    def backward(fctx, g_h, g_rho, g_drho, g_omega):
+        tree = fctx.tree
+        h, rho, drho = fctx.saved_tensors
+        n = tree.n
+        gp, gm = _grad_buf(tree, n, 3), _grad_buf(tree, n)
+        # the total gradient of h: its upstream one plus what rho, drho/dh
+        # and Omega owe it at fixed h (the fixed-h adjoint adds into it)
+        gh = _grad_buf(tree, n) if g_h is None else g_h.contiguous().clone()
+        na, ap = _active(tree, fctx.active)
+        p = g3.g3_params.of(fctx.params or tree.params)
+        st = _stream(tree.ctx.device)
+        if g_rho is not None or g_drho is not None or g_omega is not None:
+            c = lambda t: None if t is None else t.contiguous()
+            g_rho, g_drho, g_omega = c(g_rho), c(g_drho), c(g_omega)
+            g3.g3_density_backward(tree.ctx.handle, tree.handle, na, ap, p, _ptr(h), _ptr(rho),
+                                   _ptr(drho), _ptr(g_rho), _ptr(g_drho), _ptr(g_omega),
+                                   _ptr(gp), _ptr(gm), _ptr(gh), st)
+        g3.g3_density_solve_backward(tree.ctx.handle, tree.handle, na, ap, p, _ptr(h), _ptr(rho),
+                                     _ptr(drho), _ptr(gh), _ptr(gp), _ptr(gm), st)
+        return None, None, None, None, gp, gm
+
+
 class _HydroFn(torch.autograd.Function):
     """acc, du/dt as a differentiable function of (pos, vel, mass, u, h, rho,
     omega); the backward is g3_hydro_force_backward."""
@@ -326,6 +363,17 @@ def density_ad(tree: Tree, pos, mass, h, params=None, active=None):
     copies); gradients flow to pos, mass and h."""
     _need(h, torch.float32, (tree.n,), "h", tree.ctx.device)
     return _DensityFn.apply(tree, params, active, pos, mass, h)
+
+
+def density_solve_ad(tree: Tree, pos, mass, h0=None, params=None, active=None):
+    """Differentiable (h, rho, drho_dh, omega) with h solved at the active gas
+    rows (h0: optional first guess, not differentiated). pos and mass must be
+    the tensors `tree` was built from; gradients flow to pos and mass, also
+    through the solved h. Rows whose solve did not converge hold their h
+    fixed (no gradient through it)."""
+    if h0 is not None:
+        _need(h0, torch.float32, (tree.n,), "h0", tree.ctx.device)
+    return _DensitySolveFn.apply(tree, params, active, h0, pos, mass)
 
 
 def hydro_force_ad(tree: Tree, pos, vel, mass, u, h, rho, omega, params=None, active=None):
