@@ -139,9 +139,12 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().g3ref_tree_free(h)
-            self._h = None
+        self._h = None
+        # at interpreter exit the module's globals may already be cleared;
+        # the process then releases the tree itself
+        L = _lib
+        if h and L is not None:
+            L.g3ref_tree_free(h)
 
     @property
     def nnodes(self) -> int:
