@@ -9,7 +9,7 @@
 // The wave descends while any lane opens. Accepted monopoles and the members
 // of opened leaves become entries of a 64-entry interaction tile in LDS,
 // each with the 64-bit mask of lanes that use it; the tile is then
-// evaluated by all lanes with the mask folded into the source mass. This
+// evaluated by all lanes with the mask applied to the inverse distance. This
 // keeps the interaction step out of the walk's branches (the limitation the
 // paper names for gravity, section 2.4) and reproduces the per-particle
 // interaction list exactly.
@@ -62,6 +62,11 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     float *__restrict__ acc, float *__restrict__ pot, int32_t *__restrict__ nterms) {
   __shared__ Entry tiles[kWpb][kTile];
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];  // FP64 source positions
+  // running totals (acc, pot) and their Neumaier compensations, and the term
+  // count, one slot per lane: touched only at a flush, so the walk loop
+  // carries no per-lane sums from one node to the next
+  __shared__ float4 tot[kWpb][kTile], comp[kWpb][kTile];
+  __shared__ int32_t nts[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   int range = 0;
   for (int g; (g = next_group(gs, range)) >= 0;) {
@@ -79,10 +84,9 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   Entry *tile = tiles[w];
   double4 *tile64 = tiles64[w];
 
-  // totals with Neumaier compensation terms; per-tile partials are plain
-  float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-  float cax = 0.f, cay = 0.f, caz = 0.f, cph = 0.f;
-  int nt = 0;
+  tot[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  comp[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  nts[w][lane] = 0;
   int tc = 0;
 
   // this lane's bit in an entry's mask: word (low or high half) and offset
@@ -93,6 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   auto flush = [&](int nc) {
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pp = 0.f;
+    int pn = 0;  // terms: entries whose mask holds this lane's bit
     for (int k = 0; k < nc; ++k) {
       const float4 ep = tile[k].p;
       // branch-free use: the signed extract of the lane's bit is 0 or all
@@ -120,11 +125,16 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       py += mr3 * dy;
       pz += mr3 * dz;
       pp -= mr;
+      pn -= use;
     }
-    neumaier_add(ax, cax, px);
-    neumaier_add(ay, cay, py);
-    neumaier_add(az, caz, pz);
-    neumaier_add(ph, cph, pp);
+    float4 t = tot[w][lane], c = comp[w][lane];
+    neumaier_add(t.x, c.x, px);
+    neumaier_add(t.y, c.y, py);
+    neumaier_add(t.z, c.z, pz);
+    neumaier_add(t.w, c.w, pp);
+    tot[w][lane] = t;
+    comp[w][lane] = c;
+    nts[w][lane] += pn;
     wave_sync();
   };
 
@@ -158,10 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     }
     const uint64_t amask = __ballot(accept);
     const uint64_t omask = __ballot(act && !accept);
-    if (accept) {
-      resume = nd.meta.x;
-      ++nt;  // terms are counted here, not in the tile loop
-    }
+    if (accept) resume = nd.meta.x;
     if (amask) {
       if (tc == kTile) {
         flush(kTile);
@@ -185,8 +192,6 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       continue;
     }
     int st = nd.meta.y, c = nd.meta.z;
-    // an opening lane interacts with every member but itself
-    if (act && !accept) nt += c - ((s >= st && s < st + c) ? 1 : 0);
     while (c > 0) {
       if (tc == kTile) {
         flush(kTile);
@@ -215,10 +220,9 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     cur = nd.meta.x;
   }
   if (tc > 0) flush(tc);
-  ax += cax;
-  ay += cay;
-  az += caz;
-  ph += cph;
+  const float4 tt = tot[w][lane], tc4 = comp[w][lane];
+  const float ax = tt.x + tc4.x, ay = tt.y + tc4.y, az = tt.z + tc4.z, ph = tt.w + tc4.w;
+  const int nt = nts[w][lane];
 
   if (valid) {
     const int cid = perm[s];
