@@ -293,10 +293,9 @@ def test_loss_gradient_vs_oracle_and_finite_differences(ctx):
     assert checked >= 18
 
 
-def test_adjoints_on_a_forest(ctx):
-    """Every snapshot of a forest gets the gradients its own tree gives:
-    density and gravity adjoints over a three-snapshot forest with boxes
-    at different places, against the oracle per snapshot."""
+def forest_case(ctx):
+    """A three-snapshot forest with boxes of different sizes at different
+    places, and a model h per snapshot."""
     from paper_2003_10850_amd import ops
     snaps, boxes = [], []
     for k, n in enumerate((3000, 700, 5000)):
@@ -319,6 +318,15 @@ def test_adjoints_on_a_forest(ctx):
                              np.array([0, 0, 0, 1.0]), w.params)
         w2.model = w.model
         h[off[k]:off[k + 1]] = inputs.model_smoothing(w2, 40.0) * side
+    return snaps, off, pos32, m32, p, tree, h
+
+
+def test_adjoints_on_a_forest(ctx):
+    """Every snapshot of a forest gets the gradients its own tree gives:
+    density and gravity adjoints over a three-snapshot forest with boxes
+    at different places, against the oracle per snapshot."""
+    from paper_2003_10850_amd import ops
+    snaps, off, pos32, m32, p, tree, h = forest_case(ctx)
     pos = dev_t(pos32).requires_grad_(True)
     mass = dev_t(m32).requires_grad_(True)
     hh = dev_t(h).requires_grad_(True)
@@ -344,3 +352,37 @@ def test_adjoints_on_a_forest(ctx):
         check(f"forest {k} g_mass", gm[r], rd["mass"] + rg["mass"],
               rd["S"]["mass"] + rg["S"]["mass"])
         check(f"forest {k} g_h", gh[r], rd["h"], rd["S"]["h"])
+
+
+def test_solve_adjoint_on_a_forest(ctx):
+    """The gradient through the h solve on a forest: L = sum a h + b rho at
+    the solved h of every gas particle, against the oracle per snapshot
+    (its own solve, closed to 1e-10)."""
+    import dataclasses
+    from paper_2003_10850_amd import ops
+    snaps, off, pos32, m32, p, tree, _ = forest_case(ctx)
+    pos = dev_t(pos32).requires_grad_(True)
+    mass = dev_t(m32).requires_grad_(True)
+    hs, rho, _, _ = ops.density_solve_ad(tree, pos, mass)
+    rng = np.random.default_rng(13)
+    typ = np.concatenate([w.type for w in snaps])
+    a, b = (np.where(typ == 0, rng.normal(size=len(m32)), 0).astype(np.float32) for _ in range(2))
+    L = (hs * dev_t(a)).sum() + (rho * dev_t(b)).sum()
+    L.backward()
+    gp, gm, hg = host(pos.grad), host(mass.grad), host(hs).astype(np.float64)
+    for k, w in enumerate(snaps):
+        r = slice(off[k], off[k + 1])
+        P, M = pos32[r].astype(np.float64), m32[r].astype(np.float64)
+        gt = oracle.Tree(P, M, w.box, type=w.type, gas_only=True)
+        gas = np.nonzero(w.type == 0)[0]
+        ref = oracle.density(gt, dataclasses.replace(p, h_tol=1e-10), active=gas, solve_h=True)
+        rel = np.abs(hg[r][gas] / ref["h"][gas] - 1.0).max()
+        print(f"forest {k} solved h: max rel diff {rel:.2e}", flush=True)
+        assert rel < 2e-6
+        e1 = oracle.density_backward(gt, p, ref["h"], g_rho=b[r].astype(np.float64), active=gas)
+        e2 = oracle.density_solve_backward(gt, p, ref["h"], ref["rho"], ref["drho_dh"],
+                                           a[r] + e1["h"], active=gas)
+        check(f"forest {k} solve g_pos", gp[r], e1["pos"] + e2["pos"],
+              e1["S"]["pos"] + e2["S"]["pos"], tol=SOLVE_TOL)
+        check(f"forest {k} solve g_mass", gm[r], e1["mass"] + e2["mass"],
+              e1["S"]["mass"] + e2["S"]["mass"], tol=SOLVE_TOL)
