@@ -165,12 +165,50 @@ __global__ __launch_bounds__(kBlock) void k_density(
     float sw = 0.0f, swh = 0.0f, sss = 0.0f, csw = 0.0f, cswh = 0.0f, csss = 0.0f;
     int cnt = 0;
     int tc = 0, cand = 0;
+    // the box of this pass's live targets and their largest squared radius:
+    // a candidate whose box_dist2 to that box is not below it fails every
+    // lane's neighbour test (box_dist2 never exceeds the r2 of a point in
+    // the box), so it is dropped before the tile is scanned
+    float4 tlo = make_float4(live ? xi.x : INFINITY, live ? xi.y : INFINITY,
+                             live ? xi.z : INFINITY, 0.f);
+    float4 thi = make_float4(live ? xi.x : -INFINITY, live ? xi.y : -INFINITY,
+                             live ? xi.z : -INFINITY, 0.f);
+    float hmax2 = h2;
+    if constexpr (!kF64 && kQ == 1) {
+#pragma unroll
+      for (int m = 1; m < kWave; m <<= 1) {
+        tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
+        tlo.y = fminf(tlo.y, __shfl_xor(tlo.y, m));
+        tlo.z = fminf(tlo.z, __shfl_xor(tlo.z, m));
+        thi.x = fmaxf(thi.x, __shfl_xor(thi.x, m));
+        thi.y = fmaxf(thi.y, __shfl_xor(thi.y, m));
+        thi.z = fmaxf(thi.z, __shfl_xor(thi.z, m));
+        hmax2 = fmaxf(hmax2, __shfl_xor(hmax2, m));
+      }
+      // wave-uniform now: held in scalar registers through the walk
+      auto su = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+      tlo = make_float4(su(tlo.x), su(tlo.y), su(tlo.z), 0.f);
+      thi = make_float4(su(thi.x), su(thi.y), su(thi.z), 0.f);
+      hmax2 = su(hmax2);
+    }
     auto flush = [&](int nc) {
       // unused slots sit at infinity and fail every neighbour test
-      if constexpr (kF64)
+      if constexpr (kF64) {
         tile64[lane] = (lane < nc) ? x64[cand] : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-      else
+      } else if constexpr (kQ == 1) {
+        const float4 v = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        const bool keep = lane < nc && box_dist2(make_float3(v.x, v.y, v.z), tlo, thi) < hmax2;
+        const uint64_t km = __ballot(keep);
+        const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        // kept candidates in their order at the front, infinity behind
+        // (the two stores of one wave reach LDS in program order)
+        tile[lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        if (keep) tile[slot] = v;
+        nc = __popcll(km);
+      } else {
         tile[lane] = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+      }
       wave_sync();
       // every lane tests every entry (read by broadcast); the kernel sum runs
       // under the lanes that pass, and is skipped when none does. (Marking
@@ -484,9 +522,55 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vs = 0.f;
   float cax = 0.f, cay = 0.f, caz = 0.f, cdu = 0.f;
   int np = 0, tc = 0, cand = 0;
+  // the box of the group's targets and their largest squared radius: a
+  // candidate j whose box_dist2 to that box reaches both it and fl(h_j^2)
+  // fails every lane's symmetric test (box_dist2 never exceeds the r2 of a
+  // point in the box), so it is dropped before the tile is scanned
+  float4 tlo = make_float4(valid ? xi.x : INFINITY, valid ? xi.y : INFINITY,
+                           valid ? xi.z : INFINITY, 0.f);
+  float4 thi = make_float4(valid ? xi.x : -INFINITY, valid ? xi.y : -INFINITY,
+                           valid ? xi.z : -INFINITY, 0.f);
+  float hmax2 = hi2;
+  if constexpr (!kF64) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+      tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
+      tlo.y = fminf(tlo.y, __shfl_xor(tlo.y, m));
+      tlo.z = fminf(tlo.z, __shfl_xor(tlo.z, m));
+      thi.x = fmaxf(thi.x, __shfl_xor(thi.x, m));
+      thi.y = fmaxf(thi.y, __shfl_xor(thi.y, m));
+      thi.z = fmaxf(thi.z, __shfl_xor(thi.z, m));
+      hmax2 = fmaxf(hmax2, __shfl_xor(hmax2, m));
+    }
+    // wave-uniform now: held in scalar registers through the walk
+    auto su = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+    tlo = make_float4(su(tlo.x), su(tlo.y), su(tlo.z), 0.f);
+    thi = make_float4(su(thi.x), su(thi.y), su(thi.z), 0.f);
+    hmax2 = su(hmax2);
+  }
 
   auto flush = [&](int nc) {
-    if (lane < nc) {
+    if constexpr (!kF64) {
+      float4 vx = make_float4(INFINITY, INFINITY, INFINITY, 0.f), vv = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 va = vv;
+      if (lane < nc) {
+        vx = xm[cand];
+        vv = vh[cand];
+        va = aux[cand];
+      }
+      const float d2 = box_dist2(make_float3(vx.x, vx.y, vx.z), tlo, thi);
+      const bool keep = lane < nc && (d2 < hmax2 || d2 < sq_exact(vv.w));
+      const uint64_t km = __ballot(keep);
+      const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      // kept candidates in their order at the front; the scan stops at nc
+      if (keep) {
+        T.xm[w][slot] = vx;
+        T.vh[w][slot] = vv;
+        T.aux[w][slot] = va;
+      }
+      nc = __popcll(km);
+    } else if (lane < nc) {
       T.xm[w][lane] = xm[cand];
       if constexpr (kF64) {
         tiles64[w][lane] = x64[cand];
@@ -497,10 +581,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     } else {  // unused slots sit at infinity and fail every neighbour test
       T.xm[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
       T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if constexpr (kF64) {
-        tiles64[w][lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-        th64[w][lane] = 0.0;
-      }
+      tiles64[w][lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+      th64[w][lane] = 0.0;
     }
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
