@@ -144,13 +144,50 @@ __global__ __launch_bounds__(kBlock) void k_density_bwd(
     float gx = 0.f, gy = 0.f, gz = 0.f, gm = 0.f, gh = 0.f;
     float cx = 0.f, cy = 0.f, cz = 0.f, cm = 0.f, ch = 0.f;
     int tc = 0, cand = 0;
+    // the box of the group's particles and the largest radius of their own
+    // sums: a candidate q whose box_dist2 to the box reaches that radius and
+    // (when q's sums carry gradients) fl(h_q^2) meets no lane's test, since
+    // box_dist2 never exceeds the r2 of a point inside the box
+    float4 tlo = make_float4(valid ? me.x : INFINITY, valid ? me.y : INFINITY,
+                             valid ? me.z : INFINITY, 0.f);
+    float4 thi = make_float4(valid ? me.x : -INFINITY, valid ? me.y : -INFINITY,
+                             valid ? me.z : -INFINITY, 0.f);
+    float hmax2 = own_on ? hp2 : -1.0f;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+      tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
+      tlo.y = fminf(tlo.y, __shfl_xor(tlo.y, m));
+      tlo.z = fminf(tlo.z, __shfl_xor(tlo.z, m));
+      thi.x = fmaxf(thi.x, __shfl_xor(thi.x, m));
+      thi.y = fmaxf(thi.y, __shfl_xor(thi.y, m));
+      thi.z = fmaxf(thi.z, __shfl_xor(thi.z, m));
+      hmax2 = fmaxf(hmax2, __shfl_xor(hmax2, m));
+    }
+    {
+      auto su = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+      tlo = make_float4(su(tlo.x), su(tlo.y), su(tlo.z), 0.f);
+      thi = make_float4(su(thi.x), su(thi.y), su(thi.z), 0.f);
+      hmax2 = su(hmax2);
+    }
     auto flush = [&](int nc) {
-      if (lane < nc) {
-        tx[w][lane] = xm[cand];
-        tb[w][lane] = bw[cand];
-      } else {
-        tx[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-        tb[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+      {
+        float4 vx = make_float4(INFINITY, INFINITY, INFINITY, 0.f), vb = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < nc) {
+          vx = xm[cand];
+          vb = bw[cand];
+        }
+        const float d2 = box_dist2(make_float3(vx.x, vx.y, vx.z), tlo, thi);
+        const bool keep = lane < nc && (d2 < hmax2 || ((vb.y != 0.0f || vb.z != 0.0f) &&
+                                                       d2 < sq_exact(vb.x)));
+        const uint64_t km = __ballot(keep);
+        const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        // kept candidates in their order at the front; the scan stops at nc
+        if (keep) {
+          tx[w][slot] = vx;
+          tb[w][slot] = vb;
+        }
+        nc = __popcll(km);
       }
       wave_sync();
       float px = 0.f, py = 0.f, pz = 0.f, pm = 0.f, ph = 0.f;
@@ -681,17 +718,52 @@ __global__ __launch_bounds__(kBlock) void k_hydro_bwd(
 #pragma unroll
     for (int k = 0; k < kN; ++k) acc[k] = cmp[k] = 0.0f;
     int tc = 0, cand = 0;
+    // the box of the group's particles and their largest fl(h^2): a
+    // candidate q whose box_dist2 to the box reaches both that and
+    // fl(h_q^2) is in no lane's symmetric neighbourhood, since box_dist2
+    // never exceeds the r2 of a point inside the box
+    float4 tlo = make_float4(valid ? P.xm.x : INFINITY, valid ? P.xm.y : INFINITY,
+                             valid ? P.xm.z : INFINITY, 0.f);
+    float4 thi = make_float4(valid ? P.xm.x : -INFINITY, valid ? P.xm.y : -INFINITY,
+                             valid ? P.xm.z : -INFINITY, 0.f);
+    float hmax2 = valid ? sq_exact(hp) : -1.0f;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+      tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
+      tlo.y = fminf(tlo.y, __shfl_xor(tlo.y, m));
+      tlo.z = fminf(tlo.z, __shfl_xor(tlo.z, m));
+      thi.x = fmaxf(thi.x, __shfl_xor(thi.x, m));
+      thi.y = fmaxf(thi.y, __shfl_xor(thi.y, m));
+      thi.z = fmaxf(thi.z, __shfl_xor(thi.z, m));
+      hmax2 = fmaxf(hmax2, __shfl_xor(hmax2, m));
+    }
+    {
+      auto su = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+      tlo = make_float4(su(tlo.x), su(tlo.y), su(tlo.z), 0.f);
+      thi = make_float4(su(thi.x), su(thi.y), su(thi.z), 0.f);
+      hmax2 = su(hmax2);
+    }
     auto flush = [&](int nc) {
-      if (lane < nc) {
-        T[w][lane].xm = xm[cand];
-        T[w][lane].vh = vh[cand];
-        T[w][lane].aux = aux[cand];
-        T[w][lane].up = up[cand];
-      } else {
-        T[w][lane].xm = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-        T[w][lane].vh = make_float4(0.f, 0.f, 0.f, 0.f);
-        T[w][lane].aux = make_float4(0.f, 0.f, 1.f, 1.f);
-        T[w][lane].up = make_float4(0.f, 0.f, 0.f, 0.f);
+      {
+        HSide Q;
+        Q.xm = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        Q.vh = make_float4(0.f, 0.f, 0.f, 0.f);
+        Q.aux = make_float4(0.f, 0.f, 1.f, 1.f);
+        Q.up = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < nc) {
+          Q.xm = xm[cand];
+          Q.vh = vh[cand];
+          Q.aux = aux[cand];
+          Q.up = up[cand];
+        }
+        const float d2 = box_dist2(make_float3(Q.xm.x, Q.xm.y, Q.xm.z), tlo, thi);
+        const bool keep = lane < nc && (d2 < hmax2 || d2 < sq_exact(Q.vh.w));
+        const uint64_t km = __ballot(keep);
+        const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        // kept candidates in their order at the front; the scan stops at nc
+        if (keep) T[w][slot] = Q;
+        nc = __popcll(km);
       }
       wave_sync();
       float part[kN];
