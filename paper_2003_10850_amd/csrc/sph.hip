@@ -173,8 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_density(
                              live ? xi.z : INFINITY, 0.f);
     float4 thi = make_float4(live ? xi.x : -INFINITY, live ? xi.y : -INFINITY,
                              live ? xi.z : -INFINITY, 0.f);
-    float hmax2 = h2;
-    if constexpr (!kF64 && kQ == 1) {
+    // (with FP64 positions: the FP32 copies and the walk's padded radius)
+    float hmax2 = kF64 ? hw2 : h2;
+    if constexpr (kQ == 1) {
 #pragma unroll
       for (int m = 1; m < kWave; m <<= 1) {
         tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
@@ -194,7 +195,19 @@ __global__ __launch_bounds__(kBlock) void k_density(
     auto flush = [&](int nc) {
       // unused slots sit at infinity and fail every neighbour test
       if constexpr (kF64) {
-        tile64[lane] = (lane < nc) ? x64[cand] : make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        double4 v64 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        float4 v = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        if (lane < nc) {
+          v64 = x64[cand];
+          v = xm[cand];
+        }
+        const bool keep = lane < nc && box_dist2(make_float3(v.x, v.y, v.z), tlo, thi) < hmax2;
+        const uint64_t km = __ballot(keep);
+        const int slot = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+        tile64[lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        if (keep) tile64[slot] = v64;
+        nc = __popcll(km);
       } else if constexpr (kQ == 1) {
         const float4 v = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
         const bool keep = lane < nc && box_dist2(make_float3(v.x, v.y, v.z), tlo, thi) < hmax2;
@@ -530,8 +543,9 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
                            valid ? xi.z : INFINITY, 0.f);
   float4 thi = make_float4(valid ? xi.x : -INFINITY, valid ? xi.y : -INFINITY,
                            valid ? xi.z : -INFINITY, 0.f);
-  float hmax2 = hi2;
-  if constexpr (!kF64) {
+  // (with FP64 positions: the FP32 copies and radii padded as in the walk)
+  float hmax2 = kF64 ? (valid ? sq_exact(hi + slack) : -1.0f) : hi2;
+  {
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) {
       tlo.x = fminf(tlo.x, __shfl_xor(tlo.x, m));
@@ -550,16 +564,22 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   }
 
   auto flush = [&](int nc) {
-    if constexpr (!kF64) {
+    {
       float4 vx = make_float4(INFINITY, INFINITY, INFINITY, 0.f), vv = make_float4(0.f, 0.f, 0.f, 0.f);
       float4 va = vv;
+      double4 v64 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+      double h64c = 0.0;
       if (lane < nc) {
         vx = xm[cand];
         vv = vh[cand];
         va = aux[cand];
+        if constexpr (kF64) {
+          v64 = x64[cand];
+          h64c = h64[cand];
+        }
       }
       const float d2 = box_dist2(make_float3(vx.x, vx.y, vx.z), tlo, thi);
-      const bool keep = lane < nc && (d2 < hmax2 || d2 < sq_exact(vv.w));
+      const bool keep = lane < nc && (d2 < hmax2 || d2 < sq_exact(kF64 ? vv.w + slack : vv.w));
       const uint64_t km = __ballot(keep);
       const int slot = (int)__builtin_amdgcn_mbcnt_hi(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
@@ -568,21 +588,12 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
         T.xm[w][slot] = vx;
         T.vh[w][slot] = vv;
         T.aux[w][slot] = va;
+        if constexpr (kF64) {
+          tiles64[w][slot] = v64;
+          th64[w][slot] = h64c;
+        }
       }
       nc = __popcll(km);
-    } else if (lane < nc) {
-      T.xm[w][lane] = xm[cand];
-      if constexpr (kF64) {
-        tiles64[w][lane] = x64[cand];
-        th64[w][lane] = h64[cand];
-      }
-      T.vh[w][lane] = vh[cand];
-      T.aux[w][lane] = aux[cand];
-    } else {  // unused slots sit at infinity and fail every neighbour test
-      T.xm[w][lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-      T.vh[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-      tiles64[w][lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-      th64[w][lane] = 0.0;
     }
     wave_sync();
     float px = 0.f, py = 0.f, pz = 0.f, pu = 0.f;
