@@ -25,6 +25,13 @@
  *    and the call returns without waiting, unless its comment says SYNCS.
  *  - Every call returns a g3_status and never aborts; an asynchronous device
  *    error surfaces as G3_EHIP on a later call. g3_last_error() gives text.
+ *    A call that fails with G3_EINVAL, G3_ESTATE or G3_ENOMEM leaves no work
+ *    of its own on the stream: the interaction calls (g3_walk, g3_density,
+ *    g3_hydro_force, g3_gravity and the _backward twins) take every device
+ *    buffer before their first launch and enqueue nothing when one cannot
+ *    be had; the builds, which SYNC anyway, wait for what they had enqueued
+ *    before returning, and a tree whose build failed is unusable (G3_ESTATE)
+ *    until a later build of it succeeds. Outputs are then untouched.
  *  - One g3_ctx per host thread. A g3_tree belongs to the ctx that built it.
  *  - Graph capture: g3_density, g3_hydro_force, g3_gravity and the
  *    _backward calls neither wait on the host nor use memset nodes; they
@@ -54,10 +61,10 @@ extern "C" {
 typedef enum {
   G3_OK = 0,
   G3_EINVAL = -1,    /* bad argument; nothing enqueued */
-  G3_ENOMEM = -2,    /* device allocation failed */
+  G3_ENOMEM = -2,    /* device allocation failed; nothing enqueued */
   G3_EHIP = -3,      /* HIP runtime or earlier asynchronous device error */
   G3_EOVERFLOW = -4, /* g3_walk: list longer than capacity (total is set) */
-  G3_ENOCONV = -5,   /* h solve did not converge for some particles */
+  G3_ENOCONV = -5,   /* g3_ctx_stats: some h solve did not converge */
   G3_ESTATE = -6     /* tree/ctx misuse (e.g. tree of another device) */
 } g3_status;
 
@@ -91,10 +98,26 @@ void g3_ctx_destroy(g3_ctx *ctx);
 /* Text of the last error of this ctx ("" if none). Valid until the next call. */
 const char *g3_last_error(const g3_ctx *ctx);
 /* Counters of the h solve since the last reset (reset != 0 clears them):
- * stats (host) [4] = particles whose solve hit its iteration or bracket cap
- * (non-converged), walk passes summed over wavefronts, wavefronts, 0.
- * SYNCS the ctx's last stream. */
+ * stats (host) [4] = particles whose solve hit its pass limit or the
+ * bracket cap of twice the box diagonal without converging (their h and
+ * density are those of the last pass), walk passes summed over wavefronts,
+ * wavefronts, 0. This is where g3_density, which never waits on the host,
+ * reports non-convergence: the call returns G3_ENOCONV (stats still filled)
+ * when the first counter is above zero, else G3_OK. SYNCS the ctx's last
+ * stream. */
 int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
+/* Fault injection, for tests of the error paths:
+ *   G3_INJECT_ALLOC     value >= 0: the next `value` device allocations the
+ *                       ctx makes (trees and scratch) succeed and every
+ *                       later one fails, as on a device out of memory, so
+ *                       the calls that need one return G3_ENOMEM; value < 0
+ *                       turns the injection off.
+ *   G3_INJECT_MAX_ITER  value in 1..64: walk passes the h solve may take
+ *                       before it stops and counts the particle as not
+ *                       converged (g3_ctx_stats); value <= 0 restores 64.
+ * Host-side only (no device work, no wait). */
+enum { G3_INJECT_ALLOC = 1, G3_INJECT_MAX_ITER = 2 };
+int g3_ctx_inject(g3_ctx *ctx, int32_t what, int64_t value);
 
 /*
  * Build (or rebuild in place) the octrees of one particle set (one
@@ -212,8 +235,11 @@ int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
  * relative accuracy h_tol (h[i] > 0 on entry is the first guess); h is then
  * an output. solve_h = 0: h is an input. h is float for a tree built from
  * FP32 positions, double for FP64 positions (the h solve then runs in FP64).
- * Output pointers other than h may be NULL. Non-converged particles are
- * counted (g3_ctx_stats). */
+ * Output pointers other than h may be NULL. Particles whose solve does not
+ * converge (no root below the cap of twice the box diagonal, e.g. a target
+ * above what the snapshot's gas can give, or the pass limit reached) keep
+ * the h and sums of their last pass and are counted: g3_ctx_stats then
+ * returns G3_ENOCONV. */
 int g3_density(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                const int32_t *active, const g3_params *p, int32_t solve_h,
                void *h, float *rho, float *drho_dh, float *omega,

@@ -18,6 +18,15 @@ namespace g3 {
 
 int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, hipStream_t s);
 
+hipError_t dev_malloc(g3_ctx *c, void **p, size_t bytes) {
+  *p = nullptr;
+  if (c->alloc_budget == 0) return hipErrorOutOfMemory;
+  if (c->alloc_budget > 0) --c->alloc_budget;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) *p = nullptr;
+  return e;
+}
+
 void *scratch(g3_ctx *c, int slot, size_t bytes) {
   g3_ctx::Buf &b = c->scratch[slot];
   if (b.p && bytes <= b.bytes) return b.p;
@@ -25,10 +34,7 @@ void *scratch(g3_ctx *c, int slot, size_t bytes) {
   b.p = nullptr;
   b.bytes = 0;
   const size_t want = bytes + bytes / 4 + 256;
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    b.p = nullptr;
-    return nullptr;
-  }
+  if (dev_malloc(c, &b.p, want) != hipSuccess) return nullptr;
   b.bytes = want;
   return b.p;
 }
@@ -229,23 +235,85 @@ __global__ void k_seg_groups(const int32_t *__restrict__ tstart, const int32_t *
 
 }  // namespace
 
+// The buffers of one call's group table, taken before its first launch so
+// that a failed allocation leaves nothing enqueued. The split tables reuse
+// the compaction's mark and row buffers (kFlags, kCounts), which the
+// stream has consumed by then; one scan buffer serves every scan.
+struct WorkBufs {
+  int64_t max_t = 0, max_seg = 0;
+  bool split_on = false;
+  uint32_t *stmp = nullptr, *mark = nullptr, *slot = nullptr;
+  int32_t *rowp1 = nullptr, *tg = nullptr, *rw = nullptr, *tab = nullptr;
+  uint32_t *flags = nullptr, *segid = nullptr, *gcnt = nullptr;
+};
+
+int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t n_act,
+                 const int32_t *active, int split, WorkBufs *b) {
+  *b = WorkBufs();
+  const int64_t m = o.n;
+  if (m == 0) return G3_OK;
+  const int n_snap = t->n_snap;
+  const int64_t max_t = active ? std::min<int64_t>(n_act, m) : m;
+  const bool split_on = split >= 0 || split == kSplitAuto;
+  const int64_t max_seg = split_on ? std::max<int64_t>(max_t, 1) : n_snap;
+  b->max_t = max_t;
+  b->max_seg = max_seg;
+  b->split_on = split_on;
+  int64_t scan_n = 1;
+  if (active) scan_n = std::max(scan_n, m + 1);
+  if (split_on) scan_n = std::max(scan_n, std::max(max_t, max_seg) + 1);
+  uint32_t *stmp = nullptr, *mark = nullptr, *slot = nullptr;
+  int32_t *rowp1 = nullptr, *tg = nullptr, *rw = nullptr;
+  if (active || split_on) {
+    stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(scan_n) * sizeof(uint32_t));
+    if (!stmp) return fail(c, G3_ENOMEM, "device allocation of the scan scratch failed");
+  }
+  if (active) {
+    mark = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
+    slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
+    rowp1 = (int32_t *)scratch(c, kCounts, (m + 2) * sizeof(int32_t));
+    tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
+    rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
+    if (!mark || !slot || !rowp1 || !tg || !rw)
+      return fail(c, G3_ENOMEM, "device allocation of the active-set scratch failed");
+  }
+  // tstart, gstart [max_seg + 2] (a scan writes one past its n), seg_snap
+  // [max_seg + 1], nseg, queue [8]
+  const size_t tab_elems = 3 * ((size_t)max_seg + 2) + 1 + 8;
+  int32_t *tab = (int32_t *)scratch(c, kGroups, tab_elems * sizeof(int32_t));
+  if (!tab) return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+  uint32_t *flags = nullptr, *segid = nullptr, *gcnt = nullptr;
+  if (split_on) {
+    flags = (uint32_t *)scratch(c, kCounts, (m + 2) * sizeof(uint32_t));
+    segid = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
+    gcnt = (uint32_t *)scratch(c, kIds, (max_seg + 2) * sizeof(uint32_t));
+    if (!flags || !segid || !gcnt)
+      return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+    // the compaction's buffers must not have moved (same slots, same sizes)
+    if (active && (flags != (uint32_t *)rowp1 || segid != mark))
+      return fail(c, G3_EHIP, "group table scratch moved");
+  }
+  b->stmp = stmp; b->mark = mark; b->slot = slot;
+  b->rowp1 = rowp1; b->tg = tg; b->rw = rw; b->tab = tab;
+  b->flags = flags; b->segid = segid; b->gcnt = gcnt;
+  return G3_OK;
+}
+
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
                  int64_t n_act, const int32_t *active, Work *w, hipStream_t s, int split) {
   *w = Work();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
+  WorkBufs b;
+  const int st = reserve_work(c, t, o, n_act, active, split, &b);
+  if (st) return st;
   const int n_snap = t->n_snap;
-  int32_t *tg = nullptr, *rw = nullptr;
-  uint32_t *slot = nullptr;
+  const int64_t max_t = b.max_t, max_seg = b.max_seg;
+  const bool split_on = b.split_on;
+  uint32_t *stmp = b.stmp, *mark = b.mark, *slot = b.slot;
+  int32_t *rowp1 = b.rowp1, *tg = b.tg, *rw = b.rw, *tab = b.tab;
+  uint32_t *flags = b.flags, *segid = b.segid, *gcnt = b.gcnt;
   if (active) {
-    uint32_t *mark = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
-    slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
-    int32_t *rowp1 = (int32_t *)scratch(c, kCounts, (m + 2) * sizeof(int32_t));
-    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(m + 1) * sizeof(uint32_t));
-    tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
-    rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
-    if (!mark || !slot || !rowp1 || !stmp || !tg || !rw)
-      return fail(c, G3_ENOMEM, "device allocation of the active-set scratch failed");
     k_zero_u32<<<nblk(m), 256, 0, s>>>(mark, m);
     if (n_act > 0)
       k_mark<<<nblk(n_act), 256, 0, s>>>(active, n_act, iperm, t->n, mark, rowp1);
@@ -253,15 +321,7 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
     if (e != hipSuccess) return hip_fail(c, e, "active-set scan");
     k_compact<<<nblk(m), 256, 0, s>>>(mark, slot, rowp1, m, tg, rw);
   }
-  const int64_t max_t = active ? std::min<int64_t>(n_act, m) : m;
   const uint32_t *ntarg = active ? slot + m : nullptr;
-  const bool split_on = split >= 0 || split == kSplitAuto;
-  const int64_t max_seg = split_on ? std::max<int64_t>(max_t, 1) : n_snap;
-  // tstart, gstart [max_seg + 2] (a scan writes one past its n), seg_snap
-  // [max_seg + 1], nseg, queue [8]
-  const size_t tab_elems = 3 * ((size_t)max_seg + 2) + 1 + 8;
-  int32_t *tab = (int32_t *)scratch(c, kGroups, tab_elems * sizeof(int32_t));
-  if (!tab) return fail(c, G3_ENOMEM, "device allocation of the group table failed");
   int32_t *tstart = tab, *gstart = tab + max_seg + 2, *seg_snap = gstart + max_seg + 2;
   int32_t *nseg = seg_snap + max_seg + 2;
   unsigned *queue = (unsigned *)(nseg + 1);
@@ -269,15 +329,6 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
     k_group_table<<<1, kTableBlock, 0, s>>>(o.soff, n_snap, slot, tstart, gstart, seg_snap, nseg,
                                             queue);
   } else {
-    // the compaction's scratch (mark, rowp1) is free again here
-    uint32_t *flags = (uint32_t *)scratch(c, kCounts, (m + 2) * sizeof(uint32_t));
-    uint32_t *segid = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
-    uint32_t *gcnt = (uint32_t *)scratch(c, kIds, (max_seg + 2) * sizeof(uint32_t));
-    uint32_t *stmp = (uint32_t *)scratch(c, kScanTmp,
-                                         scan_tmp_elems(std::max(max_t, max_seg) + 1) *
-                                             sizeof(uint32_t));
-    if (!flags || !segid || !gcnt || !stmp)
-      return fail(c, G3_ENOMEM, "device allocation of the group table failed");
     const int level = split == kSplitAuto ? split : std::min(split, (int)kMaxLevel);
     k_seg_flags<<<nblk(max_t + 1), 256, 0, s>>>(tg, ntarg, max_t, o.keys, o.soff, n_snap, level,
                                                flags);
@@ -345,7 +396,7 @@ int g3_ctx_create(g3_ctx **out, int device) {
   DeviceGuard g(device);
   g3_ctx *c = new g3_ctx;
   c->device = device;
-  if (hipMalloc((void **)&c->counters, 8 * sizeof(unsigned long long)) != hipSuccess) {
+  if (dev_malloc(c, (void **)&c->counters, 8 * sizeof(unsigned long long)) != hipSuccess) {
     delete c;
     return G3_ENOMEM;
   }
@@ -407,8 +458,30 @@ int g3_ctx_stats(g3_ctx *c, int64_t *stats, int32_t reset) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_ctx_stats reset");
   }
+  if (stats[0] > 0)
+    return fail(c, G3_ENOCONV, std::to_string(stats[0]) +
+                                   " particles' h solves did not converge since the last reset");
   return G3_OK;
 }
+
+int g3_ctx_inject(g3_ctx *c, int32_t what, int64_t value) {
+  if (!c) return G3_EINVAL;
+  if (what == G3_INJECT_ALLOC) {
+    c->alloc_budget = value < 0 ? -1 : value;
+    return G3_OK;
+  }
+  if (what == G3_INJECT_MAX_ITER) {
+    if (value > 64) return fail(c, G3_EINVAL, "g3_ctx_inject: the pass limit is at most 64");
+    c->max_iter = value <= 0 ? 64 : (int)value;
+    return G3_OK;
+  }
+  return fail(c, G3_EINVAL, "g3_ctx_inject: unknown injection");
+}
+
+static int build_forest_body(g3_ctx *c, g3_tree *t, int32_t n_snap, const int64_t *snap_off,
+                             const void *pos, const float *mass, const uint8_t *type,
+                             const double *box, const g3_params *p, int32_t pos_t,
+                             hipStream_t s);
 
 int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t pos_t,
                     const void *pos, const float *mass, const uint8_t *type, const double *box,
@@ -447,14 +520,33 @@ int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t 
     c->trees.push_back(t);
     *tree = t;
   }
+  t->built = false;
+  st = build_forest_body(c, t, n_snap, snap_off, pos, mass, type, box, p, pos_t, s);
+  if (st) {
+    // a failed build leaves no work of its own in flight on the stream
+    (void)hipStreamSynchronize(s);
+    return st;
+  }
+  t->built = true;
+  c->err.clear();
+  return G3_OK;
+}
+
+// The work of g3_build_forest after its argument checks.
+static int build_forest_body(g3_ctx *c, g3_tree *t, int32_t n_snap, const int64_t *snap_off,
+                             const void *pos, const float *mass, const uint8_t *type,
+                             const double *box, const g3_params *p, int32_t pos_t,
+                             hipStream_t s) {
+  const int64_t n = snap_off[n_snap];
+  int st = G3_OK;
   if (n > t->cap_n || !t->iperm_all) {
     if (t->iperm_all) (void)hipFree(t->iperm_all);
     if (t->iperm_gas) (void)hipFree(t->iperm_gas);
     t->iperm_all = t->iperm_gas = nullptr;
     t->cap_n = 0;
     const int64_t cap = n > 0 ? n : 1;
-    if (hipMalloc((void **)&t->iperm_all, cap * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&t->iperm_gas, cap * sizeof(int32_t)) != hipSuccess)
+    if (dev_malloc(c, (void **)&t->iperm_all, cap * sizeof(int32_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->iperm_gas, cap * sizeof(int32_t)) != hipSuccess)
       return fail(c, G3_ENOMEM, "g3_build_forest: allocation failed");
     t->cap_n = cap;
   }
@@ -466,12 +558,12 @@ int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t 
     t->all.soff = t->all.nroot = t->gas.soff = t->gas.nroot = nullptr;
     t->cap_snap = 0;
     const size_t k1 = (size_t)n_snap + 1;
-    if (hipMalloc((void **)&t->coff, k1 * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc((void **)&t->sbox, k1 * sizeof(double4)) != hipSuccess ||
-        hipMalloc((void **)&t->all.soff, k1 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&t->all.nroot, k1 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&t->gas.soff, k1 * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&t->gas.nroot, k1 * sizeof(int32_t)) != hipSuccess)
+    if (dev_malloc(c, (void **)&t->coff, k1 * sizeof(int64_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->sbox, k1 * sizeof(double4)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->all.soff, k1 * sizeof(int32_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->all.nroot, k1 * sizeof(int32_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->gas.soff, k1 * sizeof(int32_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&t->gas.nroot, k1 * sizeof(int32_t)) != hipSuccess)
       return fail(c, G3_ENOMEM, "g3_build_forest: allocation failed");
     t->cap_snap = n_snap;
   }
@@ -510,7 +602,6 @@ int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t 
   if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest");
   st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s, type);
   if (st) return st;
-  c->err.clear();
   return G3_OK;
 }
 
@@ -528,6 +619,7 @@ int g3_refit_tree(g3_ctx *c, g3_tree *t, const void *pos, const float *mass, voi
   if (!c) return G3_EINVAL;
   if (!t) return fail(c, G3_EINVAL, "g3_refit_tree: null tree");
   if (t->owner != c) return fail(c, G3_ESTATE, "g3_refit_tree: tree of another ctx");
+  if (!t->built) return fail(c, G3_ESTATE, "g3_refit_tree: tree not built (its last build failed)");
   if (t->n > 0 && (!pos || !mass)) return fail(c, G3_EINVAL, "g3_refit_tree: null pos/mass");
   DeviceGuard g(c->device);
   int st = check_pending(c);
@@ -568,6 +660,7 @@ int g3_tree_export(g3_ctx *c, const g3_tree *t, int32_t which, int32_t *order, u
   if (!c) return G3_EINVAL;
   if (!t || (which != 0 && which != 1)) return fail(c, G3_EINVAL, "g3_tree_export: bad tree");
   if (t->owner != c) return fail(c, G3_ESTATE, "g3_tree_export: tree of another ctx");
+  if (!t->built) return fail(c, G3_ESTATE, "g3_tree_export: tree not built (its last build failed)");
   DeviceGuard g(c->device);
   int st = check_pending(c);
   if (st) return st;
@@ -639,13 +732,27 @@ static Tuning tuning_for(const g3_ctx *c, int kind, int64_t n) {
   return best ? *best : default_tuning(kind);
 }
 
-static SphParams sph_params(const g3_params *p, const g3_tree *t, const Tuning &tu) {
+// FP64 trees: the gas octree's FP64 copy of h in sorted order, grown to
+// its member count (before any launch of the call that needs it).
+static int ensure_h64(g3_ctx *c, const g3_tree *t, Octree &o) {
+  if (!t->f64 || o.n == 0 || (o.h64 && o.cap_h64 >= o.n)) return G3_OK;
+  if (o.h64) (void)hipFree(o.h64);
+  o.h64 = nullptr;
+  o.cap_h64 = 0;
+  if (dev_malloc(c, (void **)&o.h64, o.n * sizeof(double)) != hipSuccess)
+    return fail(c, G3_ENOMEM, "device allocation of the FP64 smoothing lengths failed");
+  o.cap_h64 = o.n;
+  return G3_OK;
+}
+
+static SphParams sph_params(const g3_ctx *c, const g3_params *p, const g3_tree *t,
+                            const Tuning &tu) {
   SphParams sp;
   sp.n_ngb = (float)p->n_ngb;
   sp.h_tol = (float)p->h_tol;
   sp.gamma = (float)p->gamma;
   sp.alpha = (float)p->alpha;
-  sp.max_iter = 64;
+  sp.max_iter = c->max_iter;
   sp.walk_leaf = tu.walk_leaf;
   // candidate streams exist for the FP32 density only
   sp.streams = (!t->f64 && tu.streams == 4) ? 4 : 1;
@@ -658,6 +765,8 @@ static int active_args_ok(g3_ctx *c, const g3_tree *t, int64_t n_act, const int3
                           const char *who) {
   if (!t) return fail(c, G3_EINVAL, std::string(who) + ": null tree");
   if (t->owner != c) return fail(c, G3_ESTATE, std::string(who) + ": tree of another ctx");
+  if (!t->built)
+    return fail(c, G3_ESTATE, std::string(who) + ": tree not built (its last build failed)");
   if (n_act < 0) return fail(c, G3_EINVAL, std::string(who) + ": n_act < 0");
   if (!active && n_act != t->n)
     return fail(c, G3_EINVAL, std::string(who) + ": active == NULL needs n_act == n");
@@ -686,18 +795,18 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   c->last_stream = s;
   Octree &o = (kind == G3_GRAVITY) ? t->all : t->gas;
   const int32_t *iperm = (kind == G3_GRAVITY) ? t->iperm_all : t->iperm_gas;
+  int32_t *counts = (int32_t *)scratch(c, kWalkCounts, (n_act + 1) * sizeof(int32_t));
+  int64_t *stmp = (int64_t *)scratch(c, kMisc, scan_tmp_elems(n_act) * sizeof(int64_t) + 64);
+  if (!counts || !stmp) return fail(c, G3_ENOMEM, "g3_walk: allocation failed");
+  Work wk;
+  st = prepare_work(c, t, o, iperm, n_act, active, &wk, s);
+  if (st) return st;
   hipError_t e;
   if (kind != G3_GRAVITY && o.n > 0) {
     e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
     if (e == hipSuccess && kind == G3_SYMMETRIC) e = refit_hmax(o, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk prep");
   }
-  Work wk;
-  st = prepare_work(c, t, o, iperm, n_act, active, &wk, s);
-  if (st) return st;
-  int32_t *counts = (int32_t *)scratch(c, kWalkCounts, (n_act + 1) * sizeof(int32_t));
-  int64_t *stmp = (int64_t *)scratch(c, kMisc, scan_tmp_elems(n_act) * sizeof(int64_t) + 64);
-  if (!counts || !stmp) return fail(c, G3_ENOMEM, "g3_walk: allocation failed");
   e = fill_i32(counts, 0, n_act, s);
   GravParams gp = grav_params(p, t);
   if (e == hipSuccess)
@@ -738,7 +847,7 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
-  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(p, t, tu), solve_h ? 1 : 0,
+  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(c, p, t, tu), solve_h ? 1 : 0,
                                 h, rho, drho_dh, omega, nngb, c->counters, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
@@ -762,13 +871,15 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   c->last_stream = s;
   Octree &o = t->gas;
   const Tuning tu = tuning_for(c, kTuneHydro, active ? std::min<int64_t>(n_act, o.n) : o.n);
-  const SphParams sp = sph_params(p, t, tu);
-  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
-  if (e == hipSuccess) e = refit_hmax(o, s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
+  const SphParams sp = sph_params(c, p, t, tu);
+  st = ensure_h64(c, t, o);
+  if (st) return st;
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
+  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
   e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force");
   c->err.clear();
@@ -947,7 +1058,7 @@ int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, con
           if (r != hipSuccess) return r;
           if (prepare_work(c, t, gas, t->iperm_gas, n_act, active, &wk, s, tu.split))
             return hipErrorUnknown;
-          return launch_density(gas, wk.gs, wk.max_groups, sph_params(p, t, tu), 1, hs, nullptr,
+          return launch_density(gas, wk.gs, wk.max_groups, sph_params(c, p, t, tu), 1, hs, nullptr,
                                 nullptr, nullptr, nullptr, c->counters, s);
         }, &ms);
         if (st) return finish(st);
@@ -960,7 +1071,9 @@ int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, con
   }
   // hydro, when its inputs are given
   if (gas.n > 0 && h && vel && u && rho && omega) {
-    const SphParams base = sph_params(p, t, Tuning());
+    const SphParams base = sph_params(c, p, t, Tuning());
+    st = ensure_h64(c, t, gas);
+    if (st) return finish(st);
     e = launch_hydro_prep(gas, vel, u, h, rho, omega, base.gamma, t->f64, s);
     if (e == hipSuccess) e = refit_hmax(gas, s);
     if (e != hipSuccess) return finish(hip_fail(c, e, "g3_autotune"));
@@ -976,7 +1089,7 @@ int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, con
         st = time_candidate(c, s, e0, e1, [&]() -> hipError_t {
           if (prepare_work(c, t, gas, t->iperm_gas, n_act, active, &wk, s, tu.split))
             return hipErrorUnknown;
-          return launch_hydro(gas, wk.gs, wk.max_groups, sph_params(p, t, tu), nullptr, nullptr,
+          return launch_hydro(gas, wk.gs, wk.max_groups, sph_params(c, p, t, tu), nullptr, nullptr,
                               nullptr, nullptr, s);
         }, &ms);
         if (st) return finish(st);
@@ -1035,12 +1148,12 @@ int g3_density_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *act
   c->last_stream = s;
   Octree &o = t->gas;
   if (o.n == 0) return G3_OK;
-  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
-  if (e == hipSuccess) e = refit_hmax(o, s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_density_backward prep");
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
   if (st) return st;
+  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_backward prep");
   e = launch_density_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active, h, rho,
                          drho_dh, g_rho, g_drho_dh, g_omega, g_pos, g_mass, g_h, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density_backward");
@@ -1066,12 +1179,12 @@ int g3_density_solve_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_
   c->last_stream = s;
   Octree &o = t->gas;
   if (o.n == 0) return G3_OK;
-  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
-  if (e == hipSuccess) e = refit_hmax(o, s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_density_solve_backward prep");
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
   if (st) return st;
+  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_density_solve_backward prep");
   e = launch_density_solve_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active,
                                (float)p->n_ngb, h, rho, drho_dh, g_h, g_pos, g_mass, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density_solve_backward");
@@ -1099,15 +1212,15 @@ int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
   c->last_stream = s;
   Octree &o = t->gas;
   if (o.n == 0) return G3_OK;
-  const SphParams sp = sph_params(p, t, Tuning());
-  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, 0, s);
-  if (e == hipSuccess) e = refit_hmax(o, s);
-  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_backward prep");
+  const SphParams sp = sph_params(c, p, t, Tuning());
+  float4 *up = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));
+  if (!up) return fail(c, G3_ENOMEM, "g3_hydro_force_backward: scratch allocation failed");
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, o.n, nullptr, &wk, s);
   if (st) return st;
-  float4 *up = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));
-  if (!up) return fail(c, G3_ENOMEM, "g3_hydro_force_backward: scratch allocation failed");
+  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_backward prep");
   e = launch_hydro_bwd(o, t->iperm_gas, t->n, wk.gs, wk.max_groups, n_act, active, sp.alpha,
                        sp.gamma, u, omega, g_acc, g_dudt, up, g_pos, g_vel, g_mass, g_h, g_u,
                        g_rho, g_omega, s);
@@ -1131,15 +1244,15 @@ int g3_gravity_backward(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_
   c->last_stream = s;
   const Octree &o = t->all;
   if (o.n == 0) return G3_OK;
-  Work wk;
-  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
-  if (st) return st;
   float4 *gsrc = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));
   float4 *gnode = (float4 *)scratch(c, kAdjNode, o.nnodes * sizeof(float4));
   double4 *pq = (double4 *)scratch(c, kAdjPQ, o.nnodes * sizeof(double4));
   double *rr = (double *)scratch(c, kAdjR, o.nnodes * sizeof(double));
   if (!gsrc || !gnode || !pq || !rr)
     return fail(c, G3_ENOMEM, "g3_gravity_backward: scratch allocation failed");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
+  if (st) return st;
   hipError_t e = launch_gravity_bwd(o, wk.gs, wk.max_groups, grav_params(p, t), g_acc, g_pot,
                                     gsrc, gnode, pq, rr, g_pos, g_mass, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity_backward");

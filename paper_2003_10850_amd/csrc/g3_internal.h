@@ -87,6 +87,7 @@ struct g3_tree {
   int64_t cap_snap = 0;
   double max_side = 0;            // largest snapshot side
   int32_t leaf = 8;
+  bool built = false;  // false until a build has completed (a failed build leaves it false)
   int32_t f64 = 0;   // positions (and h) are FP64: the mixed-precision path
   float slack = 0;   // bound on the rounding of the FP32 position copies
   int32_t *iperm_all = nullptr;  // [n] caller id -> position in `all`
@@ -108,6 +109,10 @@ struct g3_ctx {
   unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
   int64_t *pinned = nullptr;               // host pinned readback slots [8]
   hipStream_t last_stream = nullptr;
+  // fault injection (g3_ctx_inject): device allocations left before every
+  // later one fails (-1: off), and the h solve's pass limit
+  int64_t alloc_budget = -1;
+  int max_iter = 64;
 };
 
 namespace g3 {
@@ -124,6 +129,11 @@ static_assert(kNumSlots <= (int)(sizeof(g3_ctx::scratch) / sizeof(g3_ctx::Buf)),
               "more scratch slots than the ctx holds");
 
 void *scratch(g3_ctx *c, int slot, size_t bytes);  // nullptr on failure
+
+// Device allocation on behalf of a ctx: hipMalloc, unless the ctx's
+// allocation-failure injection says this one fails (then *p = nullptr and
+// hipErrorOutOfMemory).
+hipError_t dev_malloc(g3_ctx *c, void **p, size_t bytes);
 
 // ---- launch wrappers (each returns hipGetLastError() of its launches) ----
 

@@ -737,14 +737,8 @@ hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, cons
                              hipStream_t s) {
   if (gas.n == 0) return hipSuccess;
   if (f64) {
-    if (!gas.h64 || gas.cap_h64 < gas.n) {
-      if (gas.h64) (void)hipFree(gas.h64);
-      gas.h64 = nullptr;
-      gas.cap_h64 = 0;
-      if (hipMalloc((void **)&gas.h64, gas.n * sizeof(double)) != hipSuccess)
-        return hipErrorOutOfMemory;
-      gas.cap_h64 = gas.n;
-    }
+    // the FP64 h copy is sized by the caller (ensure_h64) before any launch
+    if (!gas.h64 || gas.cap_h64 < gas.n) return hipErrorInvalidValue;
     k_hydro_prep<double><<<nblk(gas.n, 256), 256, 0, s>>>(
         gas.perm, gas.n, vel, u, (const double *)h, rho, omega, gamma, gas.vh,
         rho ? gas.aux : nullptr, gas.h64);

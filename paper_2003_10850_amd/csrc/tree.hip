@@ -322,21 +322,6 @@ __global__ void k_hmax_level(Node *__restrict__ nodes, int64_t nnodes,
   nodes[k].lo_h.w = hm;
 }
 
-template <typename T>
-bool grow(T **p, int64_t *cap, int64_t need) {
-  if (need <= *cap && *p) return true;
-  if (*p) (void)hipFree(*p);
-  *p = nullptr;
-  *cap = 0;
-  const int64_t n = need > 0 ? need : 1;
-  if (hipMalloc((void **)p, (size_t)n * sizeof(T)) != hipSuccess) {
-    *p = nullptr;
-    return false;
-  }
-  *cap = n;
-  return true;
-}
-
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -357,7 +342,7 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
     if (o.x64) (void)hipFree(o.x64);
     o.x64 = nullptr;
     o.cap_x64 = 0;
-    if (hipMalloc((void **)&o.x64, m * sizeof(double4)) != hipSuccess) {
+    if (dev_malloc(c, (void **)&o.x64, m * sizeof(double4)) != hipSuccess) {
       c->err = "device allocation of the FP64 positions failed";
       return G3_ENOMEM;
     }
@@ -369,11 +354,11 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
       if (p) (void)hipFree(p);
     o.keys = nullptr; o.perm = nullptr; o.xm = nullptr; o.vh = nullptr; o.aux = nullptr;
     o.cap_n = 0;
-    if (hipMalloc((void **)&o.keys, m * sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void **)&o.perm, m * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void **)&o.xm, m * sizeof(float4)) != hipSuccess ||
-        hipMalloc((void **)&o.vh, m * sizeof(float4)) != hipSuccess ||
-        hipMalloc((void **)&o.aux, m * sizeof(float4)) != hipSuccess) {
+    if (dev_malloc(c, (void **)&o.keys, m * sizeof(uint64_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&o.perm, m * sizeof(int32_t)) != hipSuccess ||
+        dev_malloc(c, (void **)&o.xm, m * sizeof(float4)) != hipSuccess ||
+        dev_malloc(c, (void **)&o.vh, m * sizeof(float4)) != hipSuccess ||
+        dev_malloc(c, (void **)&o.aux, m * sizeof(float4)) != hipSuccess) {
       c->err = "device allocation of the sorted particle arrays failed";
       return G3_ENOMEM;
     }
@@ -461,8 +446,8 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
     if (o.mom) (void)hipFree(o.mom);
     o.nodes = nullptr; o.mom = nullptr; o.cap_nodes = 0;
     const int64_t cap = nnodes + nnodes / 8 + 64;
-    if (hipMalloc((void **)&o.nodes, cap * sizeof(Node)) != hipSuccess ||
-        hipMalloc((void **)&o.mom, cap * sizeof(double4)) != hipSuccess) {
+    if (dev_malloc(c, (void **)&o.nodes, cap * sizeof(Node)) != hipSuccess ||
+        dev_malloc(c, (void **)&o.mom, cap * sizeof(double4)) != hipSuccess) {
       c->err = "device allocation of the octree nodes failed";
       return G3_ENOMEM;
     }
@@ -473,7 +458,7 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
     o.c64 = nullptr;
     o.cap_c64 = 0;
     const int64_t cap = nnodes + nnodes / 8 + 64;
-    if (hipMalloc((void **)&o.c64, cap * sizeof(double4)) != hipSuccess) {
+    if (dev_malloc(c, (void **)&o.c64, cap * sizeof(double4)) != hipSuccess) {
       c->err = "device allocation of the FP64 node centres failed";
       return G3_ENOMEM;
     }

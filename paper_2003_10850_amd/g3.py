@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
                 -4: "G3_EOVERFLOW", -5: "G3_ENOCONV", -6: "G3_ESTATE"}
 
 # every symbol include/g3.h declares
-EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
+EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats", "g3_ctx_inject",
            "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
            "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
@@ -68,6 +68,7 @@ def lib():
             "g3_ctx_destroy": ([P], None),
             "g3_last_error": ([P], ctypes.c_char_p),
             "g3_ctx_stats": ([P, P, i32], ctypes.c_int),
+            "g3_ctx_inject": ([P, i32, i64], ctypes.c_int),
             "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_build_forest": ([P, i32, P, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_refit_tree": ([P, P, P, P, P], ctypes.c_int),
@@ -119,10 +120,25 @@ def _check(ctx, st, name, ok=(G3_OK,)):
 
 
 def g3_ctx_stats(ctx: int, reset: bool = False):
-    """(non-converged particles, walk passes summed over waves, waves)."""
+    """(non-converged particles, walk passes summed over waves, waves); the
+    library's G3_ENOCONV (some solve did not converge) is not an error here:
+    the first count says it."""
+    return g3_ctx_stats_status(ctx, reset)[1]
+
+
+def g3_ctx_stats_status(ctx: int, reset: bool = False):
+    """(status, stats) with the raw status: G3_OK or G3_ENOCONV."""
     c = (ctypes.c_int64 * 4)()
-    _check(ctx, lib().g3_ctx_stats(ctx, c, int(reset)), "g3_ctx_stats")
-    return int(c[0]), int(c[1]), int(c[2])
+    st = _check(ctx, lib().g3_ctx_stats(ctx, c, int(reset)), "g3_ctx_stats",
+                ok=(G3_OK, G3_ENOCONV))
+    return st, (int(c[0]), int(c[1]), int(c[2]))
+
+
+G3_INJECT_ALLOC, G3_INJECT_MAX_ITER = 1, 2
+
+
+def g3_ctx_inject(ctx: int, what: int, value: int) -> None:
+    _check(ctx, lib().g3_ctx_inject(ctx, int(what), int(value)), "g3_ctx_inject")
 
 
 def g3_build_tree(ctx, n, pos_t, pos, mass, type_, box, params, tree, stream) -> int:
