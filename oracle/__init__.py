@@ -71,6 +71,8 @@ def lib():
         L.g3ref_tree_build.restype = P
         L.g3ref_tree_free.argtypes = [P]
         L.g3ref_tree_free.restype = None
+        L.g3ref_tree_refit.argtypes = [P, P, P]
+        L.g3ref_tree_refit.restype = ctypes.c_int
         L.g3ref_tree_nnodes.argtypes = [P]
         L.g3ref_tree_nnodes.restype = i64
         L.g3ref_tree_nmembers.argtypes = [P]
@@ -145,6 +147,17 @@ class Tree:
         L = _lib
         if h and L is not None:
             L.g3ref_tree_free(h)
+
+    def refit(self, pos, mass) -> "Tree":
+        """Drift update: new positions and masses, the build's topology and
+        cells kept, node moments and bounding boxes recomputed."""
+        self.pos = _f64(pos, (-1, 3)).copy()
+        self.mass = _f64(mass).copy()
+        if self.pos.shape[0] != self.n or self.mass.shape[0] != self.n:
+            raise ValueError("refit needs the tree's particle count")
+        if lib().g3ref_tree_refit(self._h, _ptr(self.pos), _ptr(self.mass)) != OK:
+            raise ValueError("g3ref_tree_refit rejected its arguments")
+        return self
 
     @property
     def nnodes(self) -> int:

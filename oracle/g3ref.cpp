@@ -95,6 +95,7 @@ struct RefNode {
   double l = 0.0;                  /* cube side */
   double clo[3] = {0, 0, 0};       /* cube lower corner */
   double M = 0.0, com[3] = {0, 0, 0};
+  double blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0}; /* members' bounding box */
   std::vector<int64_t> child;      /* preorder indices, Morton order */
 };
 
@@ -150,31 +151,58 @@ int64_t subdivide(g3ref_tree &t, int64_t s, int64_t e, int32_t level) {
   return idx;
 }
 
+/* Monopole moments in FP64 (M = sum m, com = sum m x / M) and the members'
+ * bounding box of every node. */
+void node_moments(g3ref_tree &t) {
+  for (RefNode &nd : t.nodes) {
+    double M = 0.0, S[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+      nd.blo[a] = INFINITY;
+      nd.bhi[a] = -INFINITY;
+    }
+    for (int64_t k = nd.start; k < nd.start + nd.count; ++k) {
+      const int64_t j = t.order[k];
+      M += t.mass[j];
+      for (int a = 0; a < 3; ++a) {
+        const double x = t.pos[3 * j + a];
+        S[a] += t.mass[j] * x;
+        nd.blo[a] = std::min(nd.blo[a], x);
+        nd.bhi[a] = std::max(nd.bhi[a], x);
+      }
+    }
+    nd.M = M;
+    for (int a = 0; a < 3; ++a) nd.com[a] = M > 0.0 ? S[a] / M : nd.clo[a] + 0.5 * nd.l;
+  }
+}
+
 bool inside_cube(const g3ref_tree &t, int64_t i, const RefNode &nd) {
   const int sh = kMaxLevel - nd.level;
   return (t.cell[3 * i + 0] >> sh) == nd.cx && (t.cell[3 * i + 1] >> sh) == nd.cy &&
          (t.cell[3 * i + 2] >> sh) == nd.cz;
 }
 
-/* squared distance from x to the node's cube (0 inside) */
-double cube_dist2(const RefNode &nd, const double *x) {
+/* squared distance from x to the bounding box of the node's members (0
+ * inside); after a refit the members may have left the node's cube, the
+ * box always holds them */
+double box_dist2(const RefNode &nd, const double *x) {
   double d2 = 0.0;
   for (int a = 0; a < 3; ++a) {
-    double lo = nd.clo[a], hi = nd.clo[a] + nd.l, d = 0.0;
-    if (x[a] < lo) d = lo - x[a];
-    else if (x[a] > hi) d = x[a] - hi;
+    double d = 0.0;
+    if (x[a] < nd.blo[a]) d = nd.blo[a] - x[a];
+    else if (x[a] > nd.bhi[a]) d = x[a] - nd.bhi[a];
     d2 += d * d;
   }
   return d2;
 }
 
-/* Collect members j of leaves whose cube lies within radius R(node) of x
- * (R may depend on the node, e.g. the symmetric search). Pruning only. */
+/* Collect members j of leaves whose bounding box lies within radius
+ * R(node) of x (R may depend on the node, e.g. the symmetric search).
+ * Pruning only: it never drops a member within R. */
 template <class Radius, class Visit>
 void walk_leaves(const g3ref_tree &t, int64_t k, const double *x, Radius R, Visit visit) {
   const RefNode &nd = t.nodes[k];
   const double r = R(k);
-  if (cube_dist2(nd, x) > r * r) return;
+  if (box_dist2(nd, x) > r * r) return;
   if (nd.child.empty()) {
     for (int64_t s = nd.start; s < nd.start + nd.count; ++s) visit(t.order[s]);
     return;
@@ -320,18 +348,19 @@ g3ref_tree *g3ref_tree_build(int64_t n, const double *pos, const double *mass,
   });
   for (int64_t i : t->order) t->keys.push_back(key[i]);
   if (!t->order.empty()) subdivide(*t, 0, (int64_t)t->order.size(), 0);
-  /* monopole moments in FP64: M = sum m, com = sum m x / M */
-  for (RefNode &nd : t->nodes) {
-    double M = 0.0, S[3] = {0, 0, 0};
-    for (int64_t k = nd.start; k < nd.start + nd.count; ++k) {
-      const int64_t j = t->order[k];
-      M += t->mass[j];
-      for (int a = 0; a < 3; ++a) S[a] += t->mass[j] * t->pos[3 * j + a];
-    }
-    nd.M = M;
-    for (int a = 0; a < 3; ++a) nd.com[a] = M > 0.0 ? S[a] / M : nd.clo[a] + 0.5 * nd.l;
-  }
+  node_moments(*t);
   return t;
+}
+
+/* A drift update of a built tree: the members' new positions and masses
+ * are taken; order, keys, cells, topology and node cubes stay those of the
+ * build; moments and bounding boxes are recomputed. */
+int g3ref_tree_refit(g3ref_tree *t, const double *pos, const double *mass) {
+  if (!t || (t->n > 0 && (!pos || !mass))) return G3REF_EINVAL;
+  t->pos.assign(pos, pos + 3 * t->n);
+  t->mass.assign(mass, mass + t->n);
+  node_moments(*t);
+  return G3REF_OK;
 }
 
 void g3ref_tree_free(g3ref_tree *t) { delete t; }

@@ -70,6 +70,11 @@ g3ref_tree *g3ref_tree_build(int64_t n, const double *pos, const double *mass,
                              const uint8_t *type, const double *box,
                              int32_t leaf_size, int32_t gas_only);
 void g3ref_tree_free(g3ref_tree *t);
+/* Drift update (the refit of the time integration, paper section 1: tree
+ * nodes are drifted rather than rebuilt): take new positions [n][3] and
+ * masses [n]; keep the build's member order, keys, cells, topology and node
+ * cubes; recompute the node moments and the members' bounding boxes. */
+int g3ref_tree_refit(g3ref_tree *t, const double *pos, const double *mass);
 int64_t g3ref_tree_nnodes(const g3ref_tree *t);
 int64_t g3ref_tree_nmembers(const g3ref_tree *t);
 /* Any output pointer may be NULL. order/keys: [nmembers]; node arrays:

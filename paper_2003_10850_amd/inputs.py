@@ -142,6 +142,42 @@ def plummer(n: int = 1 << 21, n_spheres: int = 32, seed: int = 1,
     return w
 
 
+def plummer_equilibrium(n: int = 2048, scale_radius: float = 0.04, r_max: float = 0.45,
+                        seed: int = 5, gas_fraction: float = 0.0, eps: float | None = None,
+                        n_ngb: float = 64.0) -> Workload:
+    """One Plummer sphere of total mass 1 (G = 1) centred in the unit box,
+    drawn in dynamical equilibrium: radii by the inverse mass profile and
+    speeds from the isotropic distribution function by rejection on
+    g(q) = q^2 (1 - q^2)^(7/2), q = v / v_esc(r), v_esc^2 = 2 / sqrt(r^2 + a^2)
+    (the sampling recipe of Aarseth, Henon & Wielen 1974). Radii beyond
+    r_max are redrawn. A fraction of the particles (chosen at random) is gas
+    with u = 1/100 of the central potential depth; the rest is
+    collisionless."""
+    rng = np.random.default_rng(seed)
+    a = scale_radius
+    r = np.empty(0)
+    while r.size < n:
+        rr = _plummer_radii(rng, a, n)
+        r = np.concatenate([r, rr[rr < r_max]])
+    r = r[:n]
+    q = np.empty(0)
+    while q.size < n:
+        x4, x5 = rng.random(2 * n), rng.random(2 * n)
+        keep = 0.1 * x5 < x4 ** 2 * (1.0 - x4 ** 2) ** 3.5
+        q = np.concatenate([q, x4[keep]])
+    q = q[:n]
+    vesc = np.sqrt(2.0) * (r * r + a * a) ** -0.25
+    pos = 0.5 + r[:, None] * _directions(rng, n)
+    vel = (q * vesc)[:, None] * _directions(rng, n)
+    typ = np.full(n, COLLISIONLESS, np.uint8)
+    typ[rng.permutation(n)[: int(round(gas_fraction * n))]] = GAS
+    return Workload(
+        name=f"plummer_eq_n{n}_a{a}_seed{seed}", pos=pos, vel=vel,
+        mass=np.full(n, 1.0 / n), u=np.full(n, 0.01 / a), type=typ,
+        box=np.array([0.0, 0.0, 0.0, 1.0]),
+        params=Params(n_ngb=n_ngb, eps=a / 20.0 if eps is None else eps), seed=seed)
+
+
 @dataclass
 class Batch:
     """Snapshots concatenated in caller order: snapshot k is the rows
