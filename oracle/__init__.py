@@ -63,6 +63,8 @@ def lib():
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.g3ref_threads.argtypes = []
         L.g3ref_threads.restype = i32
+        L.g3ref_set_threads.argtypes = [i32]
+        L.g3ref_set_threads.restype = None
         L.g3ref_kernel.argtypes = [dbl, dbl, P, P, P, P]
         L.g3ref_kernel.restype = None
         L.g3ref_key.argtypes = [P, P]
@@ -84,6 +86,13 @@ def lib():
         L.g3ref_hydro.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.g3ref_hydro.restype = ctypes.c_int
         L.g3ref_gravity.argtypes = [P, i64, P, P, P, P, P, P]
+        L.g3ref_hydro_switches.restype = ctypes.c_int
+        L.g3ref_hydro_switches.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, dbl, P, P, P, P, P,
+                                           P]
+        L.g3ref_velgrad.restype = ctypes.c_int
+        L.g3ref_velgrad.argtypes = [P, i64, P, P, P, P, P, P, P, P, P, P]
+        L.g3ref_conduction.restype = ctypes.c_int
+        L.g3ref_conduction.argtypes = [P, i64, P, P, dbl, dbl, P, P, P, P, P, P]
         L.g3ref_gravity.restype = ctypes.c_int
         L.g3ref_lists.argtypes = [P, i32, i64, P, P, P, P, P]
         L.g3ref_lists.restype = ctypes.c_int
@@ -111,6 +120,11 @@ def _f64(a, shape=None):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().g3ref_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's parallel loops."""
+    lib().g3ref_set_threads(int(n))
 
 
 def kernel(r: float, h: float):
@@ -213,6 +227,87 @@ def hydro(tree: Tree, params, vel, u, h, rho, omega, active=None) -> dict:
                            *[_ptr(out[k]) for k in ("acc", "dudt", "vsig", "S", "npairs")])
     if st != OK:
         raise ValueError(f"g3ref_hydro status {st}")
+    return out
+
+
+def hydro_switches(tree: Tree, params, vel, u, h, rho, omega, alpha=None, balsara=None,
+                   alpha_u: float = 0.0, active=None) -> dict:
+    """The hydro force with per-particle viscosity strengths and Balsara
+    factors (None: params.alpha and 1) and artificial conduction alpha_u;
+    see g3ref_hydro_switches."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(acc=np.zeros((n, 3)), dudt=np.zeros(n), vsig=np.zeros(n), S=np.zeros(n),
+               npairs=np.zeros(n, np.int32), S_du=np.zeros(n))
+    ins = [_f64(vel, (-1, 3)), _f64(u), _f64(h), _f64(rho), _f64(omega)]
+    al = None if alpha is None else _f64(alpha)
+    bf = None if balsara is None else _f64(balsara)
+    p = Params.of(params)
+    st = lib().g3ref_hydro_switches(tree._h, act.size, _ptr(act), ctypes.byref(p),
+                                    *[_ptr(a) for a in ins], _ptr(al), _ptr(bf), float(alpha_u),
+                                    *[_ptr(out[k]) for k in ("acc", "dudt", "vsig", "S",
+                                                             "npairs", "S_du")])
+    if st != OK:
+        raise ValueError(f"g3ref_hydro_switches status {st}")
+    return out
+
+
+def balsara(div_v, curl_v, u, h, gamma: float, eps: float = 1e-4):
+    """The Balsara (1995) factor f = |div v| / (|div v| + |curl v| + eps c / h),
+    c = sqrt(gamma (gamma - 1) u): near 1 in compression, near 0 in shear."""
+    d = np.abs(_f64(div_v))
+    c = np.sqrt(gamma * (gamma - 1.0) * np.maximum(_f64(u), 0.0))
+    cv = np.linalg.norm(_f64(curl_v, (-1, 3)), axis=1)
+    return d / (d + cv + eps * c / _f64(h))
+
+
+def alpha_step(alpha, dt, div_v, f, u, h, gamma: float, alpha_min: float, alpha_max: float,
+               decay: float):
+    """One step dt of the time-dependent viscosity strength (Morris &
+    Monaghan 1997, with the (alpha_max - alpha) source factor of Rosswog et
+    al. 2000 and the Balsara factor f in the source):
+        d alpha / dt = -(alpha - alpha_min) / tau + s (alpha_max - alpha),
+        tau = h / (decay c),  s = f max(-div v, 0),
+    integrated exactly over the step for inputs held fixed: the equation is
+    linear in alpha, so alpha relaxes to alpha_inf = (alpha_min/tau + s
+    alpha_max) / (1/tau + s) at the rate 1/tau + s."""
+    c = np.sqrt(gamma * (gamma - 1.0) * np.maximum(_f64(u), 0.0))
+    rate_decay = decay * c / _f64(h)
+    s = _f64(f) * np.maximum(-_f64(div_v), 0.0)
+    k = rate_decay + s
+    with np.errstate(invalid="ignore", divide="ignore"):
+        a_inf = np.where(k > 0, (alpha_min * rate_decay + s * alpha_max) / k, _f64(alpha))
+    return a_inf + (_f64(alpha) - a_inf) * np.exp(-k * dt)
+
+
+def velgrad(tree: Tree, params, vel, h, rho, omega, active=None) -> dict:
+    """Velocity divergence and curl (grad-h SPH estimates); see g3ref_velgrad."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(div=np.zeros(n), curl=np.zeros((n, 3)), S_div=np.zeros(n), S_curl=np.zeros(n))
+    p = Params.of(params)
+    st = lib().g3ref_velgrad(tree._h, act.size, _ptr(act), ctypes.byref(p),
+                             _ptr(_f64(vel, (-1, 3))), _ptr(_f64(h)), _ptr(_f64(rho)),
+                             _ptr(_f64(omega)),
+                             *[_ptr(out[k]) for k in ("div", "curl", "S_div", "S_curl")])
+    if st != OK:
+        raise ValueError(f"g3ref_velgrad status {st}")
+    return out
+
+
+def conduction(tree: Tree, params, u, h, rho, kappa0: float, kappa_exp: float = 0.0,
+               active=None) -> dict:
+    """du/dt of thermal conduction (Brookshaw 1985; Jubelgas, Springel & Dolag
+    2004) with kappa = kappa0 u^kappa_exp; see g3ref_conduction."""
+    act = _active(tree.n, active)
+    n = tree.n
+    out = dict(dudt=np.zeros(n), S=np.zeros(n), npairs=np.zeros(n, np.int32))
+    p = Params.of(params)
+    st = lib().g3ref_conduction(tree._h, act.size, _ptr(act), ctypes.byref(p), float(kappa0),
+                                float(kappa_exp), _ptr(_f64(u)), _ptr(_f64(h)), _ptr(_f64(rho)),
+                                *[_ptr(out[k]) for k in ("dudt", "S", "npairs")])
+    if st != OK:
+        raise ValueError(f"g3ref_conduction status {st}")
     return out
 
 

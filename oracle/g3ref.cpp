@@ -311,6 +311,14 @@ int32_t g3ref_threads(void) {
 #endif
 }
 
+void g3ref_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void g3ref_kernel(double r, double h, double *W, double *dWdr, double *dWdh, double *F) {
   wc6(r, h, W, dWdr, dWdh, F);
 }
@@ -449,13 +457,25 @@ int g3ref_density(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
  *        Pi = -(alpha/2) v_sig w / ((rho_i + rho_j)/2)    else Pi = 0
  *   a_i   -= m_j Pi gbar x_ij
  *   du_i  += m_j A_i g_i v_ij.x_ij + (1/2) m_j Pi gbar v_ij.x_ij
- *   vsig_i = max_j (c_i + c_j - 3 min(w, 0))   (0 with no pair) */
-int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
-                const g3ref_params *p, const double *vel, const double *u, const double *h,
-                const double *rho, const double *omega, double *acc, double *dudt,
-                double *vsig, double *S, int32_t *npairs) {
+ *   vsig_i = max_j (c_i + c_j - 3 min(w, 0))   (0 with no pair)
+ * The switches of the improved SPH that Gadget3 ran (Beck et al. 2016), each
+ * a published method, change only the viscosity and add a conduction term:
+ *   - per-particle viscosity strengths alpha_i (a time-dependent viscosity,
+ *     Morris & Monaghan 1997) and Balsara (1995) factors f_i enter as
+ *     alpha -> (alpha_i + alpha_j)/2 * (f_i + f_j)/2 in Pi (alpha_arr and
+ *     balsara nullable: p->alpha and 1);
+ *   - artificial conduction of the internal energy (Price 2008, eq. 28, with
+ *     the pressure-difference signal speed):
+ *       du_i += m_j alpha_u v_u (u_i - u_j) gbar r / rhobar,
+ *       v_u = sqrt(|P_i - P_j| / rhobar), rhobar = (rho_i + rho_j)/2
+ *     (alpha_u = 0: none). */
+static int hydro_general(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                  const g3ref_params *p, const double *vel, const double *u, const double *h,
+                  const double *rho, const double *omega, const double *alpha_arr,
+                  const double *balsara, double alpha_u, double *acc, double *dudt,
+                  double *vsig, double *S, int32_t *npairs, double *S_du) {
   if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !vel || !u ||
-      !h || !rho || !omega)
+      !h || !rho || !omega || !std::isfinite(alpha_u) || alpha_u < 0.0)
     return G3REF_EINVAL;
   const g3ref_tree &t = *gas;
   const double gm = p->gamma;
@@ -464,18 +484,18 @@ int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
   for (size_t k = 0; k < t.nodes.size(); ++k)
     for (int64_t s = t.nodes[k].start; s < t.nodes[k].start + t.nodes[k].count; ++s)
       hmax[k] = std::max(hmax[k], h[t.order[s]]);
-  auto A_of = [&](int64_t j) {
-    const double P = (gm - 1.0) * rho[j] * u[j];
-    return P / (omega[j] * rho[j] * rho[j]);
-  };
+  auto P_of = [&](int64_t j) { return (gm - 1.0) * rho[j] * u[j]; };
+  auto A_of = [&](int64_t j) { return P_of(j) / (omega[j] * rho[j] * rho[j]); };
   auto c_of = [&](int64_t j) { return std::sqrt(gm * (gm - 1.0) * u[j]); };
+  auto alpha_of = [&](int64_t j) { return alpha_arr ? alpha_arr[j] : p->alpha; };
+  auto f_of = [&](int64_t j) { return balsara ? balsara[j] : 1.0; };
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t a = 0; a < n_act; ++a) {
     const int64_t i = active[a];
     if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
     const double *xi = &t.pos[3 * i];
     const double Ai = A_of(i), ci = c_of(i), hi = h[i];
-    double ax = 0, ay = 0, az = 0, du = 0, vs = 0, s = 0;
+    double ax = 0, ay = 0, az = 0, du = 0, vs = 0, s = 0, sdu = 0;
     int32_t cnt = 0;
     walk_leaves(t, 0, xi, [&](int64_t k) { return std::max(hi, hmax[k]) * kPruneMargin; },
                 [&](int64_t j) {
@@ -495,10 +515,13 @@ int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
       const double Aj = A_of(j), cj = c_of(j), mj = t.mass[j];
       const double vx = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
       const double w = vx / r;
+      const double rhobar = 0.5 * (rho[i] + rho[j]);
+      double du_pair = 0.0;
       double Pi = 0.0;
       if (w < 0.0) {
         const double vsig_ij = ci + cj - 3.0 * w;
-        Pi = -0.5 * p->alpha * vsig_ij * w / (0.5 * (rho[i] + rho[j]));
+        const double alpha_ij = 0.5 * (alpha_of(i) + alpha_of(j)) * 0.5 * (f_of(i) + f_of(j));
+        Pi = -0.5 * alpha_ij * vsig_ij * w / rhobar;
       }
       vs = std::max(vs, ci + cj - 3.0 * std::min(w, 0.0));
       const double gbar = 0.5 * (gi + gj);
@@ -507,7 +530,15 @@ int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
       ax += (tp + tv) * x[0];
       ay += (tp + tv) * x[1];
       az += (tp + tv) * x[2];
-      du += mj * Ai * gi * vx + 0.5 * mj * Pi * gbar * vx;
+      du_pair = mj * Ai * gi * vx + 0.5 * mj * Pi * gbar * vx;
+      sdu += std::fabs(mj * Ai * gi * vx) + std::fabs(0.5 * mj * Pi * gbar * vx);
+      if (alpha_u > 0.0) {
+        const double vu = std::sqrt(std::fabs(P_of(i) - P_of(j)) / rhobar);
+        const double cond = mj * alpha_u * vu * (u[i] - u[j]) * gbar * r / rhobar;
+        du_pair += cond;
+        sdu += std::fabs(cond);
+      }
+      du += du_pair;
       s += (std::fabs(tp) + std::fabs(tv)) * r;
     });
     if (acc) {
@@ -517,6 +548,138 @@ int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
     }
     if (dudt) dudt[i] = du;
     if (vsig) vsig[i] = vs;
+    if (S) S[i] = s;
+    if (npairs) npairs[i] = cnt;
+    if (S_du) S_du[i] = sdu;
+  }
+  return G3REF_OK;
+}
+
+int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                const g3ref_params *p, const double *vel, const double *u, const double *h,
+                const double *rho, const double *omega, double *acc, double *dudt,
+                double *vsig, double *S, int32_t *npairs) {
+  return hydro_general(gas, n_act, active, p, vel, u, h, rho, omega, nullptr, nullptr, 0.0, acc,
+                       dudt, vsig, S, npairs, nullptr);
+}
+
+int g3ref_hydro_switches(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                         const g3ref_params *p, const double *vel, const double *u,
+                         const double *h, const double *rho, const double *omega,
+                         const double *alpha, const double *balsara, double alpha_u,
+                         double *acc, double *dudt, double *vsig, double *S, int32_t *npairs,
+                         double *S_du) {
+  return hydro_general(gas, n_act, active, p, vel, u, h, rho, omega, alpha, balsara, alpha_u,
+                       acc, dudt, vsig, S, npairs, S_du);
+}
+
+/* Velocity divergence and curl of the active gas particles: the grad-h SPH
+ * estimates (as the Balsara 1995 and Cullen & Dehnen 2010 switches take
+ * them; Price 2012, eqs. 103-104):
+ *   div v_i  =  (1/(Omega_i rho_i)) sum_j m_j (v_j - v_i) . grad_i W(r_ij, h_i)
+ *   curl v_i = -(1/(Omega_i rho_i)) sum_j m_j (v_j - v_i) x grad_i W(r_ij, h_i)
+ * with grad_i W = F(r, h_i) (x_i - x_j), over gas j with r < h_i (the
+ * density's pairs; the self pair adds nothing). Outputs div_v [n] and
+ * curl_v [n][3] at the active rows; S_div (nullable) the sum of the
+ * magnitudes of the divergence's terms, S_curl (nullable) of the curl's. */
+int g3ref_velgrad(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                  const g3ref_params *p, const double *vel, const double *h, const double *rho,
+                  const double *omega, double *div_v, double *curl_v, double *S_div,
+                  double *S_curl) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !vel || !h || !rho ||
+      !omega)
+    return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    const double *xi = &t.pos[3 * i];
+    const double hi = h[i];
+    double dv = 0, cx = 0, cy = 0, cz = 0, sd = 0, sc = 0;
+    walk_leaves(t, 0, xi, [&](int64_t) { return hi * kPruneMargin; }, [&](int64_t j) {
+      if (j == i || !is_gas(t, j)) return;
+      if (!within(t, i, j, hi, p->flags)) return;
+      const double r = dist(t, i, j);
+      if (!(r > 0.0)) return;
+      double W, dWdr, dWdh, F;
+      wc6(r, hi, &W, &dWdr, &dWdh, &F);
+      const double mj = t.mass[j];
+      const double g[3] = {F * (xi[0] - t.pos[3 * j]), F * (xi[1] - t.pos[3 * j + 1]),
+                           F * (xi[2] - t.pos[3 * j + 2])};
+      const double d[3] = {vel[3 * j] - vel[3 * i], vel[3 * j + 1] - vel[3 * i + 1],
+                           vel[3 * j + 2] - vel[3 * i + 2]};
+      const double td = mj * (d[0] * g[0] + d[1] * g[1] + d[2] * g[2]);
+      const double c[3] = {-mj * (d[1] * g[2] - d[2] * g[1]), -mj * (d[2] * g[0] - d[0] * g[2]),
+                           -mj * (d[0] * g[1] - d[1] * g[0])};
+      dv += td;
+      cx += c[0];
+      cy += c[1];
+      cz += c[2];
+      sd += std::fabs(td);
+      sc += std::fabs(c[0]) + std::fabs(c[1]) + std::fabs(c[2]);
+    });
+    const double norm = 1.0 / (omega[i] * rho[i]);
+    if (div_v) div_v[i] = dv * norm;
+    if (curl_v) {
+      curl_v[3 * i] = cx * norm;
+      curl_v[3 * i + 1] = cy * norm;
+      curl_v[3 * i + 2] = cz * norm;
+    }
+    if (S_div) S_div[i] = sd * norm;
+    if (S_curl) S_curl[i] = sc * norm;
+  }
+  return G3REF_OK;
+}
+
+/* Thermal conduction of the active gas particles: the SPH form of
+ * rho du/dt = div(kappa grad u) of Brookshaw (1985), as Gadget's conduction
+ * module uses it (Jubelgas, Springel & Dolag 2004), with the conductivity in
+ * units of the internal energy per mass (the heat capacity absorbed) and a
+ * power law of it, kappa = kappa0 u^kappa_exp (kappa_exp = 5/2: Spitzer's
+ * temperature dependence, 0: constant):
+ *   du_i/dt = sum_j m_j (kappa_i + kappa_j) (u_i - u_j) Fbar_ij / (rho_i rho_j),
+ *   Fbar_ij = (F(r, h_i) + F(r, h_j)) / 2,  F = (1/r) dW/dr <= 0,
+ * over gas j != i with r < max(h_i, h_j) (the hydro force's pairs); pairs at
+ * zero separation add nothing. Each pair's exchange is antisymmetric, so
+ * sum_i m_i du_i/dt = 0 over a set that holds every pair of its members. */
+int g3ref_conduction(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                     const g3ref_params *p, double kappa0, double kappa_exp,
+                     const double *u, const double *h, const double *rho, double *dudt,
+                     double *S, int32_t *npairs) {
+  if (!gas || !valid_params(p) || n_act < 0 || (n_act > 0 && !active) || !u || !h || !rho ||
+      !std::isfinite(kappa0) || kappa0 < 0.0 || !std::isfinite(kappa_exp))
+    return G3REF_EINVAL;
+  const g3ref_tree &t = *gas;
+  std::vector<double> hmax(t.nodes.size(), 0.0);
+  for (size_t k = 0; k < t.nodes.size(); ++k)
+    for (int64_t s = t.nodes[k].start; s < t.nodes[k].start + t.nodes[k].count; ++s)
+      hmax[k] = std::max(hmax[k], h[t.order[s]]);
+  auto kappa = [&](int64_t j) { return kappa0 * std::pow(std::max(u[j], 0.0), kappa_exp); };
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < n_act; ++a) {
+    const int64_t i = active[a];
+    if (i < 0 || i >= t.n || !is_gas(t, i)) continue;
+    const double *xi = &t.pos[3 * i];
+    const double hi = h[i], ki = kappa(i);
+    double du = 0.0, s = 0.0;
+    int32_t cnt = 0;
+    walk_leaves(t, 0, xi, [&](int64_t k) { return std::max(hi, hmax[k]) * kPruneMargin; },
+                [&](int64_t j) {
+      if (j == i || !is_gas(t, j)) return;
+      if (!within(t, i, j, std::max(hi, h[j]), p->flags)) return;
+      ++cnt;
+      const double r = dist(t, i, j);
+      if (!(r > 0.0)) return;
+      double W, dWdr, dWdh, Fi, Fj;
+      wc6(r, hi, &W, &dWdr, &dWdh, &Fi);
+      wc6(r, h[j], &W, &dWdr, &dWdh, &Fj);
+      const double term = t.mass[j] * (ki + kappa(j)) * (u[i] - u[j]) * 0.5 * (Fi + Fj) /
+                          (rho[i] * rho[j]);
+      du += term;
+      s += std::fabs(term);
+    });
+    if (dudt) dudt[i] = du;
     if (S) S[i] = s;
     if (npairs) npairs[i] = cnt;
   }

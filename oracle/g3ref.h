@@ -54,8 +54,9 @@ enum { G3REF_GATHER = 0, G3REF_SYMMETRIC = 1, G3REF_GRAVITY = 2 };
 
 typedef struct g3ref_tree g3ref_tree;
 
-/* Number of OpenMP threads the parallel loops use. */
+/* Number of OpenMP threads the parallel loops use, and setting it (n > 0). */
 int32_t g3ref_threads(void);
+void g3ref_set_threads(int32_t n);
 
 /* Wendland C6 and its derivatives at (r, h): W, dW/dr, dW/dh, F = dW/dr / r. */
 void g3ref_kernel(double r, double h, double *W, double *dWdr, double *dWdh,
@@ -99,6 +100,33 @@ int g3ref_hydro(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
                 const double *h, const double *rho, const double *omega,
                 double *acc, double *dudt, double *vsig, double *S,
                 int32_t *npairs);
+
+/* The hydro force with the improved-SPH switches (Beck et al. 2016):
+ * per-particle viscosity strengths alpha [n] and Balsara factors balsara [n]
+ * (each nullable: params->alpha and 1) and artificial conduction of
+ * strength alpha_u (0: none). With all three off it is g3ref_hydro. S_du
+ * (nullable) receives the L1 sum of the du/dt terms. */
+int g3ref_hydro_switches(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                         const g3ref_params *p, const double *vel, const double *u,
+                         const double *h, const double *rho, const double *omega,
+                         const double *alpha, const double *balsara, double alpha_u,
+                         double *acc, double *dudt, double *vsig, double *S,
+                         int32_t *npairs, double *S_du);
+
+/* Velocity divergence [n] and curl [n][3] of the active gas particles (the
+ * grad-h SPH estimates over the density's pairs); S_div and S_curl (the L1
+ * sums of the terms) nullable. */
+int g3ref_velgrad(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                  const g3ref_params *p, const double *vel, const double *h,
+                  const double *rho, const double *omega, double *div_v,
+                  double *curl_v, double *S_div, double *S_curl);
+
+/* Thermal conduction rate of the active gas particles. S (L1 magnitude of
+ * the terms) and npairs may be NULL. kappa_j = kappa0 u_j^kappa_exp. */
+int g3ref_conduction(const g3ref_tree *gas, int64_t n_act, const int64_t *active,
+                     const g3ref_params *p, double kappa0, double kappa_exp,
+                     const double *u, const double *h, const double *rho,
+                     double *dudt, double *S, int32_t *npairs);
 
 /* Barnes-Hut gravity. S and nterms may be NULL. */
 int g3ref_gravity(const g3ref_tree *all, int64_t n_act, const int64_t *active,

@@ -51,6 +51,17 @@ class Params:
 
 
 @dataclass
+class SwitchParams:
+    """Parameters of the improved-SPH switches (plain numbers)."""
+    alpha_min: float = 0.025   # floor of the viscosity strength
+    alpha_max: float = 1.0     # ceiling of the viscosity strength
+    decay: float = 0.2         # l of the decay time h / (l c)
+    balsara_eps: float = 1e-4  # eps of the Balsara factor's c/h term
+    alpha_u: float = 1.0       # artificial conduction strength
+    flags: int = 0
+
+
+@dataclass
 class Workload:
     name: str
     pos: np.ndarray            # [N,3] float64 draws (cast per precision)
