@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 # algorithmic FP32 operations per interaction (an FMA counts 2), counted from
 # the formulas each kernel evaluates; sqrt, rsqrt and division count 1
 FLOP_DENSITY = 36   # rho and drho/dh of one pair in the support
-FLOP_HYDRO = 74     # pressure + viscosity acceleration, du/dt, signal speed
+FLOP_HYDRO = 90     # pressure + viscosity acceleration, du/dt, signal speed
 FLOP_GRAVITY = 20   # softened monopole or particle term, acc + potential
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 HBM_TBS = 8.0
@@ -70,12 +70,60 @@ def traffic_for(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(w, samples: int, seed: int = 0) -> dict:
-    """The FP64 oracle, as it stands, on this host: octree builds in full,
-    density (with the h bisection), hydro and gravity on random samples of
-    the active particles; each op's time is scaled by its sample fraction."""
+def _oracle_ops(gt, at, p, vel, u, fields, sd, sh, sg):
+    """One pass of the FP64 oracle over samples: density with the h
+    bisection on sd, hydro on sh at the given (h, rho, omega) fields,
+    gravity on sg. Returns (seconds per op, interactions per op, results)."""
     import oracle
-    from paper_2003_10850_amd import inputs
+    t0 = time.perf_counter()
+    d = oracle.density(gt, p, active=sd)
+    t_d = time.perf_counter() - t0
+    h, rho, om = fields
+    t0 = time.perf_counter()
+    hy = oracle.hydro(gt, p, vel, u, h, rho, om, active=sh)
+    t_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = oracle.gravity(at, p, active=sg)
+    t_g = time.perf_counter() - t0
+    inter = (float(d["nngb"][sd].sum()), float(hy["npairs"][sh].sum()),
+             float(g["nterms"][sg].sum()))
+    return (t_d, t_h, t_g), inter, (d, hy, g)
+
+
+def _errors(gt, p, gpu, sd, sh, sg, ref) -> dict:
+    """Errors of one GPU step against the oracle on the sampled rows: h
+    against the oracle's own solve; rho and the neighbour counts at the
+    GPU's h; hydro and gravity accelerations relative to the sum S of the
+    magnitudes of their terms; counts must be exact."""
+    import oracle
+    d, hy, g = ref
+    h = gpu["h"].astype(np.float64)
+    at_h = oracle.density(gt, p, active=sd, h=h, solve_h=False)
+    rel = lambda a, b: np.abs(a - b) / np.abs(b)
+    e = {
+        "h_rel": float(rel(h[sd], d["h"][sd]).max()),
+        "rho_rel": float(rel(gpu["rho"][sd], at_h["rho"][sd]).max()),
+        "hydro_acc_rel_S": float((np.linalg.norm(gpu["acc"][sh] - hy["acc"][sh], axis=1) /
+                                  hy["S"][sh]).max()),
+        "grav_acc_rel_S": float((np.linalg.norm(gpu["gacc"][sg] - g["acc"][sg], axis=1) /
+                                 g["S"][sg]).max()),
+        "counts_exact": bool(np.array_equal(gpu["nngb"][sd], at_h["nngb"][sd]) and
+                             np.array_equal(gpu["npairs"][sh], hy["npairs"][sh]) and
+                             np.array_equal(gpu["nterms"][sg], g["nterms"][sg])),
+        "samples": {"density": int(sd.size), "hydro": int(sh.size), "gravity": int(sg.size)},
+    }
+    return e
+
+
+def cpu_baseline(w, samples: int, gpu=None, seed: int = 0) -> dict:
+    """The FP64 oracle, as it stands, on this host: both octrees built in
+    full, then density (with the h bisection), hydro and gravity on random
+    samples of the active particles, each op's time scaled by its sample
+    fraction. On every host core: the median of three passes (each over a
+    third of the sample); on one thread: one pass over a sixteenth. With the
+    plain GPU step's outputs (gpu), also that step's errors on the first
+    pass's samples, the hydro evaluated at the GPU's h, rho and Omega."""
+    import oracle
 
     pos32, vel32, m32, u32 = w.as_f32()
     P, M = pos32.astype(np.float64), m32.astype(np.float64)
@@ -86,45 +134,136 @@ def cpu_baseline(w, samples: int, seed: int = 0) -> dict:
     gt = oracle.Tree(P, M, w.box, type=w.type, gas_only=True)
     at = oracle.Tree(P, M, w.box, type=w.type)
     t_build = time.perf_counter() - t0
+    if gpu is not None:
+        fields = (gpu["h"].astype(np.float64), gpu["rho"].astype(np.float64),
+                  gpu["omega"].astype(np.float64))
+    else:  # the generating model's smooth fields
+        from paper_2003_10850_amd import inputs
+        fields = (inputs.model_smoothing(w).astype(np.float32).astype(np.float64),
+                  inputs.model_gas_density(w).astype(np.float32).astype(np.float64),
+                  np.ones(w.n))
 
-    sd = rng.choice(gas, min(samples, gas.size), replace=False)
-    t0 = time.perf_counter()
-    d = oracle.density(gt, p, active=sd)
-    t_d = time.perf_counter() - t0
-    i_d = float(d["nngb"][sd].sum())
+    def draw(k):
+        return (np.sort(rng.choice(gas, min(k, gas.size), replace=False)),
+                np.sort(rng.choice(gas, min(k, gas.size), replace=False)),
+                np.sort(rng.choice(w.n, min(10 * k, w.n), replace=False)))
 
-    # hydro inputs: the generating model's smooth fields (no solve needed)
-    h = inputs.model_smoothing(w).astype(np.float32).astype(np.float64)
-    rho = inputs.model_gas_density(w).astype(np.float32).astype(np.float64)
-    sh = rng.choice(gas, min(samples, gas.size), replace=False)
-    t0 = time.perf_counter()
-    hy = oracle.hydro(gt, p, vel32, u32, h, rho, np.ones(w.n), active=sh)
-    t_h = time.perf_counter() - t0
-    i_h = float(hy["npairs"][sh].sum())
+    def rate(samp, times, inter):
+        fr = (samp[0].size / gas.size, samp[1].size / gas.size, samp[2].size / w.n)
+        t_full = t_build + sum(t / f for t, f in zip(times, fr))
+        return sum(i / f for i, f in zip(inter, fr)) / t_full, t_full
 
-    # gravity is the cheapest per target: ten times the sample
-    sg = rng.choice(w.n, min(10 * samples, w.n), replace=False)
-    t0 = time.perf_counter()
-    g = oracle.gravity(at, p, active=sg)
-    t_g = time.perf_counter() - t0
-    i_g = float(g["nterms"][sg].sum())
-
-    fd, fh, fg = sd.size / gas.size, sh.size / gas.size, sg.size / w.n
-    t_full = t_build + t_d / fd + t_h / fh + t_g / fg
-    i_full = i_d / fd + i_h / fh + i_g / fg
-    return {
-        "value": i_full / t_full,
+    passes, first = [], None
+    for _ in range(3):
+        samp = draw(max(samples // 3, 1))
+        times, inter, ref = _oracle_ops(gt, at, p, vel32, u32, fields, *samp)
+        passes.append(rate(samp, times, inter) + (times,))
+        if first is None:
+            first = (samp, ref)
+    order = sorted(range(3), key=lambda k: passes[k][0])
+    value, t_full, times = passes[order[1]]
+    cores = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        samp1 = draw(max(samples // 16, 1))
+        times1, inter1, _ = _oracle_ops(gt, at, p, vel32, u32, fields, *samp1)
+    finally:
+        oracle.set_threads(cores)
+    value1, t_full1 = rate(samp1, times1, inter1)
+    out = {
+        "value": value,
         "unit": "interactions/s",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"FP64 oracle on the same workload: both octrees built in full "
-                   f"({t_build:.2f} s); density with h bisection on {sd.size}, hydro on "
-                   f"{sh.size} gas and gravity on {sg.size} random particles "
-                   f"({t_d:.2f}/{t_h:.2f}/{t_g:.2f} s), each scaled by its sample "
-                   f"fraction; estimated full step {t_full:.1f} s"),
+                   f"({t_build:.2f} s); per pass density with h bisection on "
+                   f"{first[0][0].size}, hydro on {first[0][1].size} gas and gravity on "
+                   f"{first[0][2].size} random particles, each op scaled by its sample "
+                   f"fraction; median of 3 passes (median pass {times[0]:.2f}/{times[1]:.2f}/"
+                   f"{times[2]:.2f} s, estimated full step {t_full:.1f} s)"),
+        "one_thread": {"value": value1, "cores": 1,
+                       "sample": f"one pass over {samp1[0].size}/{samp1[1].size}/"
+                                 f"{samp1[2].size} samples, estimated full step "
+                                 f"{t_full1:.0f} s"},
         "cpu_model": _cpu_model(),
         "nproc": os.cpu_count(),
     }
+    if gpu is not None:
+        samp, ref = first
+        out["gpu_errors"] = _errors(gt, p, gpu, *samp, ref)
+    return out
+
+
+def batched_errors(check, n_pick: int = 4, per: int = 300, seed: int = 5) -> dict:
+    """Errors of the batched legs' last steps against the FP64 oracle: on
+    n_pick snapshots drawn at random (those with active gas), up to `per`
+    active gas particles (density, hydro) and active particles (gravity)
+    each; the FP32 forest with FP32 decisions, the mixed-precision forest
+    (FP64 positions) with FP64 decisions. The hydro is evaluated at the
+    step's own h, rho and Omega."""
+    import dataclasses
+    import oracle
+    b = check["batch"]
+    rng = np.random.default_rng(seed)
+    act = b.active.astype(np.int64)
+    cand = [k for k in range(b.n_snap)
+            if np.any(b.type[act[(act >= b.snap_off[k]) & (act < b.snap_off[k + 1])]] == 0)]
+    picks = sorted(rng.choice(cand, min(n_pick, len(cand)), replace=False).tolist())
+    out = {}
+    for leg, flags in (("fp32", 0), ("mixed", oracle.FLAG_FP64_DECISIONS)):
+        gpu = check[leg]
+        p = dataclasses.replace(b.params, flags=flags)
+        worst = {}
+        for k in picks:
+            r0, r1 = int(b.snap_off[k]), int(b.snap_off[k + 1])
+            a = act[(act >= r0) & (act < r1)] - r0
+            typ = b.type[r0:r1]
+            pos = b.pos[r0:r1] if flags else b.pos[r0:r1].astype(np.float32).astype(np.float64)
+            M = b.mass[r0:r1].astype(np.float32).astype(np.float64)
+            gt = oracle.Tree(pos, M, b.boxes[k], type=typ, gas_only=True)
+            at = oracle.Tree(pos, M, b.boxes[k], type=typ)
+            ag = a[typ[a] == 0]
+            sd = np.sort(rng.choice(ag, min(per, ag.size), replace=False))
+            sg = np.sort(rng.choice(a, min(per, a.size), replace=False))
+            g = {f: v[r0:r1] for f, v in gpu.items()}
+            fields = (g["h"].astype(np.float64), g["rho"].astype(np.float64),
+                      g["omega"].astype(np.float64))
+            _, _, ref = _oracle_ops(gt, at, p, b.vel[r0:r1].astype(np.float32),
+                                    b.u[r0:r1].astype(np.float32), fields, sd, sd, sg)
+            e = _errors(gt, p, g, sd, sd, sg, ref)
+            for f, v in e.items():
+                if f == "counts_exact":
+                    worst[f] = worst.get(f, True) and v
+                elif f == "samples":
+                    worst[f] = {x: worst.get(f, {}).get(x, 0) + y for x, y in v.items()}
+                else:
+                    worst[f] = max(worst.get(f, 0.0), v)
+        worst["snapshots"] = picks
+        out[leg] = worst
+    return out
+
+
+def precision_errors(check, k: int = 10_000, seed: int = 11) -> dict:
+    """Errors of the precision leg's last step against the FP64 oracle (FP64
+    decisions) on random subsamples of 1e4 gas (density, hydro) and 1e4
+    particles (gravity), over the full 2e7-particle trees."""
+    import dataclasses
+    import oracle
+    w = check["w"]
+    gpu = check["gpu"]
+    rng = np.random.default_rng(seed)
+    gas = np.nonzero(w.type == 0)[0]
+    sd = np.sort(rng.choice(gas, k, replace=False))
+    sg = np.sort(rng.choice(w.n, k, replace=False))
+    p = dataclasses.replace(w.params, flags=oracle.FLAG_FP64_DECISIONS)
+    M = w.mass.astype(np.float32).astype(np.float64)
+    gt = oracle.Tree(w.pos, M, w.box, type=w.type, gas_only=True)
+    at = oracle.Tree(w.pos, M, w.box, type=w.type)
+    fields = (gpu["h"].astype(np.float64), gpu["rho"].astype(np.float64),
+              gpu["omega"].astype(np.float64))
+    _, _, ref = _oracle_ops(gt, at, p, w.vel.astype(np.float32), w.u.astype(np.float32),
+                            fields, sd, sd, sg)
+    return _errors(gt, p, gpu, sd, sd, sg, ref)
 
 
 COPY_BYTES = 256 << 20  # the calibration copy: 256 MiB read + 256 MiB written
@@ -197,7 +336,15 @@ def step_roofline(counts, ms: float) -> dict:
             "frac": achieved / PEAK_FP32_TFLOPS}
 
 
-def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -> dict:
+def _host_outputs(o) -> dict:
+    """Host copies of one step's outputs, under the names the error
+    evaluation reads (gravity's acceleration as gacc)."""
+    names = {"h": "h", "rho": "rho", "omega": "omega", "nngb": "nngb", "acc": "acc",
+             "npairs": "npairs", "gacc": "gacc", "nterms": "nterms"}
+    return {k: o[v].detach().cpu().numpy() for k, v in names.items()}
+
+
+def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
     """The batching workload: a forest of n_snap Plummer snapshots (sizes
     log-uniform in [1e3, 1e6]) with time-bin active sets. One step = the
     interaction phase of the active particles of every snapshot (h solve and
@@ -236,13 +383,17 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
              acc=torch.zeros(n, 3, **f32), dudt=torch.zeros(n, **f32), vsig=torch.zeros(n, **f32),
              npairs=torch.zeros(n, **i32), gacc=torch.zeros(n, 3, **f32),
              pot=torch.zeros(n, **f32), nterms=torch.zeros(n, **i32))
+    # the carried fields of the inactive particles; the active ones are
+    # overwritten by every step's density, whose outputs the hydro reads
+    B["rho"].copy_(rho0)
+    B["omega"].copy_(om0)
     rho_in, om_in = rho0.clone(), om0.clone()
 
     def step():
         B["h"].copy_(h0)  # last step's h is the first guess of the solve
         ops.density(tree, active=act, out={k: B[k] for k in
                                            ("h", "rho", "drho_dh", "omega", "nngb")})
-        ops.hydro_force(tree, vel, u, B["h"], rho_in, om_in, active=act,
+        ops.hydro_force(tree, vel, u, B["h"], B["rho"], B["omega"], active=act,
                         out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
         ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
                                            "nterms": B["nterms"]})
@@ -287,6 +438,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     i_g = int(B["nterms"][act.long()].sum())
     inter = i_d + i_h + i_g
     nonconv = ctx.nonconverged(reset=True)
+    check = {"batch": b, "fp32": _host_outputs(B)}
     print(f"bench: batched graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms/step, "
           f"build {build_ms:.2f} ms; interactions {inter}", file=sys.stderr, flush=True)
 
@@ -294,12 +446,14 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     tree64 = ops.Tree(ctx, T(b.pos), mass, typ, boxes, b.params, snap_off=b.snap_off)
     h64 = h0.double()
     H64 = torch.zeros(n, dtype=torch.float64, device=dev)
+    B["rho"].copy_(rho0)
+    B["omega"].copy_(om0)
 
     def step64():
         H64.copy_(h64)
         ops.density(tree64, active=act, out={"h": H64, **{k: B[k] for k in
                                                          ("rho", "drho_dh", "omega", "nngb")}})
-        ops.hydro_force(tree64, vel, u, H64, rho_in, om_in, active=act,
+        ops.hydro_force(tree64, vel, u, H64, B["rho"], B["omega"], active=act,
                         out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
         ops.gravity(tree64, active=act, out={"acc": B["gacc"], "pot": B["pot"],
                                              "nterms": B["nterms"]})
@@ -315,6 +469,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     k64 = (int(B["nngb"][T(gas_act)].sum()), int(B["npairs"][T(gas_act)].sum()),
            int(B["nterms"][act.long()].sum()))
     i64 = sum(k64)
+    check["mixed"] = _host_outputs(dict(B, h=H64))
     tree64.close()
     ctx.nonconverged(reset=True)
     print(f"bench: batched mixed precision {mixed_ms:.3f} ms/step", file=sys.stderr, flush=True)
@@ -356,7 +511,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2) -
     for t in trees:
         t[0].close()
     print(f"bench: unbatched {unbatched_ms:.3f} ms/step", file=sys.stderr, flush=True)
-    return {
+    return check, {
         "workload": (f"{b.name}: {b.n_snap} Plummer snapshots (32 spheres + 20% background, "
                      f"half gas), sizes log-uniform in [1e3, 1e6], n={b.n}, time-bin active "
                      f"sets 2^-K with K = round(-log2 f), f log-uniform in [1e-3, 1]; "
@@ -437,7 +592,7 @@ def run_differentiation(dev, steps: int, warmup: int, n: int = 1 << 20, seed: in
     }
 
 
-def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int = 3) -> dict:
+def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int = 3):
     """The precision workload: N = 2e7 particles clustered as the plain
     workload but in 256 Plummer spheres, FP64 stored positions, on the
     mixed-precision path. One step = both octree builds, density with a
@@ -483,7 +638,10 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
     nonconv = ctx.nonconverged(reset=True)
     print(f"bench: precision {ms:.3f} ms/step, {inter} interactions", file=sys.stderr,
           flush=True)
-    return {
+    check = {"w": w, "gpu": _host_outputs(dict(od, acc=oh["acc"], npairs=oh["npairs"],
+                                               gacc=og["acc"], nterms=og["nterms"]))}
+    tree.close()
+    return check, {
         "workload": f"{w.name}: N={n} in 256 Plummer spheres + 20% background (half gas), "
                     "FP64 stored positions, 295 neighbours, theta=0.5, eps=1e-3, all active",
         "value": inter / (ms * 1e-3),
@@ -594,7 +752,10 @@ def main() -> int:
     if args.only:
         leg = {"batched": run_batched, "differentiation": run_differentiation,
                "precision": run_precision}[args.only]
-        print(json.dumps({args.only: leg(dev, args.steps, args.warmup)}), flush=True)
+        res = leg(dev, args.steps, args.warmup)
+        if isinstance(res, tuple):
+            res = res[1]
+        print(json.dumps({args.only: res}), flush=True)
         return 0
     w = inputs.plummer(n=args.n, n_spheres=args.spheres, seed=1)
     pos32, vel32, m32, u32 = w.as_f32()
@@ -672,6 +833,9 @@ def main() -> int:
     i_g = int(outg["nterms"].sum())
     inter = i_d + i_h + i_g
     times = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    plain_out = _host_outputs(dict(outd, h=d["h"], acc=outh["acc"], npairs=outh["npairs"],
+                                   gacc=outg["acc"], nterms=outg["nterms"]))
+    ms_interactions = times["density"] + times["hydro"] + times["gravity"]
     print(f"bench: {args.steps} steps, {ms:.3f} ms/step; per op ms {times}; "
           f"interactions dens {i_d} hydro {i_h} grav {i_g}; nonconv {nonconv}",
           file=sys.stderr, flush=True)
@@ -710,21 +874,42 @@ def main() -> int:
                    "h_nonconverged": nonconv,
                    "h_passes_per_wave": passes / max(waves, 1), "path": "plain",
                    "launch_choices": tuned, "autotune_s": tune_s},
+        # the same interactions over the three interaction calls alone (the
+        # octree builds excluded: HIP-event times of the timed steps)
+        "value_excl_build": inter / (ms_interactions * 1e-3),
+        "build_ms": times["build"],
         "roofline": roofline,
         # the whole plain step's algorithmic FP32 work against the same peak
         "step_fp32_roofline": step_roofline((i_d, i_h, i_g), ms),
+        "max_err": None,
     }
+    checks = {}
     if not args.no_batched:
-        line["batched"] = run_batched(dev, args.steps, args.warmup)
+        checks["batched"], line["batched"] = run_batched(dev, args.steps, args.warmup)
+        line["batched"]["max_err"] = None
+        line["batched"]["mixed_precision"]["max_err"] = None
     if not args.no_differentiation:
         line["differentiation"] = run_differentiation(dev, args.steps, args.warmup)
     if not args.no_precision:
-        line["precision"] = run_precision(dev, args.steps, args.warmup)
+        checks["precision"], line["precision"] = run_precision(dev, args.steps, args.warmup)
+        line["precision"]["max_err"] = None
     if args.copy_calibration:
         copy_calibration(dev)
     if not args.no_cpu_baseline:
+        # the oracle leg: the CPU baseline, and every GPU leg's errors
+        # against the oracle (outside the timed regions)
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_samples)
+        cb = cpu_baseline(w, args.cpu_samples, gpu=plain_out)
+        line["max_err"] = cb.pop("gpu_errors")
+        line["cpu_baseline"] = cb
+        if "batched" in checks:
+            print("bench: batched errors (oracle) ...", file=sys.stderr, flush=True)
+            e = batched_errors(checks.pop("batched"))
+            line["batched"]["max_err"] = e["fp32"]
+            line["batched"]["mixed_precision"]["max_err"] = e["mixed"]
+        if "precision" in checks:
+            print("bench: precision errors (oracle) ...", file=sys.stderr, flush=True)
+            line["precision"]["max_err"] = precision_errors(checks.pop("precision"))
     print(json.dumps(line), flush=True)
     return 0
 

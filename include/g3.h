@@ -269,6 +269,96 @@ int g3_hydro_force(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
                    int32_t *npairs, void *stream);
 
 /*
+ * Thermal conduction, the third SPH module the paper moves to the GPU
+ * (paper section 1, the module list; section 3.3). The paper prints no
+ * formula; Gadget's conduction module (Jubelgas, Springel & Dolag 2004)
+ * discretises rho du/dt = div(kappa grad u) in the form of Brookshaw (1985):
+ *   du_i/dt = sum_j m_j (kappa_i + kappa_j) (u_i - u_j) Fbar_ij / (rho_i rho_j),
+ *   Fbar_ij = (F(r, h_i) + F(r, h_j)) / 2,  F = (1/r) dW/dr,
+ * over gas j != i with r < max(h_i, h_j) (the hydro force's symmetric test);
+ * pairs at r = 0 add nothing. The conductivity is in units of the internal
+ * energy per mass (the heat capacity absorbed into it) and a power law of
+ * it: kappa = kappa0 u^kappa_exp (kappa_exp = 5/2 follows Spitzer's
+ * temperature dependence, 0 is a constant conductivity). Every pair's
+ * exchange is antisymmetric, so sum_i m_i du_i/dt = 0 over a set that holds
+ * every pair of its members.
+ *   u [n], h [n] (float, FP32 trees only), rho [n]: inputs of every gas
+ *   particle; dudt [n] (the conduction rate alone) and npairs [n]: outputs
+ *   at the active gas rows, each nullable.
+ * Refits the gas octree's per-node maximum h from `h` first. */
+int g3_conduction(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                  const int32_t *active, const g3_params *p, double kappa0,
+                  double kappa_exp, const float *u, const void *h,
+                  const float *rho, float *dudt, int32_t *npairs, void *stream);
+
+/*
+ * The improved SPH that the paper's code ran (Beck et al. 2016; paper
+ * section 1 names it) adds switches to the hydro force; the paper prints
+ * none of them, so these are the published methods, in their usual form:
+ *   - velocity divergence and curl, the grad-h SPH estimates over the
+ *     density's gather pairs (r < h_i):
+ *       div v_i  =  (1/(Omega_i rho_i)) sum_j m_j (v_j - v_i) . grad_i W(r, h_i),
+ *       curl v_i = -(1/(Omega_i rho_i)) sum_j m_j (v_j - v_i) x grad_i W(r, h_i),
+ *     grad_i W = F(r, h_i) (x_i - x_j);
+ *   - the Balsara (1995) factor f = |div v| / (|div v| + |curl v| + eps c/h),
+ *     c = sqrt(gamma (gamma-1) u), near 1 in compression, near 0 in shear;
+ *   - a time-dependent viscosity strength per particle (Morris & Monaghan
+ *     1997, with the source factor of Rosswog et al. 2000, the Balsara
+ *     factor in the source):
+ *       d alpha/dt = -(alpha - alpha_min)/tau + f max(-div v, 0)(alpha_max - alpha),
+ *       tau = h / (decay c),
+ *     stepped exactly over dt for inputs held fixed (it is linear in alpha);
+ *   - in the hydro force the strength alpha of the viscosity term becomes
+ *     (alpha_i + alpha_j)/2 * (f_i + f_j)/2, and artificial conduction of the
+ *     internal energy (Price 2008, eq. 28) is added:
+ *       du_i/dt += m_j alpha_u v_u (u_i - u_j) gbar r / rhobar,
+ *       v_u = sqrt(|P_i - P_j| / rhobar), rhobar = (rho_i + rho_j)/2,
+ *     gbar = (F(r, h_i) + F(r, h_j))/2, over the hydro force's pairs; every
+ *     pair's exchange is antisymmetric, so total energy is conserved.
+ */
+typedef struct {
+  double alpha_min;   /* floor of the viscosity strength (0.025) */
+  double alpha_max;   /* ceiling of the viscosity strength (1) */
+  double decay;       /* decay parameter l of tau = h / (l c) (0.2) */
+  double balsara_eps; /* eps of the Balsara factor's c/h term (1e-4) */
+  double alpha_u;     /* artificial conduction strength (1; 0: none) */
+  int32_t flags;      /* reserved, must be 0 */
+} g3_switch_params;
+
+/* Velocity divergence and curl of the active gas particles (FP32 trees).
+ *   vel [n][3], h [n] (float), rho [n], omega [n]: inputs of every gas
+ *   particle; div_v [n] and curl_v [n][3]: outputs at the active gas rows,
+ *   each nullable. */
+int g3_velocity_gradients(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                          const int32_t *active, const g3_params *p,
+                          const float *vel, const void *h, const float *rho,
+                          const float *omega, float *div_v, float *curl_v,
+                          void *stream);
+/* One step dt of the viscosity strength and the Balsara factor of the rows
+ * `active` of [n] caller-order arrays (active NULL: every row, n_act == n):
+ * u [n], h [n] (float or double after h_type), div_v [n], curl_v [n][3]
+ * inputs; alpha [n] in/out (nullable: the factor only), balsara [n] out
+ * (nullable). No tree: a per-particle kernel. */
+int g3_viscosity_switch(g3_ctx *ctx, int64_t n, int32_t h_type, int64_t n_act,
+                        const int32_t *active, const g3_params *p,
+                        const g3_switch_params *sw, double dt, const float *u,
+                        const void *h, const float *div_v, const float *curl_v,
+                        float *alpha, float *balsara, void *stream);
+/* g3_hydro_force with the switches: per-particle strengths alpha [n] and
+ * Balsara factors balsara [n] of every gas particle (each nullable:
+ * p->alpha and 1) and artificial conduction of strength sw->alpha_u (the
+ * other fields of sw are not read). Same pairs, outputs and rules as
+ * g3_hydro_force, which it equals with one strength, unit factors and
+ * alpha_u = 0. */
+int g3_hydro_force_switches(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
+                            const int32_t *active, const g3_params *p,
+                            const g3_switch_params *sw, const float *vel,
+                            const float *u, const void *h, const float *rho,
+                            const float *omega, const float *alpha,
+                            const float *balsara, float *acc, float *dudt,
+                            float *vsig, int32_t *npairs, void *stream);
+
+/*
  * Barnes-Hut gravity of the active particles from all particles: walk the
  * all-particle octree in preorder from the root; a node whose cube does not
  * contain x_i and whose side l satisfies l < theta |x_i - c| contributes its
@@ -282,6 +372,85 @@ int g3_hydro_force(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
 int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                const int32_t *active, const g3_params *p, float *acc,
                float *pot, int32_t *nterms, void *stream);
+
+/*
+ * Time integration around the interaction phase. The paper's code moves
+ * only the particles that are active at a step, on adaptive steps, and
+ * drifts the tree between rebuilds instead of rebuilding it (paper section 1
+ * on adaptive time-stepping, section 2.2). These calls run that loop on the
+ * device: the kick-drift-kick leapfrog on power-of-two time bins of
+ * Springel (2005, section 5).
+ *
+ * A system step lasts dt_max and is cut into 2^B ticks of tau = dt_max/2^B.
+ * A particle in bin k (0 <= k <= B) takes steps of 2^(B-k) ticks and is
+ * active at tick T iff 2^(B-k) divides T. Its step criterion (Springel
+ * 2005, eqs. 34 and 16) is dt = sqrt(2 eta eps / |a|), for gas also at most
+ * C h / vsig; the bin is the smallest k in [0, B] with dt_max/2^k <= dt (B
+ * if none), but at tick T no smaller than B - min(tz(T), B), tz the number
+ * of trailing zero bits of T, so that the new step ends on a tick that its
+ * bin is active at. The criterion is evaluated in FP64 from the FP32
+ * forces.
+ *
+ * One system step, from a synchronised state whose forces and bins are
+ * known (g3_integrate_start, or the end of the previous system step):
+ *  1. the trees are built from the positions (the call SYNCS, as builds do);
+ *     every particle takes the opening half kick of its bin's step;
+ *  2. for T = 1 .. 2^B: every particle drifts x += v tau (in the positions'
+ *     precision); both octrees are refit to the new positions
+ *     (g3_refit_tree: same order and topology, new moments and boxes); the
+ *     active particles get the density with the smoothing-length solve from
+ *     their last h (active gas), the hydro force (active gas) from every gas
+ *     particle's velocity and internal energy predicted to T from the middle
+ *     of its current step, v + a (T - T_mid) tau and
+ *     max(u + du/dt (T - T_mid) tau, 0), and the stored h, rho and Omega of
+ *     inactive neighbours, and gravity; then acc = gravity + hydro, the
+ *     closing half kick with the step they had, the new bin and, unless
+ *     T = 2^B, the opening half kick of the new step;
+ *  3. at T = 2^B every particle has been active: the state is synchronised.
+ * Kicks are v += a dt/2 and, for gas, u = max(u + du/dt dt/2, 0).
+ * Active sets are found on the device from the bins (no host wait inside
+ * the tick loop).
+ */
+typedef struct {
+  double dt_max;     /* the longest step (bin 0), > 0 */
+  double courant;    /* C of the hydrodynamic step criterion (0.15) */
+  double eta;        /* accuracy parameter of the gravitational step (0.025) */
+  int32_t bin_depth; /* B: bins 0..B, 2^B ticks per system step, 0..20 */
+  int32_t flags;     /* reserved, must be 0 */
+} g3_integ_params;
+
+/* The particle state (device pointers, caller order, [n] rows). pos and h
+ * are float or double after pos_t; the rest FP32. Updated in place. */
+typedef struct {
+  void *pos;          /* [n][3] in/out */
+  float *vel;         /* [n][3] in/out */
+  const float *mass;  /* [n] */
+  float *u;           /* [n] in/out: internal energy per unit mass (gas rows) */
+  const uint8_t *type;/* [n] 0 gas, 1 collisionless; NULL: all gas */
+  void *h;            /* [n] in/out: smoothing length (gas rows; <= 0: none yet) */
+  float *rho, *omega; /* [n] in/out: density and grad-h factor (gas rows) */
+  float *acc;         /* [n][3] in/out: total acceleration, gravity + hydro */
+  float *dudt, *vsig; /* [n] in/out: du/dt and max signal velocity (gas rows) */
+  float *pot;         /* [n] in/out: gravitational potential */
+  int32_t *bin;       /* [n] in/out: time bin */
+} g3_state;
+
+/* Forces and bins of a synchronised state at the start of integration:
+ * builds the trees into *tree (a new tree when *tree is NULL) and evaluates
+ * density with the h solve, hydro and gravity of every particle, then the
+ * bins (no kick). SYNCS (a build). */
+int g3_integrate_start(g3_ctx *ctx, g3_tree **tree, int64_t n, int32_t pos_t,
+                       const g3_state *state, const double *box /* host [4] */,
+                       const g3_params *p, const g3_integ_params *ip,
+                       void *stream);
+/* One system step (see above), rebuilding *tree from the positions at its
+ * start. tick_active (device int64 [2^B], nullable) receives the number of
+ * active particles at each tick. Non-converged h solves are counted as in
+ * g3_density (g3_ctx_stats). SYNCS once, at the build. */
+int g3_system_step(g3_ctx *ctx, g3_tree **tree, int64_t n, int32_t pos_t,
+                   const g3_state *state, const double *box /* host [4] */,
+                   const g3_params *p, const g3_integ_params *ip,
+                   int64_t *tick_active, void *stream);
 
 /*
  * Launch tuning (the batching extension's autotuner). Two launch choices

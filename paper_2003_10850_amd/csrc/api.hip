@@ -86,6 +86,18 @@ __global__ void k_mark(const int32_t *__restrict__ active, int64_t n_act,
   rowp1[s] = (int32_t)(a + 1);
 }
 
+// Targets by the time-bin rule: member s is a target iff the bin of its
+// particle is at least kmin (rows are then caller ids).
+__global__ void k_mark_bins(const int32_t *__restrict__ perm, int64_t m,
+                            const int32_t *__restrict__ bins, int32_t kmin,
+                            uint32_t *__restrict__ mark, int32_t *__restrict__ rowp1) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int32_t cid = perm[s];
+  mark[s] = bins[cid] >= kmin ? 1u : 0u;
+  rowp1[s] = cid + 1;
+}
+
 __global__ void k_compact(const uint32_t *__restrict__ mark, const uint32_t *__restrict__ slot,
                           const int32_t *__restrict__ rowp1, int64_t m,
                           int32_t *__restrict__ targets, int32_t *__restrict__ rows) {
@@ -247,50 +259,53 @@ struct WorkBufs {
   uint32_t *flags = nullptr, *segid = nullptr, *gcnt = nullptr;
 };
 
-int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t n_act,
-                 const int32_t *active, int split, WorkBufs *b) {
+// listed: targets come from a mark pass (an active list or a bin rule)
+// instead of being every member; max_t bounds their number.
+int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t max_t_in, bool listed,
+                 int split, WorkBufs *b) {
+  auto no_room = [&](const char *msg) { return fail(c, G3_ENOMEM, msg); };
   *b = WorkBufs();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
   const int n_snap = t->n_snap;
-  const int64_t max_t = active ? std::min<int64_t>(n_act, m) : m;
+  const int64_t max_t = listed ? std::min<int64_t>(max_t_in, m) : m;
   const bool split_on = split >= 0 || split == kSplitAuto;
   const int64_t max_seg = split_on ? std::max<int64_t>(max_t, 1) : n_snap;
   b->max_t = max_t;
   b->max_seg = max_seg;
   b->split_on = split_on;
   int64_t scan_n = 1;
-  if (active) scan_n = std::max(scan_n, m + 1);
+  if (listed) scan_n = std::max(scan_n, m + 1);
   if (split_on) scan_n = std::max(scan_n, std::max(max_t, max_seg) + 1);
   uint32_t *stmp = nullptr, *mark = nullptr, *slot = nullptr;
   int32_t *rowp1 = nullptr, *tg = nullptr, *rw = nullptr;
-  if (active || split_on) {
+  if (listed || split_on) {
     stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(scan_n) * sizeof(uint32_t));
-    if (!stmp) return fail(c, G3_ENOMEM, "device allocation of the scan scratch failed");
+    if (!stmp) return no_room("device allocation of the scan scratch failed");
   }
-  if (active) {
+  if (listed) {
     mark = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
     slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
     rowp1 = (int32_t *)scratch(c, kCounts, (m + 2) * sizeof(int32_t));
     tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
     rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
     if (!mark || !slot || !rowp1 || !tg || !rw)
-      return fail(c, G3_ENOMEM, "device allocation of the active-set scratch failed");
+      return no_room("device allocation of the active-set scratch failed");
   }
   // tstart, gstart [max_seg + 2] (a scan writes one past its n), seg_snap
   // [max_seg + 1], nseg, queue [8]
   const size_t tab_elems = 3 * ((size_t)max_seg + 2) + 1 + 8;
   int32_t *tab = (int32_t *)scratch(c, kGroups, tab_elems * sizeof(int32_t));
-  if (!tab) return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+  if (!tab) return no_room("device allocation of the group table failed");
   uint32_t *flags = nullptr, *segid = nullptr, *gcnt = nullptr;
   if (split_on) {
     flags = (uint32_t *)scratch(c, kCounts, (m + 2) * sizeof(uint32_t));
     segid = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
     gcnt = (uint32_t *)scratch(c, kIds, (max_seg + 2) * sizeof(uint32_t));
     if (!flags || !segid || !gcnt)
-      return fail(c, G3_ENOMEM, "device allocation of the group table failed");
+      return no_room("device allocation of the group table failed");
     // the compaction's buffers must not have moved (same slots, same sizes)
-    if (active && (flags != (uint32_t *)rowp1 || segid != mark))
+    if (listed && (flags != (uint32_t *)rowp1 || segid != mark))
       return fail(c, G3_EHIP, "group table scratch moved");
   }
   b->stmp = stmp; b->mark = mark; b->slot = slot;
@@ -300,12 +315,14 @@ int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t n_act,
 }
 
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
-                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s, int split) {
+                 int64_t n_act, const int32_t *active, Work *w, hipStream_t s, int split,
+                 const int32_t *bins, int32_t kmin) {
   *w = Work();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
   WorkBufs b;
-  const int st = reserve_work(c, t, o, n_act, active, split, &b);
+  const bool listed = active || bins;
+  const int st = reserve_work(c, t, o, active ? n_act : m, listed, split, &b);
   if (st) return st;
   const int n_snap = t->n_snap;
   const int64_t max_t = b.max_t, max_seg = b.max_seg;
@@ -313,15 +330,19 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
   uint32_t *stmp = b.stmp, *mark = b.mark, *slot = b.slot;
   int32_t *rowp1 = b.rowp1, *tg = b.tg, *rw = b.rw, *tab = b.tab;
   uint32_t *flags = b.flags, *segid = b.segid, *gcnt = b.gcnt;
-  if (active) {
-    k_zero_u32<<<nblk(m), 256, 0, s>>>(mark, m);
-    if (n_act > 0)
-      k_mark<<<nblk(n_act), 256, 0, s>>>(active, n_act, iperm, t->n, mark, rowp1);
+  if (listed) {
+    if (bins) {
+      k_mark_bins<<<nblk(m), 256, 0, s>>>(o.perm, m, bins, kmin, mark, rowp1);
+    } else {
+      k_zero_u32<<<nblk(m), 256, 0, s>>>(mark, m);
+      if (n_act > 0)
+        k_mark<<<nblk(n_act), 256, 0, s>>>(active, n_act, iperm, t->n, mark, rowp1);
+    }
     hipError_t e = scan_u32(mark, slot, m, stmp, s);
     if (e != hipSuccess) return hip_fail(c, e, "active-set scan");
     k_compact<<<nblk(m), 256, 0, s>>>(mark, slot, rowp1, m, tg, rw);
   }
-  const uint32_t *ntarg = active ? slot + m : nullptr;
+  const uint32_t *ntarg = listed ? slot + m : nullptr;
   int32_t *tstart = tab, *gstart = tab + max_seg + 2, *seg_snap = gstart + max_seg + 2;
   int32_t *nseg = seg_snap + max_seg + 2;
   unsigned *queue = (unsigned *)(nseg + 1);
@@ -352,6 +373,7 @@ int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *ip
   w->gs.queue = queue;
   w->gs.n_snap = n_snap;
   w->rows = rw;
+  w->ntarg = ntarg;
   w->max_groups = split_on ? max_t : max_groups_of(max_t, n_snap);
   return G3_OK;
 }
@@ -844,11 +866,12 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   c->last_stream = s;
   const Octree &o = t->gas;
   const Tuning tu = tuning_for(c, kTuneDensity, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  const SphParams sp = sph_params(c, p, t, tu);
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
-  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sph_params(c, p, t, tu), solve_h ? 1 : 0,
-                                h, rho, drho_dh, omega, nngb, c->counters, s);
+  hipError_t e = launch_density(o, wk.gs, wk.max_groups, sp, solve_h ? 1 : 0, h, rho, drho_dh,
+                                omega, nngb, c->counters, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
   return G3_OK;
@@ -904,6 +927,345 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   if (st) return st;
   hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_conduction(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                  const g3_params *p, double kappa0, double kappa_exp, const float *u,
+                  const void *h, const float *rho, float *dudt, int32_t *npairs,
+                  void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_conduction");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_conduction: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_conduction: FP32 trees only");
+  if (!std::isfinite(kappa0) || kappa0 < 0.0 || !std::isfinite(kappa_exp))
+    return fail(c, G3_EINVAL, "g3_conduction: bad conductivity");
+  if (t->gas.n > 0 && (!u || !h || !rho)) return fail(c, G3_EINVAL, "g3_conduction: null input");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  if (o.n == 0) {
+    c->err.clear();
+    return G3_OK;
+  }
+  const Tuning tu = tuning_for(c, kTuneHydro, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  float4 *ch = (float4 *)scratch(c, kCondCh, (size_t)o.n * sizeof(float4));
+  if (!ch) return fail(c, G3_ENOMEM, "g3_conduction: allocation failed");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
+  if (st) return st;
+  // node hmax from h (the walk's symmetric radius), then the pair inputs
+  hipError_t e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e == hipSuccess)
+    e = launch_conduction_prep(o, u, h, 0, rho, (float)kappa0, (float)kappa_exp, ch, s);
+  if (e == hipSuccess)
+    e = launch_conduction(o, wk.gs, wk.max_groups, tu.walk_leaf, ch, dudt, npairs, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_conduction");
+  c->err.clear();
+  return G3_OK;
+}
+
+// ---- improved-SPH switches ----
+
+static bool switch_params_ok(const g3_switch_params *sp) {
+  return sp && std::isfinite(sp->alpha_min) && std::isfinite(sp->alpha_max) &&
+         sp->alpha_min >= 0.0 && sp->alpha_max >= sp->alpha_min && std::isfinite(sp->decay) &&
+         sp->decay >= 0.0 && std::isfinite(sp->balsara_eps) && sp->balsara_eps >= 0.0 &&
+         std::isfinite(sp->alpha_u) && sp->alpha_u >= 0.0 && sp->flags == 0;
+}
+
+int g3_velocity_gradients(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                          const g3_params *p, const float *vel, const void *h, const float *rho,
+                          const float *omega, float *div_v, float *curl_v, void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_velocity_gradients");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_velocity_gradients: bad params");
+  if (t->f64) return fail(c, G3_EINVAL, "g3_velocity_gradients: FP32 trees only");
+  if (t->gas.n > 0 && (!vel || !h || !rho || !omega))
+    return fail(c, G3_EINVAL, "g3_velocity_gradients: null input");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  if (o.n == 0) {
+    c->err.clear();
+    return G3_OK;
+  }
+  const Tuning tu = tuning_for(c, kTuneDensity, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
+  if (st) return st;
+  // (v, h) in sorted order, then the gather walk
+  hipError_t e = launch_hydro_prep(o, vel, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+  if (e == hipSuccess)
+    e = launch_velgrad(o, wk.gs, wk.max_groups, tu.walk_leaf, rho, omega, div_v, curl_v, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_velocity_gradients");
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_viscosity_switch(g3_ctx *c, int64_t n, int32_t h_type, int64_t n_act,
+                        const int32_t *active, const g3_params *p, const g3_switch_params *sw,
+                        double dt, const float *u, const void *h, const float *div_v,
+                        const float *curl_v, float *alpha, float *balsara, void *stream) {
+  if (!c) return G3_EINVAL;
+  if (n < 0 || n_act < 0 || (!active && n_act != n) || (h_type != G3_F32 && h_type != G3_F64))
+    return fail(c, G3_EINVAL, "g3_viscosity_switch: bad sizes");
+  if (!params_ok(p) || !switch_params_ok(sw) || !std::isfinite(dt) || dt < 0.0)
+    return fail(c, G3_EINVAL, "g3_viscosity_switch: bad params");
+  if (n_act > 0 && (!u || !h || !div_v || !curl_v || (!alpha && !balsara)))
+    return fail(c, G3_EINVAL, "g3_viscosity_switch: null argument");
+  DeviceGuard g(c->device);
+  int st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  SwitchStep step;
+  step.gamma = (float)p->gamma;
+  step.alpha_min = (float)sw->alpha_min;
+  step.alpha_max = (float)sw->alpha_max;
+  step.decay = (float)sw->decay;
+  step.eps = (float)sw->balsara_eps;
+  step.dt = (float)dt;
+  hipError_t e = launch_alpha_update(n, n_act, active, step, h_type == G3_F64, u, h, div_v,
+                                     curl_v, alpha, balsara, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_viscosity_switch");
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_hydro_force_switches(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
+                            const g3_params *p, const g3_switch_params *sw, const float *vel,
+                            const float *u, const void *h, const float *rho,
+                            const float *omega, const float *alpha, const float *balsara,
+                            float *acc, float *dudt, float *vsig, int32_t *npairs,
+                            void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_hydro_force_switches");
+  if (st) return st;
+  if (!params_ok(p) || !switch_params_ok(sw))
+    return fail(c, G3_EINVAL, "g3_hydro_force_switches: bad params");
+  if (t->gas.n > 0 && (!vel || !u || !h || !rho || !omega))
+    return fail(c, G3_EINVAL, "g3_hydro_force_switches: null input");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  Octree &o = t->gas;
+  const Tuning tu = tuning_for(c, kTuneHydro, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  const SphParams sp = sph_params(c, p, t, tu);
+  st = ensure_h64(c, t, o);
+  if (st) return st;
+  float4 *ext = (float4 *)scratch(c, kHydroExt, (size_t)std::max<int64_t>(o.n, 1) * sizeof(float4));
+  if (!ext) return fail(c, G3_ENOMEM, "g3_hydro_force_switches: allocation failed");
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
+  if (st) return st;
+  hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
+  if (e == hipSuccess) e = refit_hmax(o, s);
+  if (e == hipSuccess)
+    e = launch_hydro_ext_prep(o, u, rho, alpha, balsara, sp.alpha, ext, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_switches prep");
+  e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s, ext,
+                   (float)sw->alpha_u);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force_switches");
+  c->err.clear();
+  return G3_OK;
+}
+
+// ---- time integration ----
+
+static bool integ_args_ok(g3_ctx *c, int64_t n, int32_t pos_t, const g3_state *st,
+                          const double *box, const g3_params *p, const g3_integ_params *ip,
+                          const char *who) {
+  auto bad = [&](const char *what) {
+    fail(c, G3_EINVAL, std::string(who) + ": " + what);
+    return false;
+  };
+  if (n < 0 || n >= (int64_t)INT32_MAX) return bad("n out of range");
+  if (pos_t != G3_F32 && pos_t != G3_F64) return bad("unknown pos_t");
+  if (!st || !box || !p || !ip) return bad("null argument");
+  if (!params_ok(p)) return bad("bad params");
+  if (!(p->n_ngb > 1365.0 / 48.0 && p->h_tol > 0.0 && p->h_tol < 1.0))
+    return bad("n_ngb must exceed 1365/48 and 0 < h_tol < 1");
+  if (!(ip->dt_max > 0.0) || !std::isfinite(ip->dt_max) || ip->bin_depth < 0 ||
+      ip->bin_depth > 20 || !(ip->courant > 0.0) || !(ip->eta > 0.0) || ip->flags != 0)
+    return bad("bad integration params");
+  if (n > 0 && (!st->pos || !st->vel || !st->mass || !st->u || !st->h || !st->rho ||
+                !st->omega || !st->acc || !st->dudt || !st->vsig || !st->pot || !st->bin))
+    return bad("null state array");
+  return true;
+}
+
+// Forces of the particles that are active at tick T (every particle at
+// T = 0 and with `every`), then their kicks and new bins: the density with
+// the smoothing-length solve (active gas), the hydro force from the gas
+// velocities and internal energies predicted to T, gravity, and the update.
+static int tick_forces(g3_ctx *c, g3_tree *t, int64_t n, const g3_state *st,
+                       const g3_params *p, const g3_integ_params *ip, int64_t T, bool every,
+                       const IntegUpdate &iu, float *acc_h, float *vp, float *up,
+                       int64_t *count_out, hipStream_t s) {
+  const int32_t *bins = every ? nullptr : st->bin;
+  const int32_t kmin = iu.kmin;
+  const double tau = std::ldexp(ip->dt_max, -ip->bin_depth);
+  Octree &gas = t->gas;
+  int rc = ensure_h64(c, t, gas);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  if (gas.n > 0) {
+    const Tuning td = tuning_for(c, kTuneDensity, gas.n);
+    const SphParams spd = sph_params(c, p, t, td);
+    Work wd;
+    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wd, s, td.split, bins, kmin);
+    if (rc) return rc;
+    e = launch_density(gas, wd.gs, wd.max_groups, spd, 1, st->h, st->rho, nullptr, st->omega,
+                       nullptr, c->counters, s);
+    if (e != hipSuccess) return hip_fail(c, e, "density at a tick");
+    const float *vh = st->vel, *uh = st->u;
+    if (T > 0) {
+      e = launch_predict(n, st->type, st->vel, st->u, st->acc, st->dudt, st->bin,
+                         ip->bin_depth, T, tau, vp, up, s);
+      if (e != hipSuccess) return hip_fail(c, e, "prediction at a tick");
+      vh = vp;
+      uh = up;
+    }
+    const Tuning th = tuning_for(c, kTuneHydro, gas.n);
+    const SphParams sp = sph_params(c, p, t, th);
+    e = launch_hydro_prep(gas, vh, uh, st->h, st->rho, st->omega, sp.gamma, t->f64, s);
+    if (e == hipSuccess) e = refit_hmax(gas, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hydro prep at a tick");
+    Work wh;
+    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wh, s, th.split, bins, kmin);
+    if (rc) return rc;
+    e = launch_hydro(gas, wh.gs, wh.max_groups, sp, acc_h, st->dudt, st->vsig, nullptr, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hydro at a tick");
+  }
+  const Octree &all = t->all;
+  const Tuning tg = tuning_for(c, kTuneGravity, all.n);
+  Work wg;
+  rc = prepare_work(c, t, all, t->iperm_all, all.n, nullptr, &wg, s, tg.split, bins, kmin);
+  if (rc) return rc;
+  e = launch_gravity(all, wg.gs, wg.max_groups, grav_params(p, t), st->acc, st->pot, nullptr, s);
+  if (e == hipSuccess && count_out) e = launch_store_count(wg.ntarg, count_out, s);
+  if (e == hipSuccess)
+    e = launch_update(n, t->f64, iu, st->type, st->vel, st->u, st->acc, acc_h, st->dudt,
+                      st->vsig, st->h, st->bin, s);
+  if (e != hipSuccess) return hip_fail(c, e, "gravity and update at a tick");
+  return G3_OK;
+}
+
+static IntegUpdate integ_update(const g3_params *p, const g3_integ_params *ip) {
+  IntegUpdate iu;
+  iu.depth = ip->bin_depth;
+  iu.dt_max = ip->dt_max;
+  iu.eta_eps2 = 2.0 * ip->eta * p->eps;
+  iu.courant = ip->courant;
+  return iu;
+}
+
+// The ctx scratch of the integration calls, taken before their first launch.
+static int integ_scratch(g3_ctx *c, int64_t n, float **acc_h, float **vp, float **up) {
+  const int64_t m = std::max<int64_t>(n, 1);
+  *acc_h = (float *)scratch(c, kIntAccH, (size_t)m * 3 * sizeof(float));
+  *vp = (float *)scratch(c, kIntVp, (size_t)m * 3 * sizeof(float));
+  *up = (float *)scratch(c, kIntUp, (size_t)m * sizeof(float));
+  if (!*acc_h || !*vp || !*up)
+    return fail(c, G3_ENOMEM, "device allocation of the integration scratch failed");
+  return G3_OK;
+}
+
+static int integ_build(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3_state *st,
+                       const double *box, const g3_params *p, void *stream) {
+  const int64_t off[2] = {0, n};
+  return g3_build_forest(c, 1, off, pos_t, st->pos, st->mass, st->type, box, p, tree, stream);
+}
+
+int g3_integrate_start(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3_state *st,
+                       const double *box, const g3_params *p, const g3_integ_params *ip,
+                       void *stream) {
+  if (!c) return G3_EINVAL;
+  if (!tree) return fail(c, G3_EINVAL, "g3_integrate_start: null tree handle");
+  if (!integ_args_ok(c, n, pos_t, st, box, p, ip, "g3_integrate_start")) return G3_EINVAL;
+  DeviceGuard g(c->device);
+  int rc = check_pending(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  float *acc_h, *vp, *up;
+  rc = integ_scratch(c, n, &acc_h, &vp, &up);
+  if (rc) return rc;
+  rc = integ_build(c, tree, n, pos_t, st, box, p, stream);
+  if (rc) return rc;
+  IntegUpdate iu = integ_update(p, ip);
+  iu.every_particle = 1;
+  iu.sum = 1;
+  iu.rebin = 1;
+  iu.kmin = 0;
+  rc = tick_forces(c, *tree, n, st, p, ip, 0, true, iu, acc_h, vp, up, nullptr, s);
+  if (rc) return rc;
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_system_step(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3_state *st,
+                   const double *box, const g3_params *p, const g3_integ_params *ip,
+                   int64_t *tick_active, void *stream) {
+  if (!c) return G3_EINVAL;
+  if (!tree) return fail(c, G3_EINVAL, "g3_system_step: null tree handle");
+  if (!integ_args_ok(c, n, pos_t, st, box, p, ip, "g3_system_step")) return G3_EINVAL;
+  DeviceGuard g(c->device);
+  int rc = check_pending(c);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  float *acc_h, *vp, *up;
+  rc = integ_scratch(c, n, &acc_h, &vp, &up);
+  if (rc) return rc;
+  // the trees of this system step, from the positions at its start
+  rc = integ_build(c, tree, n, pos_t, st, box, p, stream);
+  if (rc) return rc;
+  g3_tree *t = *tree;
+  const int B = ip->bin_depth;
+  const int64_t ticks = (int64_t)1 << B;
+  const double tau = std::ldexp(ip->dt_max, -B);
+  const IntegUpdate base = integ_update(p, ip);
+  // opening half kick of every particle with its bin's step
+  IntegUpdate open = base;
+  open.every_particle = 1;
+  open.open = 1;
+  hipError_t e = launch_update(n, t->f64, open, st->type, st->vel, st->u, st->acc, acc_h,
+                               st->dudt, st->vsig, st->h, st->bin, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_system_step opening kick");
+  for (int64_t T = 1; T <= ticks; ++T) {
+    e = launch_drift(st->pos, t->f64, st->vel, n, tau, s);
+    if (e != hipSuccess) return hip_fail(c, e, "g3_system_step drift");
+    rc = refit_octree(c, t, t->all, st->pos, st->mass, s);
+    if (rc) return rc;
+    rc = refit_octree(c, t, t->gas, st->pos, st->mass, s);
+    if (rc) return rc;
+    // active at T: bins k with 2^(B-k) | T, i.e. k >= B - min(tz(T), B)
+    int tz = 0;
+    while (tz < B && ((T >> tz) & 1) == 0) ++tz;
+    IntegUpdate iu = base;
+    iu.kmin = B - tz;
+    iu.sum = 1;
+    iu.close = 1;
+    iu.rebin = 1;
+    iu.open = T < ticks ? 1 : 0;
+    rc = tick_forces(c, t, n, st, p, ip, T, false, iu, acc_h, vp, up,
+                     tick_active ? tick_active + (T - 1) : nullptr, s);
+    if (rc) return rc;
+  }
   c->err.clear();
   return G3_OK;
 }
@@ -1058,8 +1420,8 @@ int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, con
           if (r != hipSuccess) return r;
           if (prepare_work(c, t, gas, t->iperm_gas, n_act, active, &wk, s, tu.split))
             return hipErrorUnknown;
-          return launch_density(gas, wk.gs, wk.max_groups, sph_params(c, p, t, tu), 1, hs, nullptr,
-                                nullptr, nullptr, nullptr, c->counters, s);
+          return launch_density(gas, wk.gs, wk.max_groups, sph_params(c, p, t, tu), 1, hs,
+                                nullptr, nullptr, nullptr, nullptr, c->counters, s);
         }, &ms);
         if (st) return finish(st);
         if (ms < best_ms) {

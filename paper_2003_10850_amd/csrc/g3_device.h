@@ -63,6 +63,19 @@ __device__ __forceinline__ float sq_exact(float a) {
   return a * a;
 }
 
+// Wendland C6 in 3D with support radius h (Dehnen & Aly 2012): the
+// normalisation C = 1365 / (64 pi), and the radial factor of
+// F = (1/r) dW/dr = -22 C/h^5 (1-q)^7 (1 + 7q + 16q^2) as a function of
+// q = r/h: wendland_f(q) = (1-q)^7 (1 + 7q + 16q^2), zero at and beyond the
+// support.
+constexpr float kWendlandC = 6.7889530412636603f;
+constexpr float kWendlandF = -22.0f * 6.7889530412636603f;
+__device__ __forceinline__ float wendland_f(float q) {
+  const float t = fmaxf(1.0f - q, 0.0f);
+  const float t2 = t * t, t4 = t2 * t2;
+  return t4 * t2 * t * (1.0f + q * (7.0f + q * 16.0f));
+}
+
 }  // namespace g3
 
 namespace g3 {

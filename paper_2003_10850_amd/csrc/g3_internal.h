@@ -103,7 +103,7 @@ struct g3_ctx {
     void *p = nullptr;
     size_t bytes = 0;
   };
-  Buf scratch[24];
+  Buf scratch[32];
   // autotuned launch choices: (kind, floor(log2(targets))) -> choice
   std::map<std::pair<int, int>, g3::Tuning> tuning;
   unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
@@ -122,7 +122,7 @@ enum Slot {
   kSortKeys = 0, kSortVals, kSortTmp, kScanTmp, kCounts, kOffsets,
   kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
   kSnapKeys, kSnapKeysAlt, kGroups, kAdjSrc, kAdjNode, kAdjPQ, kAdjR,
-  kGasFlags, kGasSlot, kGasScan,
+  kGasFlags, kGasSlot, kGasScan, kIntAccH, kIntVp, kIntUp, kCondCh, kHydroExt,
   kNumSlots
 };
 static_assert(kNumSlots <= (int)(sizeof(g3_ctx::scratch) / sizeof(g3_ctx::Buf)),
@@ -199,10 +199,14 @@ struct Work {
   Groups gs;
   const int32_t *rows;
   int64_t max_groups;
+  const uint32_t *ntarg;  // device count of the targets (nullptr: every member)
 };
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
                  int64_t n_act, const int32_t *active, Work *w, hipStream_t s,
-                 int split = -1);
+                 int split = -1, const int32_t *bins = nullptr, int32_t kmin = 0);
+// (bins: the targets are instead the members whose particle's bins[caller
+// id] >= kmin, found on the device; active and n_act are then ignored.)
+
 
 // Grid of a persistent launch: the workgroups that can be resident at once
 // (occupancy of `kern` x compute units), or fewer if there are few groups.
@@ -224,9 +228,29 @@ hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_group
 hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, const void *h,
                              const float *rho, const float *omega, float gamma, int f64,
                              hipStream_t s);
+// ext (nullable): the improved-SPH switches' sorted inputs (alpha, Balsara
+// factor, u, rho) from launch_hydro_ext_prep, with conduction strength alpha_u.
 hipError_t launch_hydro(const Octree &gas, const Groups &gs, int64_t max_groups,
                         const SphParams &sp, float *acc, float *dudt, float *vsig,
-                        int32_t *npairs, hipStream_t s);
+                        int32_t *npairs, hipStream_t s, const float4 *ext = nullptr,
+                        float alpha_u = 0.0f);
+hipError_t launch_hydro_ext_prep(Octree &gas, const float *u, const float *rho,
+                                 const float *alpha, const float *balsara, float alpha0,
+                                 float4 *ext, hipStream_t s);
+// Velocity divergence and curl (switches.hip), after the hydro prep of vh
+// (v, h); rho, omega in caller order.
+hipError_t launch_velgrad(const Octree &gas, const Groups &gs, int64_t max_groups,
+                          int walk_leaf, const float *rho, const float *omega, float *div_v,
+                          float *curl_v, hipStream_t s);
+// The viscosity strength step and the Balsara factor of the rows `active`
+// (nullptr: rows 0..n-1), see switches.hip.
+struct SwitchStep {
+  float gamma, alpha_min, alpha_max, decay, eps, dt;
+};
+hipError_t launch_alpha_update(int64_t n, int64_t n_act, const int32_t *active,
+                               const SwitchStep &sw, int f64, const float *u, const void *h,
+                               const float *div_v, const float *curl_v, float *alpha,
+                               float *balsara, hipStream_t s);
 
 struct GravParams {
   float theta2, eps2, G;
@@ -269,6 +293,32 @@ hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_g
                               const GravParams &gp, const float *g_acc, const float *g_pot,
                               float4 *gsrc, float4 *gnode, double4 *pq, double *rr,
                               float *g_pos, float *g_mass, hipStream_t s);
+
+// Thermal conduction (conduction.hip): ch [n_gas] scratch of the sorted
+// pair inputs; the gas octree's node hmax must be refit from h first.
+hipError_t launch_conduction_prep(Octree &gas, const float *u, const void *h, int f64,
+                                  const float *rho, float kappa0, float kappa_exp,
+                                  float4 *ch, hipStream_t s);
+hipError_t launch_conduction(const Octree &gas, const Groups &gs, int64_t max_groups,
+                             int walk_leaf, const float4 *ch, float *dudt, int32_t *npairs,
+                             hipStream_t s);
+
+// Time integration (integrate.hip). One tick's particle update, see
+// k_update: a particle takes part iff every_particle or bin >= kmin.
+struct IntegUpdate {
+  int every_particle = 0, sum = 0, close = 0, rebin = 0, open = 0;
+  int32_t kmin = 0, depth = 0;
+  double dt_max = 0, eta_eps2 = 0, courant = 0;  // eta_eps2 = 2 eta eps
+};
+hipError_t launch_drift(void *pos, int f64, const float *vel, int64_t n, double tau,
+                        hipStream_t s);
+hipError_t launch_predict(int64_t n, const uint8_t *type, const float *vel, const float *u,
+                          const float *acc, const float *dudt, const int32_t *bin, int depth,
+                          int64_t T, double tau, float *vp, float *up, hipStream_t s);
+hipError_t launch_update(int64_t n, int f64, const IntegUpdate &up, const uint8_t *type,
+                         float *vel, float *u, float *acc, const float *acc_h, const float *dudt,
+                         const float *vsig, const void *h, int32_t *bin, hipStream_t s);
+hipError_t launch_store_count(const uint32_t *count, int64_t *out, hipStream_t s);
 
 // Walk lists: counts pass (list == nullptr) or fill pass.
 hipError_t launch_walk(const Octree &o, int kind, const Groups &gs, const int32_t *rows,

@@ -28,7 +28,6 @@ constexpr int kTile = kWave;
 // F = (1/r) dW/dr = -22 C/h^5 (1-q)^7 (1 + 7q + 16q^2).
 constexpr float kC = 6.7889530412636603f;        // 1365 / (64 pi)
 constexpr float kNeffSelf = 28.4375f;            // (4 pi / 3) C = 1365 / 48
-constexpr float kF = -22.0f * 6.7889530412636603f;
 
 // With s = ln h and q = r/h: w(q), wh = -3 w - q w' (so that d(h^-3 w)/ds =
 // h^-3 wh), and wss = q w' + q^2 w'' = d(-q w')/ds, the curvature term of
@@ -39,13 +38,6 @@ __device__ __forceinline__ void wc6_w_wh(float q, float &w, float &wh, float &ws
   w = t7 * t * (1.0f + q * (8.0f + q * (25.0f + q * 32.0f)));
   wh = t7 * (-3.0f + q * (-21.0f + q * (-29.0f + q * (133.0f + q * 448.0f))));
   wss = (q * q) * t6 * (-44.0f + q * (-264.0f + q * (132.0f + q * 3872.0f)));
-}
-
-// (1-q)^7 (1 + 7q + 16q^2), zero at and beyond the support
-__device__ __forceinline__ float wc6_f(float q) {
-  const float t = fmaxf(1.0f - q, 0.0f);
-  const float t2 = t * t, t4 = t2 * t2;
-  return t4 * t2 * t * (1.0f + q * (7.0f + q * 16.0f));
 }
 
 // First guess of h: descend from the root along target s while the child
@@ -499,21 +491,52 @@ __global__ void k_hydro_prep(const int32_t *__restrict__ perm, int64_t m,
   }
 }
 
+// The improved-SPH switches' sorted inputs: ext[s] = (alpha, Balsara
+// factor, u, rho) (alpha, balsara nullable: alpha0 and 1).
+__global__ void k_hydro_ext_prep(const int32_t *__restrict__ perm, int64_t m,
+                                 const float *__restrict__ u, const float *__restrict__ rho,
+                                 const float *__restrict__ alpha,
+                                 const float *__restrict__ balsara, float alpha0,
+                                 float4 *__restrict__ ext) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int j = perm[s];
+  ext[s] = make_float4(alpha ? alpha[j] : alpha0, balsara ? balsara[j] : 1.0f, u[j], rho[j]);
+}
+
+// rho_i u_i - rho_j u_j to a few ulp of itself: the second product split
+// into its FP32 rounding and the exact error of that rounding (an FMA), so
+// that nearly equal pressures do not cancel to the rounding of each.
+__device__ __forceinline__ float rho_u_difference(float ri, float ui, float rj, float uj) {
+  const float pj = rj * uj;
+  const float ej = __builtin_fmaf(rj, uj, -pj);
+  return __builtin_fmaf(ri, ui, -pj) - ej;
+}
+
 struct HydroTile {
   float4 xm[kWpb][kTile];
   float4 vh[kWpb][kTile];
   float4 aux[kWpb][kTile];
 };
 
-template <bool kF64>
+// The extra tile of the switches' inputs (a one-entry stand-in without them).
+template <bool kExt>
+struct ExtTile {
+  float4 e[kWpb][kExt ? kTile : 1];
+};
+
+// kExt: the improved-SPH switches (per-particle viscosity strengths and
+// Balsara factors, artificial conduction of strength alpha_u) from ext.
+template <bool kF64, bool kExt>
 __global__ __launch_bounds__(kBlock) void k_hydro(
     const Node *__restrict__ nodes, const float4 *__restrict__ xm,
     const double4 *__restrict__ x64, const double *__restrict__ h64,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
-    const int32_t *__restrict__ perm, const Groups gs, float alpha, int walk_leaf,
-    float slack, float *__restrict__ acc, float *__restrict__ dudt, float *__restrict__ vsig,
-    int32_t *__restrict__ npairs) {
+    const float4 *__restrict__ ext, const int32_t *__restrict__ perm, const Groups gs,
+    float alpha, float alpha_u, float gm1, int walk_leaf, float slack, float *__restrict__ acc,
+    float *__restrict__ dudt, float *__restrict__ vsig, int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
+  __shared__ ExtTile<kExt> E;
   __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
   __shared__ double th64[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
@@ -524,13 +547,14 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const bool valid = lane < grp.count;
   const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
   const float4 me = xm[s], mv = vh[s], ma = aux[s];
+  const float4 mx = kExt ? ext[s] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
   const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
   const double hi64 = kF64 ? h64[s] : 0.0;
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
   const float hi2 = valid ? sq_exact(hi) : -1.0f;
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
-  const float ki = kF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
+  const float ki = kWendlandF * (hinvi * hinvi) * (hinvi * hinvi) * hinvi;
   // totals with Neumaier compensation terms; per-tile partials are plain
   float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vs = 0.f;
   float cax = 0.f, cay = 0.f, caz = 0.f, cdu = 0.f;
@@ -566,13 +590,14 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   auto flush = [&](int nc) {
     {
       float4 vx = make_float4(INFINITY, INFINITY, INFINITY, 0.f), vv = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 va = vv;
+      float4 va = vv, ve = vv;
       double4 v64 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
       double h64c = 0.0;
       if (lane < nc) {
         vx = xm[cand];
         vv = vh[cand];
         va = aux[cand];
+        if constexpr (kExt) ve = ext[cand];
         if constexpr (kF64) {
           v64 = x64[cand];
           h64c = h64[cand];
@@ -588,6 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
         T.xm[w][slot] = vx;
         T.vh[w][slot] = vv;
         T.aux[w][slot] = va;
+        if constexpr (kExt) E.e[w][slot] = ve;
         if constexpr (kF64) {
           tiles64[w][slot] = v64;
           th64[w][slot] = h64c;
@@ -608,8 +634,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           const float rinv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * rinv;
           const float hj5 = (qa.w * qa.w) * (qa.w * qa.w) * qa.w;
-          const float gi = ki * wc6_f(r * hinvi);
-          const float gj = kF * hj5 * wc6_f(r * qa.w);
+          const float gi = ki * wendland_f(r * hinvi);
+          const float gj = kWendlandF * hj5 * wendland_f(r * qa.w);
           // x_ij = x_i - x_j = -(dx, dy, dz); v_ij = v_i - v_j
           const float vdx = (mv.x - qv.x) * dx + (mv.y - qv.y) * dy + (mv.z - qv.z) * dz;
           const float vx = -vdx;  // v_ij . x_ij
@@ -618,7 +644,14 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           const float vsig_ij = ci + qa.y - 3.0f * wneg;
           vs = fmaxf(vs, vsig_ij);
           // the hardware reciprocal (1 ulp) in place of an IEEE division
-          const float Pi = alpha * vsig_ij * (-wneg) * __builtin_amdgcn_rcpf(rhoi + qa.z);
+          const float rsum_inv = __builtin_amdgcn_rcpf(rhoi + qa.z);
+          float a_ij = alpha;
+          if constexpr (kExt) {
+            // (alpha_i + alpha_j)/2 times the mean Balsara factor
+            const float4 qe = E.e[w][k];
+            a_ij = 0.25f * (mx.x + qe.x) * (mx.y + qe.y);
+          }
+          const float Pi = a_ij * vsig_ij * (-wneg) * rsum_inv;
           const float gbar = 0.5f * (gi + gj);
           const float mj = q.w;
           const float coef = mj * (Ai * gi + qa.x * gj + Pi * gbar);  // a_i -= coef x_ij
@@ -626,6 +659,15 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           py += coef * dy;
           pz += coef * dz;
           pu += mj * (Ai * gi + 0.5f * Pi * gbar) * vx;
+          if constexpr (kExt) {
+            // artificial conduction: m_j alpha_u v_u (u_i - u_j) gbar r / rhobar,
+            // v_u = sqrt(|P_i - P_j| / rhobar), rhobar = (rho_i + rho_j)/2
+            const float4 qe = E.e[w][k];
+            const float two_inv = 2.0f * rsum_inv;  // 1 / rhobar
+            const float dP = gm1 * rho_u_difference(mx.w, mx.z, qe.w, qe.z);
+            const float vu = __builtin_amdgcn_sqrtf(fabsf(dP) * two_inv);
+            pu += mj * alpha_u * vu * (mx.z - qe.z) * gbar * r * two_inv;
+          }
         }
       }
     };
@@ -752,12 +794,22 @@ hipError_t launch_hydro_prep(Octree &gas, const float *vel, const float *u, cons
 
 hipError_t launch_hydro(const Octree &gas, const Groups &gs, int64_t max_groups,
                         const SphParams &sp, float *acc, float *dudt, float *vsig,
-                        int32_t *npairs, hipStream_t s) {
+                        int32_t *npairs, hipStream_t s, const float4 *ext, float alpha_u) {
   if (max_groups <= 0 || gas.nnodes == 0) return hipSuccess;
-  auto kern = sp.f64 ? k_hydro<true> : k_hydro<false>;
+  auto kern = sp.f64 ? (ext ? k_hydro<true, true> : k_hydro<true, false>)
+                     : (ext ? k_hydro<false, true> : k_hydro<false, false>);
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
-      gas.nodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, gas.perm, gs, sp.alpha,
-      sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
+      gas.nodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, ext, gas.perm, gs, sp.alpha,
+      alpha_u, sp.gamma - 1.0f, sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_hydro_ext_prep(Octree &gas, const float *u, const float *rho,
+                                 const float *alpha, const float *balsara, float alpha0,
+                                 float4 *ext, hipStream_t s) {
+  if (gas.n == 0) return hipSuccess;
+  k_hydro_ext_prep<<<nblk(gas.n, 256), 256, 0, s>>>(gas.perm, gas.n, u, rho, alpha, balsara,
+                                                    alpha0, ext);
   return hipGetLastError();
 }
 

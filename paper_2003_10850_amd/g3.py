@@ -26,8 +26,11 @@ EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats", "
            "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
            "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
+           "g3_conduction", "g3_velocity_gradients", "g3_viscosity_switch",
+           "g3_hydro_force_switches",
            "g3_density_backward", "g3_density_solve_backward", "g3_hydro_force_backward",
            "g3_gravity_backward",
+           "g3_integrate_start", "g3_system_step",
            "g3_autotune", "g3_tuning_get", "g3_tuning_set", "g3_tuning_save", "g3_tuning_load")
 
 
@@ -43,6 +46,25 @@ class g3_params(ctypes.Structure):
         d = {f: getattr(p, f) for f, _ in cls._fields_}
         d.update(over)
         return cls(**d)
+
+
+class g3_integ_params(ctypes.Structure):
+    _fields_ = [("dt_max", ctypes.c_double), ("courant", ctypes.c_double),
+                ("eta", ctypes.c_double), ("bin_depth", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class g3_state(ctypes.Structure):
+    """Device pointers of the particle state (integers from data_ptr())."""
+    _fields_ = [(f, ctypes.c_void_p) for f in
+                ("pos", "vel", "mass", "u", "type", "h", "rho", "omega", "acc", "dudt",
+                 "vsig", "pot", "bin")]
+
+
+class g3_switch_params(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("decay", ctypes.c_double), ("balsara_eps", ctypes.c_double),
+                ("alpha_u", ctypes.c_double), ("flags", ctypes.c_int32)]
 
 
 class G3Error(RuntimeError):
@@ -79,10 +101,18 @@ def lib():
             "g3_density": ([P, P, i64, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
             "g3_hydro_force": ([P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_gravity": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
+            "g3_conduction": ([P, P, i64, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P,
+                               P], ctypes.c_int),
+            "g3_velocity_gradients": ([P, P, i64, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+            "g3_viscosity_switch": ([P, i64, i32, i64, P, P, P, ctypes.c_double, P, P, P, P, P,
+                                     P, P], ctypes.c_int),
+            "g3_hydro_force_switches": ([P, P, i64, P, P, P] + [P] * 12, ctypes.c_int),
             "g3_density_backward": ([P, P, i64, P, P] + [P] * 10, ctypes.c_int),
             "g3_density_solve_backward": ([P, P, i64, P, P] + [P] * 7, ctypes.c_int),
             "g3_hydro_force_backward": ([P, P, i64, P, P] + [P] * 15, ctypes.c_int),
             "g3_gravity_backward": ([P, P, i64, P, P] + [P] * 5, ctypes.c_int),
+            "g3_integrate_start": ([P, P, i64, i32, P, P, P, P, P], ctypes.c_int),
+            "g3_system_step": ([P, P, i64, i32, P, P, P, P, P, P], ctypes.c_int),
             "g3_autotune": ([P, P, i64, P, P] + [P] * 6, ctypes.c_int),
             "g3_tuning_get": ([P, i32, i64, P, P, P], ctypes.c_int),
             "g3_tuning_set": ([P, i32, i64, i32, i32, i32], ctypes.c_int),
@@ -221,6 +251,39 @@ def g3_gravity(ctx, tree, n_act, active, params, acc, pot, nterms, stream):
     _check(ctx, st, "g3_gravity")
 
 
+def g3_conduction(ctx, tree, n_act, active, params, kappa0, kappa_exp, u, h, rho, dudt, npairs,
+                  stream):
+    st = lib().g3_conduction(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                             float(kappa0), float(kappa_exp), u, h, rho, dudt or None,
+                             npairs or None, stream)
+    _check(ctx, st, "g3_conduction")
+
+
+def g3_velocity_gradients(ctx, tree, n_act, active, params, vel, h, rho, omega, div_v, curl_v,
+                          stream):
+    st = lib().g3_velocity_gradients(ctx, tree, int(n_act), active or None,
+                                     ctypes.byref(params), vel, h, rho, omega, div_v or None,
+                                     curl_v or None, stream)
+    _check(ctx, st, "g3_velocity_gradients")
+
+
+def g3_viscosity_switch(ctx, n, h_type, n_act, active, params, sw, dt, u, h, div_v, curl_v,
+                        alpha, balsara, stream):
+    st = lib().g3_viscosity_switch(ctx, int(n), int(h_type), int(n_act), active or None,
+                                   ctypes.byref(params), ctypes.byref(sw), float(dt), u, h,
+                                   div_v, curl_v, alpha or None, balsara or None, stream)
+    _check(ctx, st, "g3_viscosity_switch")
+
+
+def g3_hydro_force_switches(ctx, tree, n_act, active, params, sw, vel, u, h, rho, omega, alpha,
+                            balsara, acc, dudt, vsig, npairs, stream):
+    st = lib().g3_hydro_force_switches(ctx, tree, int(n_act), active or None,
+                                       ctypes.byref(params), ctypes.byref(sw), vel, u, h, rho,
+                                       omega, alpha or None, balsara or None, acc or None,
+                                       dudt or None, vsig or None, npairs or None, stream)
+    _check(ctx, st, "g3_hydro_force_switches")
+
+
 def g3_density_backward(ctx, tree, n_act, active, params, h, rho, drho_dh, g_rho, g_drho_dh,
                         g_omega, g_pos, g_mass, g_h, stream):
     st = lib().g3_density_backward(ctx, tree, int(n_act), active or None, ctypes.byref(params),
@@ -254,6 +317,23 @@ def g3_gravity_backward(ctx, tree, n_act, active, params, g_acc, g_pot, g_pos, g
                                    g_acc or None, g_pot or None, g_pos or None, g_mass or None,
                                    stream)
     _check(ctx, st, "g3_gravity_backward")
+
+
+def g3_integrate_start(ctx, tree_ref, n, pos_t, state, box, params, iparams, stream):
+    """tree_ref: a ctypes.c_void_p holding the tree handle (None: a new one)."""
+    b = (ctypes.c_double * 4)(*[float(x) for x in box])
+    st = lib().g3_integrate_start(ctx, ctypes.byref(tree_ref), int(n), int(pos_t),
+                                  ctypes.byref(state), b, ctypes.byref(params),
+                                  ctypes.byref(iparams), stream)
+    _check(ctx, st, "g3_integrate_start")
+
+
+def g3_system_step(ctx, tree_ref, n, pos_t, state, box, params, iparams, tick_active, stream):
+    b = (ctypes.c_double * 4)(*[float(x) for x in box])
+    st = lib().g3_system_step(ctx, ctypes.byref(tree_ref), int(n), int(pos_t),
+                              ctypes.byref(state), b, ctypes.byref(params),
+                              ctypes.byref(iparams), tick_active or None, stream)
+    _check(ctx, st, "g3_system_step")
 
 
 G3_TUNE_DENSITY, G3_TUNE_HYDRO, G3_TUNE_GRAVITY = 0, 1, 2

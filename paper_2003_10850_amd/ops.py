@@ -9,6 +9,8 @@ allocates them).
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import g3
@@ -203,6 +205,104 @@ def hydro_force(tree: Tree, vel, u, h, rho, omega, params=None, active=None, out
     return res
 
 
+def conduction(tree: Tree, u, h, rho, kappa0: float, kappa_exp: float = 0.0, params=None,
+               active=None, out=None):
+    """Thermal conduction rate du/dt of the active gas particles (FP32 trees),
+    kappa = kappa0 u^kappa_exp; see g3_conduction."""
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    dev = tree.ctx.device
+    _need(h, torch.float32, (n,), "h", dev)
+    for name, t in (("u", u), ("rho", rho)):
+        _need(t, torch.float32, (n,), name, dev)
+    o = out or {}
+    res = dict(dudt=o.get("dudt", _zeros(tree, n)),
+               npairs=o.get("npairs", _zeros(tree, n, dtype=torch.int32)))
+    na, ap = _active(tree, active)
+    g3.g3_conduction(tree.ctx.handle, tree.handle, na, ap, p, kappa0, kappa_exp, _ptr(u),
+                     _ptr(h), _ptr(rho), _ptr(res["dudt"]), _ptr(res["npairs"]), _stream(dev))
+    return res
+
+
+def _switch_params(sw) -> "g3.g3_switch_params":
+    return g3.g3_switch_params(alpha_min=float(sw.alpha_min), alpha_max=float(sw.alpha_max),
+                               decay=float(sw.decay), balsara_eps=float(sw.balsara_eps),
+                               alpha_u=float(sw.alpha_u), flags=int(sw.flags))
+
+
+def velocity_gradients(tree: Tree, vel, h, rho, omega, params=None, active=None, out=None):
+    """Velocity divergence [n] and curl [n, 3] of the active gas particles
+    (FP32 trees); see g3_velocity_gradients."""
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    dev = tree.ctx.device
+    _need(vel, torch.float32, (n, 3), "vel", dev)
+    _need(h, torch.float32, (n,), "h", dev)
+    for name, t in (("rho", rho), ("omega", omega)):
+        _need(t, torch.float32, (n,), name, dev)
+    o = out or {}
+    res = dict(div=o.get("div", _zeros(tree, n)), curl=o.get("curl", _zeros(tree, n, 3)))
+    na, ap = _active(tree, active)
+    g3.g3_velocity_gradients(tree.ctx.handle, tree.handle, na, ap, p, _ptr(vel), _ptr(h),
+                             _ptr(rho), _ptr(omega), _ptr(res["div"]), _ptr(res["curl"]),
+                             _stream(dev))
+    return res
+
+
+def viscosity_switch(ctx: Context, sw, params, dt: float, u, h, div, curl, alpha=None,
+                     balsara=None, active=None):
+    """One step dt of the per-particle viscosity strength (alpha, updated in
+    place when given) and the Balsara factor (returned); see
+    g3_viscosity_switch."""
+    dev = ctx.device
+    n = int(u.shape[0])
+    _need(u, torch.float32, (n,), "u", dev)
+    if h.dtype not in (torch.float32, torch.float64):
+        raise TypeError("h must be float32 or float64")
+    _need(h, h.dtype, (n,), "h", dev)
+    _need(div, torch.float32, (n,), "div", dev)
+    _need(curl, torch.float32, (n, 3), "curl", dev)
+    if alpha is not None:
+        _need(alpha, torch.float32, (n,), "alpha", dev)
+    bf = balsara if balsara is not None else torch.zeros(n, dtype=torch.float32, device=dev)
+    if active is None:
+        na, ap = n, 0
+    else:
+        _need(active, torch.int32, (active.shape[0],), "active", dev)
+        na, ap = int(active.shape[0]), active.data_ptr()
+    ht = g3.G3_F64 if h.dtype == torch.float64 else g3.G3_F32
+    g3.g3_viscosity_switch(ctx.handle, n, ht, na, ap, g3.g3_params.of(params),
+                           _switch_params(sw), dt, _ptr(u), _ptr(h), _ptr(div), _ptr(curl),
+                           _ptr(alpha), _ptr(bf), _stream(dev))
+    return bf
+
+
+def hydro_force_switches(tree: Tree, vel, u, h, rho, omega, sw, alpha=None, balsara=None,
+                         params=None, active=None, out=None):
+    """The hydro force with per-particle viscosity strengths, Balsara
+    factors and artificial conduction; see g3_hydro_force_switches."""
+    p = g3.g3_params.of(params or tree.params)
+    n = tree.n
+    dev = tree.ctx.device
+    _need(vel, torch.float32, (n, 3), "vel", dev)
+    _need(h, tree.hdtype, (n,), "h", dev)
+    for name, t in (("u", u), ("rho", rho), ("omega", omega)):
+        _need(t, torch.float32, (n,), name, dev)
+    for name, t in (("alpha", alpha), ("balsara", balsara)):
+        if t is not None:
+            _need(t, torch.float32, (n,), name, dev)
+    o = out or {}
+    res = dict(acc=o.get("acc", _zeros(tree, n, 3)), dudt=o.get("dudt", _zeros(tree, n)),
+               vsig=o.get("vsig", _zeros(tree, n)),
+               npairs=o.get("npairs", _zeros(tree, n, dtype=torch.int32)))
+    na, ap = _active(tree, active)
+    g3.g3_hydro_force_switches(tree.ctx.handle, tree.handle, na, ap, p, _switch_params(sw),
+                               _ptr(vel), _ptr(u), _ptr(h), _ptr(rho), _ptr(omega),
+                               _ptr(alpha), _ptr(balsara), _ptr(res["acc"]), _ptr(res["dudt"]),
+                               _ptr(res["vsig"]), _ptr(res["npairs"]), _stream(dev))
+    return res
+
+
 def gravity(tree: Tree, params=None, active=None, out=None):
     p = g3.g3_params.of(params or tree.params)
     n = tree.n
@@ -384,3 +484,62 @@ def hydro_force_ad(tree: Tree, pos, vel, mass, u, h, rho, omega, params=None, ac
 def gravity_ad(tree: Tree, pos, mass, params=None, active=None):
     """Differentiable (acc, pot); gradients flow to pos and mass."""
     return _GravityFn.apply(tree, params, active, pos, mass)
+
+
+class Integrator:
+    """The kick-drift-kick leapfrog on power-of-two time bins of one particle
+    set (g3_integrate_start, g3_system_step). The state tensors are updated
+    in place by the library; ``pos`` (float32 or float64) and ``h`` share a
+    dtype, the rest are float32 (``bin`` int32, ``type`` uint8)."""
+
+    FIELDS = ("pos", "vel", "mass", "u", "type", "h", "rho", "omega", "acc", "dudt", "vsig",
+              "pot", "bin")
+
+    def __init__(self, ctx: Context, pos, vel, mass, u, type=None, box=(0.0, 0.0, 0.0, 1.0),
+                 params=None, dt_max=1e-3, bin_depth=3, courant=0.15, eta=0.025):
+        dev = ctx.device
+        n = int(pos.shape[0])
+        if pos.dtype not in (torch.float32, torch.float64):
+            raise TypeError("pos must be float32 or float64")
+        self.ctx, self.n, self.params, self.box = ctx, n, params, [float(x) for x in box]
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.pos = _need(pos, pos.dtype, (n, 3), "pos", dev)
+        self.vel = _need(vel, torch.float32, (n, 3), "vel", dev)
+        self.mass = _need(mass, torch.float32, (n,), "mass", dev)
+        self.u = _need(u, torch.float32, (n,), "u", dev)
+        self.type = None if type is None else _need(type, torch.uint8, (n,), "type", dev)
+        self.h = torch.zeros(n, dtype=pos.dtype, device=dev)
+        self.rho = torch.zeros(n, **f32)
+        self.omega = torch.ones(n, **f32)
+        self.acc = torch.zeros(n, 3, **f32)
+        self.dudt = torch.zeros(n, **f32)
+        self.vsig = torch.zeros(n, **f32)
+        self.pot = torch.zeros(n, **f32)
+        self.bin = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.pos_t = g3.G3_F64 if pos.dtype == torch.float64 else g3.G3_F32
+        self.iparams = g3.g3_integ_params(dt_max=float(dt_max), courant=float(courant),
+                                          eta=float(eta), bin_depth=int(bin_depth), flags=0)
+        self.tree = ctypes.c_void_p()
+        self.started = False
+
+    def _state(self):
+        return g3.g3_state(**{f: _ptr(getattr(self, f)) for f in self.FIELDS})
+
+    def start(self):
+        """Forces and bins of the current (synchronised) state."""
+        g3.g3_integrate_start(self.ctx.handle, self.tree, self.n, self.pos_t, self._state(),
+                              self.box, g3.g3_params.of(self.params), self.iparams,
+                              _stream(self.ctx.device))
+        self.started = True
+
+    def system_step(self, tick_active=None):
+        """One system step; tick_active (int64 [2^B] on the device, optional)
+        receives the number of active particles at each tick."""
+        if not self.started:
+            self.start()
+        if tick_active is not None:
+            _need(tick_active, torch.int64, (1 << self.iparams.bin_depth,), "tick_active",
+                  self.ctx.device)
+        g3.g3_system_step(self.ctx.handle, self.tree, self.n, self.pos_t, self._state(),
+                          self.box, g3.g3_params.of(self.params), self.iparams,
+                          _ptr(tick_active), _stream(self.ctx.device))

@@ -150,7 +150,7 @@ def test_enomem_leaves_nothing_enqueued_and_recovers():
         hacc, du, vs, npair = sentinel((n, 3)), sentinel((n,)), sentinel((n,)), \
             sentinel((n,), torch.int32)
         off = sentinel((int(act.shape[0]) + 1,), torch.int64)
-        lst = sentinel((1 << 20,), torch.int32)
+        lst = sentinel((1 << 23,), torch.int32)  # room for every gravity list entry
         total = ctypes.c_int64(-1)
         P = ctypes.byref(r.p)
         calls = {
@@ -168,6 +168,7 @@ def test_enomem_leaves_nothing_enqueued_and_recovers():
                                            ctypes.byref(total), stream()),
         }
         outs = [h, rho, nn, acc, pot, nt, hacc, du, vs, npair, off, lst]
+        torch.cuda.synchronize()  # the sentinel fills are done before the calls
         # a fresh ctx owns no scratch yet: each call's first allocation fails
         assert r.L.g3_ctx_inject(r.ctx, g3.G3_INJECT_ALLOC, 0) == g3.G3_OK
         for name, call in calls.items():

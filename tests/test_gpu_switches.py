@@ -1,0 +1,150 @@
+"""The improved-SPH switches on the GPU against the oracle: velocity
+divergence and curl (g3_velocity_gradients), the Balsara factor and the
+viscosity strength step (g3_viscosity_switch), and the hydro force with
+per-particle strengths, Balsara factors and artificial conduction
+(g3_hydro_force_switches).
+
+Bars: sums of pair terms within 1e-5 of the L1 sum S of their terms (FP32
+pair arithmetic, compensated across tiles; S_div, S_curl, S for the
+acceleration, S_du for du/dt); pair counts exact; the per-particle switch
+within 2e-6 relative (FP32 expf and sqrtf of the same FP32 inputs the
+oracle reads). With one strength, unit factors and no conduction the
+switches' hydro force is g3_hydro_force (the same pair arithmetic, to
+1e-6 of S). Active subsets write only their rows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_10850_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+def dev_t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def case():
+    from paper_2003_10850_amd import ops
+    ctx = ops.Context(torch.device("cuda", 0))
+    w = inputs.plummer(n=60000, n_spheres=4, seed=17, n_ngb=64.0, eps=1e-3)
+    pos32, vel32, m32, u32 = w.as_f32()
+    # a converging flow on top of the random velocities, so that the
+    # viscosity source and the Balsara factor vary
+    vel32 = (vel32 - 0.8 * (pos32 - 0.5)).astype(np.float32)
+    rng = np.random.default_rng(3)
+    u32 = rng.uniform(0.5, 2.0, w.n).astype(np.float32)
+    tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(w.type), tuple(w.box), w.params)
+    d = ops.density(tree)
+    torch.cuda.synchronize()
+    gas = np.nonzero(w.type == 0)[0]
+    gt = oracle.Tree(pos32.astype(np.float64), m32.astype(np.float64), w.box, type=w.type,
+                     gas_only=True)
+    return dict(ctx=ctx, w=w, tree=tree, d=d, vel=vel32, u=u32, gas=gas, gt=gt)
+
+
+def test_velocity_gradients_match_the_oracle(case):
+    from paper_2003_10850_amd import ops
+    c = case
+    g = ops.velocity_gradients(c["tree"], dev_t(c["vel"]), c["d"]["h"], c["d"]["rho"],
+                               c["d"]["omega"])
+    torch.cuda.synchronize()
+    ref = oracle.velgrad(c["gt"], c["w"].params, c["vel"], host(c["d"]["h"]),
+                         host(c["d"]["rho"]), host(c["d"]["omega"]), active=c["gas"])
+    gas = c["gas"]
+    ed = np.abs(host(g["div"])[gas] - ref["div"][gas]) / ref["S_div"][gas]
+    ec = np.abs(host(g["curl"])[gas] - ref["curl"][gas]).max(1) / ref["S_curl"][gas]
+    print(f"velocity gradients: div {ed.max():.2e}, curl {ec.max():.2e} of S", flush=True)
+    assert ed.max() < TOL and ec.max() < TOL
+    # a ragged subset writes only its rows, with the full call's values
+    sub = np.sort(np.random.default_rng(5).choice(gas, gas.size // 7, replace=False))
+    sent = torch.full((c["w"].n,), -7.0, dtype=torch.float32, device=DEV)
+    gs = ops.velocity_gradients(c["tree"], dev_t(c["vel"]), c["d"]["h"], c["d"]["rho"],
+                                c["d"]["omega"], active=dev_t(sub.astype(np.int32)),
+                                out=dict(div=sent))
+    torch.cuda.synchronize()
+    got = host(gs["div"])
+    mask = np.zeros(c["w"].n, bool)
+    mask[sub] = True
+    assert np.all(got[~mask] == -7.0)
+    assert (np.abs(got[sub] - ref["div"][sub]) / ref["S_div"][sub]).max() < TOL
+
+
+def test_viscosity_switch_matches_the_oracle(case):
+    from paper_2003_10850_amd import ops
+    c = case
+    sw = inputs.SwitchParams()
+    g = ops.velocity_gradients(c["tree"], dev_t(c["vel"]), c["d"]["h"], c["d"]["rho"],
+                               c["d"]["omega"])
+    n = c["w"].n
+    alpha0 = np.random.default_rng(6).uniform(sw.alpha_min, sw.alpha_max, n).astype(np.float32)
+    alpha = dev_t(alpha0)
+    gas = c["gas"]
+    act = dev_t(gas.astype(np.int32))
+    dt = 2e-3
+    bf = ops.viscosity_switch(c["ctx"], sw, c["w"].params, dt, dev_t(c["u"]), c["d"]["h"],
+                              g["div"], g["curl"], alpha=alpha, active=act)
+    torch.cuda.synchronize()
+    div, curl, h = host(g["div"]), host(g["curl"]), host(c["d"]["h"])
+    fr = oracle.balsara(div, curl, c["u"], h, c["w"].params.gamma, sw.balsara_eps)
+    ar = oracle.alpha_step(alpha0, dt, div, fr, c["u"], h, c["w"].params.gamma, sw.alpha_min,
+                           sw.alpha_max, sw.decay)
+    ef = np.abs(host(bf)[gas] - fr[gas]).max()
+    ea = (np.abs(host(alpha)[gas] - ar[gas]) / ar[gas]).max()
+    print(f"viscosity switch: Balsara {ef:.2e} (absolute), alpha {ea:.2e} (relative); "
+          f"Balsara range {fr[gas].min():.3f}..{fr[gas].max():.3f}, "
+          f"alpha range {ar[gas].min():.3f}..{ar[gas].max():.3f}", flush=True)
+    assert ef < 2e-6 and ea < 2e-6
+    assert fr[gas].min() < 0.2 and fr[gas].max() > 0.8  # both regimes are exercised
+    # rows outside the list keep their values
+    rest = np.setdiff1d(np.arange(n), gas)
+    np.testing.assert_array_equal(host(alpha)[rest], alpha0[rest])
+
+
+@pytest.mark.parametrize("alpha_u", [0.0, 1.0])
+def test_hydro_force_switches_matches_the_oracle(case, alpha_u):
+    from paper_2003_10850_amd import ops
+    import dataclasses
+    c = case
+    sw = dataclasses.replace(inputs.SwitchParams(), alpha_u=alpha_u)
+    n = c["w"].n
+    rng = np.random.default_rng(7)
+    alpha = rng.uniform(sw.alpha_min, sw.alpha_max, n).astype(np.float32)
+    bal = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    d = c["d"]
+    hy = ops.hydro_force_switches(c["tree"], dev_t(c["vel"]), dev_t(c["u"]), d["h"], d["rho"],
+                                  d["omega"], sw, alpha=dev_t(alpha), balsara=dev_t(bal))
+    torch.cuda.synchronize()
+    gas = c["gas"]
+    ref = oracle.hydro_switches(c["gt"], c["w"].params, c["vel"], c["u"], host(d["h"]),
+                                host(d["rho"]), host(d["omega"]), alpha=alpha, balsara=bal,
+                                alpha_u=alpha_u, active=gas)
+    np.testing.assert_array_equal(host(hy["npairs"])[gas], ref["npairs"][gas])
+    ea = np.linalg.norm(host(hy["acc"])[gas] - ref["acc"][gas], axis=1) / ref["S"][gas]
+    eu = np.abs(host(hy["dudt"])[gas] - ref["dudt"][gas]) / ref["S_du"][gas]
+    print(f"hydro with switches (alpha_u {alpha_u}): acc {ea.max():.2e}, du/dt {eu.max():.2e}",
+          flush=True)
+    assert ea.max() < TOL and eu.max() < TOL
+    np.testing.assert_allclose(host(hy["vsig"])[gas], ref["vsig"][gas], rtol=1e-6)
+    # one strength, unit factors, no conduction: exactly the plain hydro force
+    plain = ops.hydro_force(c["tree"], dev_t(c["vel"]), dev_t(c["u"]), d["h"], d["rho"],
+                            d["omega"])
+    same = ops.hydro_force_switches(c["tree"], dev_t(c["vel"]), dev_t(c["u"]), d["h"],
+                                    d["rho"], d["omega"],
+                                    dataclasses.replace(sw, alpha_u=0.0))
+    torch.cuda.synchronize()
+    ref0 = oracle.hydro(c["gt"], c["w"].params, c["vel"], c["u"], host(d["h"]), host(d["rho"]),
+                        host(d["omega"]), active=gas)
+    da = np.linalg.norm(host(plain["acc"])[gas] - host(same["acc"])[gas], axis=1)
+    assert (da / ref0["S"][gas]).max() < 1e-6
+    np.testing.assert_array_equal(host(plain["npairs"])[gas], host(same["npairs"])[gas])
