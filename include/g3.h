@@ -374,6 +374,27 @@ int g3_gravity(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                float *pot, int32_t *nterms, void *stream);
 
 /*
+ * g3_gravity without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, kernels and results as g3_gravity.
+ * The call's work tables (active-set compaction, group table, per-XCD
+ * queues) live in a fixed region of 64 MiB per GPU, a device array that
+ * each GPU running the library holds until the process ends; it is looked
+ * up at g3_ctx_create. A call whose tables need more returns G3_EINVAL and
+ * enqueues nothing: with an active list the tables take about 20 bytes per
+ * member of the all-particle octree (36 with groups split at octree cells,
+ * see g3_tuning_set), so up to about 3.3e6 members fit; with every particle
+ * active (active == NULL) a few bytes per target. The tree must have been
+ * built (builds allocate). Every call on one GPU shares that GPU's region
+ * and the call clears what it needs at its start, so results never depend
+ * on an earlier call; calls whose work overlaps on one GPU (concurrent
+ * streams, or several host threads) race on the region and must be
+ * serialised by the caller. */
+int g3_gravity_noalloc(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
+                       const int32_t *active, const g3_params *p, float *acc,
+                       float *pot, int32_t *nterms, void *stream);
+
+/*
  * Time integration around the interaction phase. The paper's code moves
  * only the particles that are active at a step, on adaptive steps, and
  * drifts the tree between rebuilds instead of rebuilding it (paper section 1

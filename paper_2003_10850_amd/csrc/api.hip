@@ -39,6 +39,17 @@ void *scratch(g3_ctx *c, int slot, size_t bytes) {
   return b.p;
 }
 
+void *scratch_in(g3_ctx *c, Arena *a, int slot, size_t bytes) {
+  if (!a) return scratch(c, slot, bytes);
+  if (a->slot_p[slot]) return bytes <= a->slot_bytes[slot] ? a->slot_p[slot] : nullptr;
+  const size_t start = (a->used + 255) & ~(size_t)255;
+  if (start > a->cap || bytes > a->cap - start) return nullptr;
+  a->used = start + bytes;
+  a->slot_p[slot] = a->base + start;
+  a->slot_bytes[slot] = bytes;
+  return a->slot_p[slot];
+}
+
 namespace {
 
 struct DeviceGuard {
@@ -262,8 +273,14 @@ struct WorkBufs {
 // listed: targets come from a mark pass (an active list or a bin rule)
 // instead of being every member; max_t bounds their number.
 int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t max_t_in, bool listed,
-                 int split, WorkBufs *b) {
-  auto no_room = [&](const char *msg) { return fail(c, G3_ENOMEM, msg); };
+                 int split, WorkBufs *b, Arena *arena) {
+  // out of memory: G3_ENOMEM from the ctx's scratch, G3_EINVAL (the call is
+  // too large) from a caller-given region
+  auto no_room = [&](const char *msg) {
+    return arena ? fail(c, G3_EINVAL, "the work tables need more than the allocation-free "
+                                      "region holds")
+                 : fail(c, G3_ENOMEM, msg);
+  };
   *b = WorkBufs();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
@@ -280,28 +297,28 @@ int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t max_t_in,
   uint32_t *stmp = nullptr, *mark = nullptr, *slot = nullptr;
   int32_t *rowp1 = nullptr, *tg = nullptr, *rw = nullptr;
   if (listed || split_on) {
-    stmp = (uint32_t *)scratch(c, kScanTmp, scan_tmp_elems(scan_n) * sizeof(uint32_t));
+    stmp = (uint32_t *)scratch_in(c, arena, kScanTmp, scan_tmp_elems(scan_n) * sizeof(uint32_t));
     if (!stmp) return no_room("device allocation of the scan scratch failed");
   }
   if (listed) {
-    mark = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
-    slot = (uint32_t *)scratch(c, kOffsets, (m + 1) * sizeof(uint32_t));
-    rowp1 = (int32_t *)scratch(c, kCounts, (m + 2) * sizeof(int32_t));
-    tg = (int32_t *)scratch(c, kTargets, (m + 1) * sizeof(int32_t));
-    rw = (int32_t *)scratch(c, kRows, (m + 1) * sizeof(int32_t));
+    mark = (uint32_t *)scratch_in(c, arena, kFlags, (m + 2) * sizeof(uint32_t));
+    slot = (uint32_t *)scratch_in(c, arena, kOffsets, (m + 1) * sizeof(uint32_t));
+    rowp1 = (int32_t *)scratch_in(c, arena, kCounts, (m + 2) * sizeof(int32_t));
+    tg = (int32_t *)scratch_in(c, arena, kTargets, (m + 1) * sizeof(int32_t));
+    rw = (int32_t *)scratch_in(c, arena, kRows, (m + 1) * sizeof(int32_t));
     if (!mark || !slot || !rowp1 || !tg || !rw)
       return no_room("device allocation of the active-set scratch failed");
   }
   // tstart, gstart [max_seg + 2] (a scan writes one past its n), seg_snap
   // [max_seg + 1], nseg, queue [8]
   const size_t tab_elems = 3 * ((size_t)max_seg + 2) + 1 + 8;
-  int32_t *tab = (int32_t *)scratch(c, kGroups, tab_elems * sizeof(int32_t));
+  int32_t *tab = (int32_t *)scratch_in(c, arena, kGroups, tab_elems * sizeof(int32_t));
   if (!tab) return no_room("device allocation of the group table failed");
   uint32_t *flags = nullptr, *segid = nullptr, *gcnt = nullptr;
   if (split_on) {
-    flags = (uint32_t *)scratch(c, kCounts, (m + 2) * sizeof(uint32_t));
-    segid = (uint32_t *)scratch(c, kFlags, (m + 2) * sizeof(uint32_t));
-    gcnt = (uint32_t *)scratch(c, kIds, (max_seg + 2) * sizeof(uint32_t));
+    flags = (uint32_t *)scratch_in(c, arena, kCounts, (m + 2) * sizeof(uint32_t));
+    segid = (uint32_t *)scratch_in(c, arena, kFlags, (m + 2) * sizeof(uint32_t));
+    gcnt = (uint32_t *)scratch_in(c, arena, kIds, (max_seg + 2) * sizeof(uint32_t));
     if (!flags || !segid || !gcnt)
       return no_room("device allocation of the group table failed");
     // the compaction's buffers must not have moved (same slots, same sizes)
@@ -316,13 +333,13 @@ int reserve_work(g3_ctx *c, const g3_tree *t, const Octree &o, int64_t max_t_in,
 
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
                  int64_t n_act, const int32_t *active, Work *w, hipStream_t s, int split,
-                 const int32_t *bins, int32_t kmin) {
+                 Arena *arena, const int32_t *bins, int32_t kmin) {
   *w = Work();
   const int64_t m = o.n;
   if (m == 0) return G3_OK;
   WorkBufs b;
   const bool listed = active || bins;
-  const int st = reserve_work(c, t, o, active ? n_act : m, listed, split, &b);
+  const int st = reserve_work(c, t, o, active ? n_act : m, listed, split, &b, arena);
   if (st) return st;
   const int n_snap = t->n_snap;
   const int64_t max_t = b.max_t, max_seg = b.max_seg;
@@ -429,6 +446,14 @@ int g3_ctx_create(g3_ctx **out, int device) {
     return G3_ENOMEM;
   }
   std::memset(c->pinned, 0, 8 * sizeof(int64_t));
+  // the allocation-free calls' region on this device (looked up once per
+  // device, with the device current)
+  if (noalloc_init(device) != (int)hipSuccess) {
+    (void)hipFree(c->counters);
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return G3_EHIP;
+  }
   *out = c;
   return G3_OK;
 }
@@ -1083,6 +1108,33 @@ int g3_hydro_force_switches(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
   return G3_OK;
 }
 
+int g3_gravity_noalloc(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
+                       const g3_params *p, float *acc, float *pot, int32_t *nterms,
+                       void *stream) {
+  if (!c) return G3_EINVAL;
+  int st = active_args_ok(c, t, n_act, active, "g3_gravity_noalloc");
+  if (st) return st;
+  if (!params_ok(p)) return fail(c, G3_EINVAL, "g3_gravity_noalloc: bad params");
+  DeviceGuard g(c->device);
+  st = check_pending(c);
+  if (st) return st;
+  Arena arena;
+  arena.base = (char *)noalloc_region(c->device);
+  arena.cap = kNoAllocBytes;
+  if (!arena.base) return fail(c, G3_ESTATE, "g3_gravity_noalloc: no region on this device");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const Octree &o = t->all;
+  const Tuning tu = tuning_for(c, kTuneGravity, active ? std::min<int64_t>(n_act, o.n) : o.n);
+  Work wk;
+  st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s, tu.split, &arena);
+  if (st) return st;
+  hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_gravity_noalloc");
+  c->err.clear();
+  return G3_OK;
+}
+
 // ---- time integration ----
 
 static bool integ_args_ok(g3_ctx *c, int64_t n, int32_t pos_t, const g3_state *st,
@@ -1126,7 +1178,8 @@ static int tick_forces(g3_ctx *c, g3_tree *t, int64_t n, const g3_state *st,
     const Tuning td = tuning_for(c, kTuneDensity, gas.n);
     const SphParams spd = sph_params(c, p, t, td);
     Work wd;
-    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wd, s, td.split, bins, kmin);
+    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wd, s, td.split, nullptr, bins,
+                      kmin);
     if (rc) return rc;
     e = launch_density(gas, wd.gs, wd.max_groups, spd, 1, st->h, st->rho, nullptr, st->omega,
                        nullptr, c->counters, s);
@@ -1145,7 +1198,8 @@ static int tick_forces(g3_ctx *c, g3_tree *t, int64_t n, const g3_state *st,
     if (e == hipSuccess) e = refit_hmax(gas, s);
     if (e != hipSuccess) return hip_fail(c, e, "hydro prep at a tick");
     Work wh;
-    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wh, s, th.split, bins, kmin);
+    rc = prepare_work(c, t, gas, t->iperm_gas, gas.n, nullptr, &wh, s, th.split, nullptr, bins,
+                      kmin);
     if (rc) return rc;
     e = launch_hydro(gas, wh.gs, wh.max_groups, sp, acc_h, st->dudt, st->vsig, nullptr, s);
     if (e != hipSuccess) return hip_fail(c, e, "hydro at a tick");
@@ -1153,7 +1207,8 @@ static int tick_forces(g3_ctx *c, g3_tree *t, int64_t n, const g3_state *st,
   const Octree &all = t->all;
   const Tuning tg = tuning_for(c, kTuneGravity, all.n);
   Work wg;
-  rc = prepare_work(c, t, all, t->iperm_all, all.n, nullptr, &wg, s, tg.split, bins, kmin);
+  rc = prepare_work(c, t, all, t->iperm_all, all.n, nullptr, &wg, s, tg.split, nullptr, bins,
+                    kmin);
   if (rc) return rc;
   e = launch_gravity(all, wg.gs, wg.max_groups, grav_params(p, t), st->acc, st->pot, nullptr, s);
   if (e == hipSuccess && count_out) e = launch_store_count(wg.ntarg, count_out, s);

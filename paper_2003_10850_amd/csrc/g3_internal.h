@@ -201,12 +201,34 @@ struct Work {
   int64_t max_groups;
   const uint32_t *ntarg;  // device count of the targets (nullptr: every member)
 };
+// A caller-given device region that stands in for the ctx's scratch slots:
+// each slot is carved from it once per call, 256-byte aligned, in the order
+// the slots are first asked for; a slot asked for again gets the same bytes
+// (it must not need more than the first time). `base` is a device address.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  void *slot_p[kNumSlots] = {};
+  size_t slot_bytes[kNumSlots] = {};
+};
+// The slot's buffer from the arena when one is given (nullptr when the
+// arena is full), else from the ctx's scratch.
+void *scratch_in(g3_ctx *c, Arena *a, int slot, size_t bytes);
+
 int prepare_work(g3_ctx *c, const g3_tree *t, const Octree &o, const int32_t *iperm,
                  int64_t n_act, const int32_t *active, Work *w, hipStream_t s,
-                 int split = -1, const int32_t *bins = nullptr, int32_t kmin = 0);
+                 int split = -1, Arena *arena = nullptr, const int32_t *bins = nullptr,
+                 int32_t kmin = 0);
 // (bins: the targets are instead the members whose particle's bins[caller
 // id] >= kmin, found on the device; active and n_act are then ignored.)
 
+// Bytes of device memory that the allocation-free calls may use per GPU,
+// and that region's address on `device` (nullptr until noalloc_init has
+// run for it). noalloc_init looks the address up once per device, with
+// that device current; later calls return the kept address.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+int noalloc_init(int device);  // hipError_t of the lookup
+void *noalloc_region(int device);
 
 // Grid of a persistent launch: the workgroups that can be resident at once
 // (occupancy of `kern` x compute units), or fewer if there are few groups.

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
 EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats", "g3_ctx_inject",
            "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
            "g3_tree_export",
-           "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity",
+           "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity", "g3_gravity_noalloc",
            "g3_conduction", "g3_velocity_gradients", "g3_viscosity_switch",
            "g3_hydro_force_switches",
            "g3_density_backward", "g3_density_solve_backward", "g3_hydro_force_backward",
@@ -101,6 +101,7 @@ def lib():
             "g3_density": ([P, P, i64, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
             "g3_hydro_force": ([P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_gravity": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
+            "g3_gravity_noalloc": ([P, P, i64, P, P, P, P, P, P], ctypes.c_int),
             "g3_conduction": ([P, P, i64, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P,
                                P], ctypes.c_int),
             "g3_velocity_gradients": ([P, P, i64, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -282,6 +283,12 @@ def g3_hydro_force_switches(ctx, tree, n_act, active, params, sw, vel, u, h, rho
                                        omega, alpha or None, balsara or None, acc or None,
                                        dudt or None, vsig or None, npairs or None, stream)
     _check(ctx, st, "g3_hydro_force_switches")
+
+
+def g3_gravity_noalloc(ctx, tree, n_act, active, params, acc, pot, nterms, stream):
+    st = lib().g3_gravity_noalloc(ctx, tree, int(n_act), active or None, ctypes.byref(params),
+                                  acc or None, pot or None, nterms or None, stream)
+    _check(ctx, st, "g3_gravity_noalloc")
 
 
 def g3_density_backward(ctx, tree, n_act, active, params, h, rho, drho_dh, g_rho, g_drho_dh,
