@@ -460,8 +460,8 @@ int g3_ctx_create(g3_ctx **out, int device) {
 
 static void free_octree(Octree &o) {
   for (void *p : {(void *)o.keys, (void *)o.perm, (void *)o.xm, (void *)o.nodes, (void *)o.mom,
-                  (void *)o.vh, (void *)o.aux, (void *)o.x64, (void *)o.h64, (void *)o.c64,
-                  (void *)o.soff, (void *)o.nroot})
+                  (void *)o.gnodes, (void *)o.vh, (void *)o.aux, (void *)o.x64, (void *)o.h64,
+                  (void *)o.c64, (void *)o.soff, (void *)o.nroot})
     if (p) (void)hipFree(p);
   o = Octree();
 }

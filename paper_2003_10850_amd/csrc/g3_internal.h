@@ -27,6 +27,18 @@ static_assert(sizeof(Node) == 64, "node must be 64 bytes");
 
 constexpr int kLeafBit = 256;
 
+// The gravity walk's copy of a node, 32 bytes: two nodes per 64-byte line,
+// so a descent to cur + 1 often finds its node in the line just loaded.
+//   com_m   centre of mass, mass
+//   meta    skip, first member, member count of a leaf (-1: internal), the
+//           cube side l as bits; l = side of the root cube * 2^-level
+//           exactly, so the level is the difference of the two exponents
+struct __align__(16) GNode {
+  float4 com_m;
+  int4 meta;
+};
+static_assert(sizeof(GNode) == 32, "gravity node must be 32 bytes");
+
 // One octree over a subset of the particles (all of them, or the gas ones),
 // with the members in Morton order.
 struct Octree {
@@ -38,6 +50,7 @@ struct Octree {
   int32_t *perm = nullptr;   // [n] sorted position -> caller id
   float4 *xm = nullptr;      // [n] sorted (x, y, z, m)
   Node *nodes = nullptr;     // [nnodes] preorder
+  GNode *gnodes = nullptr;   // [nnodes] the gravity walk's copy (all-particle octree)
   double4 *mom = nullptr;    // [nnodes] FP64 (M, M x, M y, M z)
   // SPH member data in sorted order (gas octree only, filled by the calls)
   float4 *vh = nullptr;   // (vx, vy, vz, h)

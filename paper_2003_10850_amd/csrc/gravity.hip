@@ -55,7 +55,7 @@ __device__ __forceinline__ bool open_accept64(double l, double theta, double4 c,
 // offsets could disagree with the FP64 one, the FP64 test decides.
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_gravity(
-    const Node *__restrict__ nodes, const double4 *__restrict__ c64n,
+    const GNode *__restrict__ nodes, const double4 *__restrict__ c64n,
     const float4 *__restrict__ xm, const double4 *__restrict__ x64,
     const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
     float theta2, float eps2, float G, int inside_test, double theta64,
@@ -74,7 +74,9 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const int64_t t = grp.t0 + lane;
   const bool valid = lane < grp.count;
   const int s = valid ? (gs.targets ? gs.targets[t] : (int)t) : 0;
-  const double side = kF64 ? gs.sbox[grp.snap].w : 0.0;  // root cube side
+  const double side = gs.sbox[grp.snap].w;  // root cube side
+  // a node's level from its cube side: l = (float)side * 2^-level exactly
+  const int root_exp = ilogbf((float)side);
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
   // mixed precision: every offset is the FP64 difference from this target,
@@ -141,7 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   int resume = valid ? grp.root : INT32_MAX;  // lanes idle while cur < resume
   int cur = grp.root;
   while (cur < grp.end) {
-    const Node nd = nodes[cur];
+    const GNode nd = nodes[cur];
+    const float l = __int_as_float(nd.meta.w);
     const bool act = cur >= resume;
     double4 cn = make_double4(0, 0, 0, 0);
     float r2;
@@ -152,16 +155,16 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
                        sub_exact(nd.com_m.z, xi.z));
     }
-    bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
+    bool accept = act && open_accept(l, theta2, r2);
     if constexpr (kF64) {
       // the FP32 r2 of exact-to-2^-24 offsets is within about 2^-22 of the
       // FP64 value (relative); inside 2^-19 of the threshold FP64 decides
-      const float lhs = nd.hi_l.w * nd.hi_l.w, rhs = theta2 * r2;
+      const float lhs = l * l, rhs = theta2 * r2;
       if (act && fabsf(lhs - rhs) <= rhs * 1.9073486e-6f)
-        accept = open_accept64(ldexp(side, -(nd.meta.w & 255)), theta64, cn, p64);
+        accept = open_accept64(ldexp(side, -(root_exp - ilogbf(l))), theta64, cn, p64);
     }
     if (inside_test) {
-      const int level = nd.meta.w & 255;
+      const int level = root_exp - ilogbf(l);
       const uint64_t nk = keys[nd.meta.y];
       const bool inside = ((ki ^ nk) >> (3 * (kMaxLevel - level))) == 0ull;
       accept = accept && !inside;
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       cur = nd.meta.x;
       continue;
     }
-    if (!(nd.meta.w & kLeafBit)) {
+    if (nd.meta.z < 0) {  // internal
       ++cur;
       continue;
     }
@@ -244,8 +247,9 @@ hipError_t launch_gravity(const Octree &all, const Groups &gs, int64_t max_group
                           hipStream_t s) {
   if (max_groups <= 0 || all.nnodes == 0) return hipSuccess;
   auto kern = gp.f64 ? k_gravity<true> : k_gravity<false>;
+  if (!all.gnodes) return hipErrorInvalidValue;
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
-      all.nodes, all.c64, all.xm, all.x64, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
+      all.gnodes, all.c64, all.xm, all.x64, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
       gp.inside_test, gp.theta, acc, pot, nterms);
   return hipGetLastError();
 }

@@ -324,6 +324,19 @@ __global__ void k_hmax_level(Node *__restrict__ nodes, int64_t nnodes,
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// The gravity walk's 32-byte node copies (after the moments).
+__global__ void k_gnodes(const Node *__restrict__ nodes, int64_t nnodes,
+                         GNode *__restrict__ gnodes) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnodes) return;
+  const Node nd = nodes[k];
+  GNode g;
+  g.com_m = nd.com_m;
+  g.meta = make_int4(nd.meta.x, nd.meta.y, (nd.meta.w & kLeafBit) ? nd.meta.z : -1,
+                     __float_as_int(nd.hi_l.w));
+  gnodes[k] = g;
+}
+
 }  // namespace
 
 // Selects the members (gas only for the gas octree), sorts them and builds
@@ -441,13 +454,16 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   const int64_t nnodes = (int64_t)(uint32_t)(pin[0] & 0xffffffffll);
   const int32_t maxl = (int32_t)(pin[1] & 0xffffffffll);
   if (nnodes <= 0 || nnodes >= (int64_t)INT32_MAX) { c->err = "node count out of range"; return G3_EHIP; }
-  if (nnodes > o.cap_nodes) {
+  const bool grav = (&o == &t->all);
+  if (nnodes > o.cap_nodes || (grav && !o.gnodes)) {
     if (o.nodes) (void)hipFree(o.nodes);
     if (o.mom) (void)hipFree(o.mom);
-    o.nodes = nullptr; o.mom = nullptr; o.cap_nodes = 0;
+    if (o.gnodes) (void)hipFree(o.gnodes);
+    o.nodes = nullptr; o.mom = nullptr; o.gnodes = nullptr; o.cap_nodes = 0;
     const int64_t cap = nnodes + nnodes / 8 + 64;
     if (dev_malloc(c, (void **)&o.nodes, cap * sizeof(Node)) != hipSuccess ||
-        dev_malloc(c, (void **)&o.mom, cap * sizeof(double4)) != hipSuccess) {
+        dev_malloc(c, (void **)&o.mom, cap * sizeof(double4)) != hipSuccess ||
+        (grav && dev_malloc(c, (void **)&o.gnodes, cap * sizeof(GNode)) != hipSuccess)) {
       c->err = "device allocation of the octree nodes failed";
       return G3_ENOMEM;
     }
@@ -472,6 +488,7 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
   for (int l = maxl; l >= 0; --l)
     k_moments_level<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, o.mom, f64 ? o.c64 : nullptr,
                                                      nnodes, o.xm, x64, l);
+  if (o.gnodes) k_gnodes<<<nblk(nnodes), kBlock, 0, s>>>(o.nodes, nnodes, o.gnodes);
   e = hipGetLastError();
   if (e != hipSuccess) { c->err = std::string("tree build launch: ") + hipGetErrorString(e); return G3_EHIP; }
   return G3_OK;
@@ -493,6 +510,7 @@ int refit_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, const float 
     k_moments_level<<<nblk(o.nnodes), kBlock, 0, s>>>(o.nodes, o.mom, t->f64 ? o.c64 : nullptr,
                                                        o.nnodes, o.xm, t->f64 ? o.x64 : nullptr,
                                                        l);
+  if (o.gnodes) k_gnodes<<<nblk(o.nnodes), kBlock, 0, s>>>(o.nodes, o.nnodes, o.gnodes);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     c->err = std::string("tree refit launch: ") + hipGetErrorString(e);
