@@ -444,10 +444,14 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
 
     # the mixed-precision forest: FP64 positions and h, the same step
     tree64 = ops.Tree(ctx, T(b.pos), mass, typ, boxes, b.params, snap_off=b.snap_off)
-    h64 = h0.double()
+    # the state this path carries: its own FP64 h (solved to the same
+    # tolerance from the FP32 one), rho and omega
+    base64 = ops.density(tree64, h=h0.double())
+    h64 = base64["h"].clone()
     H64 = torch.zeros(n, dtype=torch.float64, device=dev)
-    B["rho"].copy_(rho0)
-    B["omega"].copy_(om0)
+    B["rho"].copy_(base64["rho"])
+    B["omega"].copy_(base64["omega"])
+    del base64
 
     def step64():
         H64.copy_(h64)
@@ -534,7 +538,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
         "fp32_roofline": step_roofline((i_d, i_h, i_g), graph_ms),
         "mixed_precision": {"ms_per_step": mixed_ms, "value": i64 / (mixed_ms * 1e-3),
                             "fp32_roofline": step_roofline(k64, mixed_ms),
-                            "path": "FP64 positions and h, FP32 offsets from each target, "
+                            "path": "FP64 positions and h, two-float FP32 offsets from each group's FP64 centre, "
                                     "FP64 decisions in the error band, eager calls"},
         "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
         "h_nonconverged": nonconv,
@@ -650,7 +654,7 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
         "interactions_per_step": inter,
         "fp32_roofline": step_roofline(kinds, ms),
         "h_nonconverged": nonconv,
-        "path": "mixed precision: FP64 positions, FP32 offsets from each target, compensated "
+        "path": "mixed precision: FP64 positions, two-float FP32 offsets from each group's FP64 centre, compensated "
                 "FP32 sums, FP64 moments and h solve, FP64 decisions in the error band",
     }
 

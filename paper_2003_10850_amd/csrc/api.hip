@@ -472,6 +472,7 @@ static void free_tree(g3_tree *t) {
   if (t->iperm_gas) (void)hipFree(t->iperm_gas);
   if (t->coff) (void)hipFree(t->coff);
   if (t->sbox) (void)hipFree(t->sbox);
+  if (t->absmax) (void)hipFree(t->absmax);
   free_octree(t->all);
   free_octree(t->gas);
   delete t;
@@ -620,16 +621,12 @@ static int build_forest_body(g3_ctx *c, g3_tree *t, int32_t n_snap, const int64_
   t->box.assign(box, box + 4 * (size_t)n_snap);
   t->leaf = p->leaf_size;
   t->f64 = pos_t == G3_F64;
-  // FP64 positions are walked through their FP32 copies: pad every pruning
-  // radius by a bound on the rounding of coordinates as large as the boxes'
-  double amax = 0.0, smax = 0.0;
-  for (int32_t k = 0; k < n_snap; ++k) {
-    const double *b = box + 4 * k;
-    for (int a = 0; a < 3; ++a) amax = std::max(amax, std::max(std::fabs(b[a]), std::fabs(b[a] + b[3])));
-    smax = std::max(smax, b[3]);
-  }
+  double smax = 0.0;
+  for (int32_t k = 0; k < n_snap; ++k) smax = std::max(smax, box[4 * k + 3]);
   t->max_side = smax;
-  t->slack = t->f64 ? (float)std::ldexp(amax, -20) : 0.0f;
+  if (t->f64 && !t->absmax &&
+      dev_malloc(c, (void **)&t->absmax, sizeof(unsigned)) != hipSuccess)
+    return fail(c, G3_ENOMEM, "g3_build_forest: allocation failed");
   std::vector<double4> hb(n_snap);
   for (int32_t k = 0; k < n_snap; ++k)
     hb[k] = make_double4(box[4 * k], box[4 * k + 1], box[4 * k + 2], box[4 * k + 3]);
@@ -649,6 +646,11 @@ static int build_forest_body(g3_ctx *c, g3_tree *t, int32_t n_snap, const int64_
   if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest");
   st = build_octree(c, t, t->gas, pos, t->f64, mass, mgas, s, type);
   if (st) return st;
+  // FP64 positions are walked through their FP32 copies: the walks pad
+  // every pruning radius by a bound on their rounding, from the largest
+  // coordinate actually held (positions may lie outside the boxes)
+  e = update_absmax(t, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_build_forest");
   return G3_OK;
 }
 
@@ -677,6 +679,8 @@ int g3_refit_tree(g3_ctx *c, g3_tree *t, const void *pos, const float *mass, voi
   if (st) return st;
   st = refit_octree(c, t, t->gas, pos, mass, s);
   if (st) return st;
+  const hipError_t e = update_absmax(t, s);
+  if (e != hipSuccess) return hip_fail(c, e, "g3_refit_tree");
   c->err.clear();
   return G3_OK;
 }
@@ -804,7 +808,7 @@ static SphParams sph_params(const g3_ctx *c, const g3_params *p, const g3_tree *
   // candidate streams exist for the FP32 density only
   sp.streams = (!t->f64 && tu.streams == 4) ? 4 : 1;
   sp.f64 = t->f64;
-  sp.slack = t->slack;
+  sp.absmax = t->absmax;
   return sp;
 }
 
@@ -1308,6 +1312,8 @@ int g3_system_step(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3
     if (rc) return rc;
     rc = refit_octree(c, t, t->gas, st->pos, st->mass, s);
     if (rc) return rc;
+    e = update_absmax(t, s);
+    if (e != hipSuccess) return hip_fail(c, e, "g3_system_step refit");
     // active at T: bins k with 2^(B-k) | T, i.e. k >= B - min(tz(T), B)
     int tz = 0;
     while (tz < B && ((T >> tz) & 1) == 0) ++tz;

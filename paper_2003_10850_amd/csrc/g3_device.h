@@ -138,4 +138,40 @@ __device__ __forceinline__ int next_group(const Groups &gs, int &range) {
   return -1;
 }
 
+// Mixed precision: the FP64 centre of a wave's group of targets, the first
+// target's FP64 position moved to the middle of the box of the targets'
+// FP32-rounded offsets from it (any FP64 point serves; the middle halves the
+// largest offset). Wave-uniform; invalid lanes take no part.
+__device__ __forceinline__ double4 group_centre(double4 c0, double4 p, bool valid) {
+  float3 a = make_float3((float)(p.x - c0.x), (float)(p.y - c0.y), (float)(p.z - c0.z));
+  float3 lo = valid ? a : make_float3(INFINITY, INFINITY, INFINITY);
+  float3 hi = valid ? a : make_float3(-INFINITY, -INFINITY, -INFINITY);
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) {
+    lo.x = fminf(lo.x, __shfl_xor(lo.x, m));
+    lo.y = fminf(lo.y, __shfl_xor(lo.y, m));
+    lo.z = fminf(lo.z, __shfl_xor(lo.z, m));
+    hi.x = fmaxf(hi.x, __shfl_xor(hi.x, m));
+    hi.y = fmaxf(hi.y, __shfl_xor(hi.y, m));
+    hi.z = fmaxf(hi.z, __shfl_xor(hi.z, m));
+  }
+  // held in scalar registers: every lane computed the same value
+  auto su = [](double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi32 << 32) | lo32));
+  };
+  return make_double4(su(c0.x + (double)(0.5f * (lo.x + hi.x))),
+                      su(c0.y + (double)(0.5f * (lo.y + hi.y))),
+                      su(c0.z + (double)(0.5f * (lo.z + hi.z))), 0.0);
+}
+
+// o = fl32(x - c) and its residual l = fl32((x - c) - o).
+__device__ __forceinline__ void two_float_offset(double4 x, double4 c, float3 &o, float3 &l) {
+  const double dx = x.x - c.x, dy = x.y - c.y, dz = x.z - c.z;
+  o = make_float3((float)dx, (float)dy, (float)dz);
+  l = make_float3((float)(dx - (double)o.x), (float)(dy - (double)o.y), (float)(dz - (double)o.z));
+}
+
 }  // namespace g3

@@ -102,7 +102,11 @@ struct g3_tree {
   int32_t leaf = 8;
   bool built = false;  // false until a build has completed (a failed build leaves it false)
   int32_t f64 = 0;   // positions (and h) are FP64: the mixed-precision path
-  float slack = 0;   // bound on the rounding of the FP32 position copies
+  // FP64 trees: the largest |coordinate| of any member, as the bits of a
+  // non-negative float (device word, set at every build and refit); the
+  // walks pad their radii by 2^-20 of it, a bound on the rounding of the
+  // FP32 position copies they prune with
+  unsigned *absmax = nullptr;
   int32_t *iperm_all = nullptr;  // [n] caller id -> position in `all`
   int32_t *iperm_gas = nullptr;  // [n] caller id -> position in `gas`, or -1
   g3::Octree all, gas;
@@ -175,6 +179,8 @@ int build_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, int f64,
 int refit_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, const float *mass,
                  hipStream_t s);
 hipError_t refit_hmax(Octree &o, hipStream_t s);
+// FP64 trees: t->absmax = max |coordinate| over the members of t->all.
+hipError_t update_absmax(g3_tree *t, hipStream_t s);
 
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 
@@ -253,7 +259,7 @@ struct SphParams {
   int walk_leaf;  // SPH walks take subtrees of at most this many members whole
   int streams;    // density candidate streams per wave (1 or 4; FP32 trees)
   int f64;        // FP64 positions and h: mixed-precision kernels
-  float slack;    // walk pruning pad for FP32 copies of FP64 positions (0 if FP32)
+  const unsigned *absmax;  // FP64 trees: device bits of max |x| (walk pad 2^-20 of it)
 };
 
 hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_groups,

@@ -49,10 +49,12 @@ __device__ __forceinline__ bool open_accept64(double l, double theta, double4 c,
   return l * l < theta * theta * ((dx * dx + dy * dy) + dz * dz);
 }
 
-// Mixed precision (kF64): positions are stored in FP64 and every term works
-// on the FP32 rounding of its FP64 offset from the target; the node centres
-// of mass come from FP64 moments. Near the threshold, where the FP32 test on
-// offsets could disagree with the FP64 one, the FP64 test decides.
+// Mixed precision (kF64): positions are stored in FP64 and the node centres
+// of mass come from FP64 moments. Each term works on the FP32 difference of
+// the source's and the target's FP32 offsets from the group's FP64 centre;
+// the opening test on the FP32 rounding of the node's FP64 offset from the
+// target, and near the threshold, where that test could disagree with the
+// FP64 one, the FP64 test decides.
 template <bool kF64>
 __global__ __launch_bounds__(kBlock) void k_gravity(
     const GNode *__restrict__ nodes, const double4 *__restrict__ c64n,
@@ -61,7 +63,6 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     float theta2, float eps2, float G, int inside_test, double theta64,
     float *__restrict__ acc, float *__restrict__ pot, int32_t *__restrict__ nterms) {
   __shared__ Entry tiles[kWpb][kTile];
-  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];  // FP64 source positions
   // running totals (acc, pot) and their Neumaier compensations, and the term
   // count, one slot per lane: touched only at a flush, so the walk loop
   // carries no per-lane sums from one node to the next
@@ -79,12 +80,18 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
   const int root_exp = ilogbf((float)side);
   const float4 me = xm[s];
   const float3 xi = make_float3(me.x, me.y, me.z);
-  // mixed precision: every offset is the FP64 difference from this target,
-  // rounded to FP32 (exact to 2^-24 of itself)
+  // mixed precision: tile entries hold FP32 offsets from the group's FP64
+  // centre and each term takes the FP32 difference of the source's and this
+  // target's offsets; the opening test takes the FP32 rounding of the FP64
+  // difference from this target (FP64 near the threshold)
   const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
+  const double4 c64 = kF64 ? group_centre(x64[gs.targets ? gs.targets[grp.t0] : grp.t0], p64, valid)
+                           : make_double4(0, 0, 0, 0);
+  const float3 xo = kF64 ? make_float3((float)(p64.x - c64.x), (float)(p64.y - c64.y),
+                                       (float)(p64.z - c64.z))
+                         : xi;
   const uint64_t ki = keys[s];
   Entry *tile = tiles[w];
-  double4 *tile64 = tiles64[w];
 
   tot[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
   comp[w][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -106,17 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       // ones, and masks the inverse distance
       const int32_t use = __builtin_amdgcn_sbfe((int32_t)maskw[k * (int)(sizeof(Entry) / 4)],
                                                 bitpos, 1u);
-      float dx, dy, dz;
-      if constexpr (kF64) {
-        const double4 q = tile64[k];
-        dx = (float)(q.x - p64.x);
-        dy = (float)(q.y - p64.y);
-        dz = (float)(q.z - p64.z);
-      } else {
-        dx = ep.x - xi.x;
-        dy = ep.y - xi.y;
-        dz = ep.z - xi.z;
-      }
+      const float dx = ep.x - xo.x, dy = ep.y - xo.y, dz = ep.z - xo.z;
       const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
       // masked here (not the mass), so that an unused entry adds exact
       // zeros even at r2 = 0 (the own entry with zero softening)
@@ -180,9 +177,11 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       if (lane == 0) {
         Entry e;
         e.p = nd.com_m;
+        if constexpr (kF64)
+          e.p = make_float4((float)(cn.x - c64.x), (float)(cn.y - c64.y), (float)(cn.z - c64.z),
+                            nd.com_m.w);
         e.meta = make_int4(-1, (int)(uint32_t)amask, (int)(uint32_t)(amask >> 32), 0);
         tile[tc] = e;
-        if constexpr (kF64) tile64[tc] = cn;
       }
       ++tc;
     }
@@ -204,7 +203,11 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       if (lane < take) {
         Entry e;
         e.p = xm[st + lane];  // FP32 mass (and FP32 position on the plain path)
-        if constexpr (kF64) tile64[tc + lane] = x64[st + lane];
+        if constexpr (kF64) {
+          const double4 q = x64[st + lane];
+          e.p = make_float4((float)(q.x - c64.x), (float)(q.y - c64.y), (float)(q.z - c64.z),
+                            e.p.w);
+        }
         e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
         tile[tc + lane] = e;
       }

@@ -76,12 +76,31 @@ __device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
   return (dx * dx + dy * dy) + dz * dz < H * H;
 }
 
-// Mixed precision: each pair works on the FP32 rounding of the FP64
-// difference x_j - x_i, so every offset is exact to 2^-24 of itself and
-// r2 = fmaf(dz,dz, fmaf(dy,dy, dx dx)) is within about 2^-22 of the FP64
-// value, relative. Inside the band 2^-19 H^2 around the threshold the FP64
-// test decides, which keeps every decision exact.
-constexpr float kBand64 = 1.9073486e-6f;  // 2^-19
+// The mixed precision of the density and hydro kernels works on FP32 offsets
+// from one FP64 centre per group (the position of its first target), each
+// carried as two floats: o = fl32(x - c) and its residual l = fl32((x - c) - o)
+// (the FP64 difference itself is exact to 2^-53 |x - c|). A candidate is
+// first tested on the high parts: d = fl(o_j - o_i) differs from x_j - x_i
+// by at most 2^-24 (|x_j - x_i| + 2E) per axis, E the largest offset
+// component of the group's targets and candidates, so
+// r2 = fmaf(dz,dz,fmaf(dy,dy,dx dx)) is within 2^-24 (5 r^2 + 7 E r) of the
+// FP64 value, below 2^-20 (h^2 + E h) near the threshold (r ~ h). Only a
+// candidate inside 2^-19 (h^2 + E h) of it or closer takes the low parts,
+// d' = d + fl(l_j - l_i), exact to about 2^-23 |x_j - x_i| + 2^-47 E per
+// axis whatever the group's extent; its r2 then stands within 2^-21 h^2 of
+// the FP64 value near the threshold, and inside the band 2^-19 (h^2 +
+// 2^-20 E h) the FP64 positions decide, which keeps every decision exact.
+// The sums take r2 of d', so their accuracy does not depend on E either.
+constexpr float kBandOff = 1.9073486e-6f;  // 2^-19
+
+// A group whose targets' offsets stay within kFineExt times its smallest h
+// skips the low parts (outside the FP64 band): there the high parts alone
+// give r2 within 2^-22 (1.5 r^2 + 1.8 E r) + 2^-24 3 r^2 of the FP64 value,
+// about 2^-20 h^2 near the threshold, of the order of the FP32 sums' own
+// rounding; wider groups take the low parts for every pair near or inside
+// the threshold.
+constexpr float kFineExt = 1.0f;
+
 
 // Candidate streams per wave (kQ > 1, FP32 path): the lanes are split into
 // kQ quarters of 64/kQ targets, and a leaf or small subtree the walk accepts
@@ -95,15 +114,20 @@ template <bool kF64, int kQ>
 __global__ __launch_bounds__(kBlock) void k_density(
     const Node *__restrict__ nodes, const float4 *__restrict__ xm,
     const double4 *__restrict__ x64, const int32_t *__restrict__ perm, const Groups gs,
-    float n_ngb, float tol, int solve, int max_iter, int walk_leaf, float slack,
+    float n_ngb, float tol, int solve, int max_iter, int walk_leaf,
+    const unsigned *__restrict__ absmax,
     void *__restrict__ hptr, float *__restrict__ rho, float *__restrict__ drho_dh,
     float *__restrict__ omega, int32_t *__restrict__ nngb,
     unsigned long long *__restrict__ counters) {
   using HT = typename std::conditional<kF64, double, float>::type;
   HT *h = (HT *)hptr;
   static_assert(kQ == 1 || !kF64, "candidate streams are for the FP32 path");
-  __shared__ float4 tiles[kWpb][(kF64 || kQ > 1) ? 1 : kTile];
-  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
+  // FP64 positions: the walk's pad for the rounding of the FP32 copies
+  const float slack = kF64 ? ldexpf(__uint_as_float(*absmax), -20) : 0.0f;
+  __shared__ float4 tiles[kWpb][kQ > 1 ? 1 : kTile];
+  // mixed precision: the low parts of the offsets, and the sorted index of
+  // each entry as the fourth component
+  __shared__ float4 tlos[kWpb][kF64 ? kTile : 1];
   __shared__ int32_t ring[kWpb][kQ > 1 ? kQ : 1][kQ > 1 ? kRing : 1];
   __shared__ float4 qtile[kWpb][kQ > 1 ? kQ : 1][kQ > 1 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
@@ -119,8 +143,22 @@ __global__ __launch_bounds__(kBlock) void k_density(
   const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
   const int cid = perm[s];
   float4 *tile = tiles[w];
-  double4 *tile64 = tiles64[w];
-  const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
+  float4 *tlo64 = tlos[w];
+  // mixed precision: the group's FP64 centre (the middle of its targets'
+  // box, wave-uniform), this target's two-float offset from it and the
+  // group's largest offset component; the target's FP64 position is read
+  // again by the rare FP64 decisions rather than held in registers
+  double4 c64 = make_double4(0, 0, 0, 0);
+  float3 xo = make_float3(0.f, 0.f, 0.f), xl = xo;
+  float ext = 0.0f;
+  if constexpr (kF64) {
+    const double4 p64 = x64[s];
+    c64 = group_centre(x64[gs.targets ? gs.targets[grp.t0] : grp.t0], p64, valid);
+    two_float_offset(p64, c64, xo, xl);
+    ext = valid ? fmaxf(fabsf(xo.x), fmaxf(fabsf(xo.y), fabsf(xo.z))) : 0.0f;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) ext = fmaxf(ext, __shfl_xor(ext, m));
+  }
 
   HT hcur = valid ? h[cid] : HT(1);
   if (solve) {
@@ -151,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     // walk pruning radius: exact for FP32 positions, padded by the rounding
     // of FP32 absolute coordinates when the positions are FP64
     const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(hf + slack) : h2);
-    const float band = kF64 ? h2 * kBand64 : 0.0f;
+
     const float hinv = 1.0f / hf;
     // sums of m w, m wh and m wss: plain per tile, compensated across tiles
     float sw = 0.0f, swh = 0.0f, sss = 0.0f, csw = 0.0f, cswh = 0.0f, csss = 0.0f;
@@ -184,21 +222,43 @@ __global__ __launch_bounds__(kBlock) void k_density(
       thi = make_float4(su(thi.x), su(thi.y), su(thi.z), 0.f);
       hmax2 = su(hmax2);
     }
+    // mixed precision: the low parts are taken within 2^-19 (h^2 + E h) of
+    // the threshold and the FP64 test decides within 2^-19 (h^2 + 2^-20 E h),
+    // E bounding every offset component of this pass's targets and
+    // candidates (the candidates lie within the walk's radius of a target)
+    const float eh = kF64 ? (ext + sqrtf(fmaxf(hmax2, 0.0f))) * hf : 0.0f;
+    const float band = kBandOff * (h2 + eh);
+    const float band2 = kBandOff * (h2 + ldexpf(eh, -20));
+    bool fine = false;  // mixed: this pass skips the low parts
+    if constexpr (kF64) {
+      float hmin = live ? hf : INFINITY;
+#pragma unroll
+      for (int m = 1; m < kWave; m <<= 1) hmin = fminf(hmin, __shfl_xor(hmin, m));
+      fine = ext <= kFineExt * hmin;
+    }
     auto flush = [&](int nc) {
       // unused slots sit at infinity and fail every neighbour test
       if constexpr (kF64) {
-        double4 v64 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-        float4 v = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        float4 o = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        float4 v = o, l = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane < nc) {
-          v64 = x64[cand];
+          const double4 v64 = x64[cand];
           v = xm[cand];
+          o = make_float4((float)(v64.x - c64.x), (float)(v64.y - c64.y), (float)(v64.z - c64.z),
+                          v.w);
+          l = make_float4((float)((v64.x - c64.x) - (double)o.x),
+                          (float)((v64.y - c64.y) - (double)o.y),
+                          (float)((v64.z - c64.z) - (double)o.z), __int_as_float(cand));
         }
         const bool keep = lane < nc && box_dist2(make_float3(v.x, v.y, v.z), tlo, thi) < hmax2;
         const uint64_t km = __ballot(keep);
         const int slot = (int)__builtin_amdgcn_mbcnt_hi(
             (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
-        tile64[lane] = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-        if (keep) tile64[slot] = v64;
+        tile[lane] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        if (keep) {
+          tile[slot] = o;
+          tlo64[slot] = l;
+        }
         nc = __popcll(km);
       } else if constexpr (kQ == 1) {
         const float4 v = (lane < nc) ? xm[cand] : make_float4(INFINITY, INFINITY, INFINITY, 0.f);
@@ -229,15 +289,36 @@ __global__ __launch_bounds__(kBlock) void k_density(
         pss += mj * wsv;
         ++cnt;
       };
-      if constexpr (kF64) {
+      if (kF64 && !fine) {
         for (int k = 0; k < nc; ++k) {
-          // offset from this target: the FP64 difference rounded to FP32
-          const double4 q = tile64[k];
+          // the FP32 difference of the high parts, then near the threshold
+          // or inside the low parts too; close to it the FP64 positions decide
+          const float4 q = tile[k];
+          float dx = sub_exact(q.x, xo.x), dy = sub_exact(q.y, xo.y), dz = sub_exact(q.z, xo.z);
+          if (dist2_exact(dx, dy, dz) < h2 + band) {
+            const float4 l = tlo64[k];
+            dx += sub_exact(l.x, xl.x);
+            dy += sub_exact(l.y, xl.y);
+            dz += sub_exact(l.z, xl.z);
+            const float r2 = dist2_exact(dx, dy, dz);
+            const bool in = fabsf(r2 - h2) <= band2
+                                ? within64(x64[s], x64[__float_as_int(l.w)], (double)hcur)
+                                : r2 < h2;
+            if (in) pair(r2, q.w);
+          }
+        }
+      } else if constexpr (kF64) {
+        for (int k = 0; k < nc; ++k) {
+          // a narrow group: the high parts; near the threshold the FP64
+          // positions decide
+          const float4 q = tile[k];
           const float r2 =
-              dist2_exact((float)(q.x - p64.x), (float)(q.y - p64.y), (float)(q.z - p64.z));
-          bool in = r2 < h2;
-          if (fabsf(r2 - h2) <= band) in = within64(p64, q, (double)hcur);
-          if (in) pair(r2, (float)q.w);
+              dist2_exact(sub_exact(q.x, xo.x), sub_exact(q.y, xo.y), sub_exact(q.z, xo.z));
+          if (r2 < h2 + band) {
+            const bool in = r2 < h2 - band ||
+                            within64(x64[s], x64[__float_as_int(tlo64[k].w)], (double)hcur);
+            if (in) pair(r2, q.w);
+          }
         }
       } else {
         // entries are read four at a time, one group ahead of their tests,
@@ -417,12 +498,25 @@ __global__ __launch_bounds__(kBlock) void k_density(
         HT hn;
         if (N == n_ngb) hn = hcur;
         else if (slope > 0.05f) {
-          const HT f = (HT)log((HT)N / (HT)n_ngb);
-          const float curv = sss / sw - slope * slope;
-          const HT den = HT(1) - f * (HT)(curv / (2.0f * slope * slope));
-          HT d = -f / (HT)slope;
-          if (den > HT(0.5) && den < HT(2)) d /= den;
-          hn = hcur * (HT)exp(d);
+          if constexpr (kF64) {
+            // FP64 h: the step in FP32 transcendentals, accurate to about
+            // 1e-7 of itself (N is an FP32 sum; N - N_ngb is exact near the
+            // root), applied to h in FP64 as h + h expm1(d); FP64 log and
+            // exp here would set the kernel's register count
+            const float f = log1pf((N - n_ngb) / n_ngb);
+            const float curv = sss / sw - slope * slope;
+            const float den = 1.0f - f * (curv / (2.0f * slope * slope));
+            float d = -f / slope;
+            if (den > 0.5f && den < 2.0f) d /= den;
+            hn = hcur + hcur * (HT)expm1f(d);
+          } else {
+            const HT f = (HT)log((HT)N / (HT)n_ngb);
+            const float curv = sss / sw - slope * slope;
+            const HT den = HT(1) - f * (HT)(curv / (2.0f * slope * slope));
+            HT d = -f / (HT)slope;
+            if (den > HT(0.5) && den < HT(2)) d /= den;
+            hn = hcur * (HT)exp(d);
+          }
         } else hn = below ? HT(2) * hcur : HT(0.5) * hcur;
         // converged when the Newton correction itself is below half the
         // tolerance (h then lies within it of the root), or the bracket has
@@ -533,13 +627,17 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     const double4 *__restrict__ x64, const double *__restrict__ h64,
     const float4 *__restrict__ vh, const float4 *__restrict__ aux,
     const float4 *__restrict__ ext, const int32_t *__restrict__ perm, const Groups gs,
-    float alpha, float alpha_u, float gm1, int walk_leaf, float slack, float *__restrict__ acc,
+    float alpha, float alpha_u, float gm1, int walk_leaf, const unsigned *__restrict__ absmax,
+    float *__restrict__ acc,
     float *__restrict__ dudt, float *__restrict__ vsig, int32_t *__restrict__ npairs) {
   __shared__ HydroTile T;
   __shared__ ExtTile<kExt> E;
-  __shared__ double4 tiles64[kWpb][kF64 ? kTile : 1];
-  __shared__ double th64[kWpb][kF64 ? kTile : 1];
+  // mixed precision: the low parts of the offsets, and the sorted index of
+  // each entry as the fourth component
+  __shared__ float4 tlos[kWpb][kF64 ? kTile : 1];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  // FP64 positions: the walk's pad for the rounding of the FP32 copies
+  const float slack = kF64 ? ldexpf(__uint_as_float(*absmax), -20) : 0.0f;
   int range = 0;
   for (int g; (g = next_group(gs, range)) >= 0;) {
   const Group grp = group_at(gs, g);
@@ -549,8 +647,28 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   const float4 me = xm[s], mv = vh[s], ma = aux[s];
   const float4 mx = kExt ? ext[s] : make_float4(0.f, 0.f, 0.f, 0.f);
   const float3 xi = make_float3(me.x, me.y, me.z);  // FP32 position (box tests)
-  const double4 p64 = kF64 ? x64[s] : make_double4(0, 0, 0, 0);
   const double hi64 = kF64 ? h64[s] : 0.0;
+  // mixed precision: two-float offsets from the group's FP64 centre, as in
+  // the density; gext is the group's largest target offset component
+  double4 c64 = make_double4(0, 0, 0, 0);
+  float3 xo = make_float3(0.f, 0.f, 0.f), xl = xo;
+  float gext = 0.0f, ext2 = 0.0f;
+  if constexpr (kF64) {
+    const double4 p64 = x64[s];
+    c64 = group_centre(x64[gs.targets ? gs.targets[grp.t0] : grp.t0], p64, valid);
+    two_float_offset(p64, c64, xo, xl);
+    gext = valid ? fmaxf(fabsf(xo.x), fmaxf(fabsf(xo.y), fabsf(xo.z))) : 0.0f;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) gext = fmaxf(gext, __shfl_xor(gext, m));
+    ext2 = gext * gext;
+  }
+  bool fine = false;  // mixed: the group skips the low parts
+  if constexpr (kF64) {
+    float hmin = valid ? (float)hi64 : INFINITY;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) hmin = fminf(hmin, __shfl_xor(hmin, m));
+    fine = gext <= kFineExt * hmin;
+  }
   const float hi = valid ? mv.w : -1.0f;  // invalid lanes never want anything
   const float hi2 = valid ? sq_exact(hi) : -1.0f;
   const float Ai = ma.x, ci = ma.y, rhoi = ma.z, hinvi = ma.w;
@@ -591,16 +709,21 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
     {
       float4 vx = make_float4(INFINITY, INFINITY, INFINITY, 0.f), vv = make_float4(0.f, 0.f, 0.f, 0.f);
       float4 va = vv, ve = vv;
-      double4 v64 = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-      double h64c = 0.0;
+      float4 vo = vx;  // the tile's position: the FP32 copy, or the offset (mixed)
+      float4 vl = vv;  // mixed: the offset's low parts and the sorted index
       if (lane < nc) {
         vx = xm[cand];
         vv = vh[cand];
         va = aux[cand];
         if constexpr (kExt) ve = ext[cand];
+        vo = vx;
         if constexpr (kF64) {
-          v64 = x64[cand];
-          h64c = h64[cand];
+          const double4 v64 = x64[cand];
+          vo = make_float4((float)(v64.x - c64.x), (float)(v64.y - c64.y),
+                           (float)(v64.z - c64.z), vx.w);
+          vl = make_float4((float)((v64.x - c64.x) - (double)vo.x),
+                           (float)((v64.y - c64.y) - (double)vo.y),
+                           (float)((v64.z - c64.z) - (double)vo.z), __int_as_float(cand));
         }
       }
       const float d2 = box_dist2(make_float3(vx.x, vx.y, vx.z), tlo, thi);
@@ -610,14 +733,11 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
       // kept candidates in their order at the front; the scan stops at nc
       if (keep) {
-        T.xm[w][slot] = vx;
+        T.xm[w][slot] = vo;
         T.vh[w][slot] = vv;
         T.aux[w][slot] = va;
         if constexpr (kExt) E.e[w][slot] = ve;
-        if constexpr (kF64) {
-          tiles64[w][slot] = v64;
-          th64[w][slot] = h64c;
-        }
+        if constexpr (kF64) tlos[w][slot] = vl;
       }
       nc = __popcll(km);
     }
@@ -672,36 +792,61 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
       }
     };
     // every lane tests every entry (read by broadcast)
-    for (int k = 0; k < nc; ++k) {
-      const float4 q = T.xm[w][k];
-      const float4 qv = T.vh[w][k];
-      float dx, dy, dz;
-      if constexpr (kF64) {
-        // offset from this target: the FP64 difference rounded to FP32
-        const double4 q64 = tiles64[w][k];
-        dx = (float)(q64.x - p64.x);
-        dy = (float)(q64.y - p64.y);
-        dz = (float)(q64.z - p64.z);
-      } else {
-        dx = sub_exact(q.x, xi.x);
-        dy = sub_exact(q.y, xi.y);
-        dz = sub_exact(q.z, xi.z);
+    auto scan = [&](auto refine_c) {
+      constexpr bool kRefine = decltype(refine_c)::value;
+      for (int k = 0; k < nc; ++k) {
+        const float4 q = T.xm[w][k];
+        const float4 qv = T.vh[w][k];
+        // plain: the FP32 positions; mixed: the FP32 difference of the two
+        // offsets from the group centre
+        float dx = sub_exact(q.x, kF64 ? xo.x : xi.x);
+        float dy = sub_exact(q.y, kF64 ? xo.y : xi.y);
+        float dz = sub_exact(q.z, kF64 ? xo.z : xi.z);
+        float r2 = dist2_exact(dx, dy, dz);
+        // r2 < fl(max(h_i, h_j)^2) taken as r2 < fl(h_i^2) or r2 < fl(h_j^2)
+        // (the same decision: rounding is monotone), without a max
+        const float hj2 = sq_exact(qv.w);
+        bool in = r2 < hi2 || r2 < hj2;
+        if constexpr (kF64) {
+          // the density's bands with E bounded by gext + H near the
+          // threshold, E H <= 3 H^2 + gext^2: a narrow group decides on the
+          // high parts outside 2^-19 (3 H^2 + gext^2) of it; a wide one
+          // takes the low parts within that band or closer and decides on
+          // them outside 2^-19 (H^2 + 2^-20 (3 H^2 + gext^2)); inside the
+          // band the FP64 test decides
+          const float H2 = fmaxf(hi2, hj2);
+          const float eb = 3.0f * H2 + ext2;
+          in = false;
+          if (valid && r2 < H2 + kBandOff * eb) {
+            float bd = kBandOff * eb;
+            int j = 0;
+            if constexpr (kRefine) {
+              const float4 l = tlos[w][k];
+              dx += sub_exact(l.x, xl.x);
+              dy += sub_exact(l.y, xl.y);
+              dz += sub_exact(l.z, xl.z);
+              r2 = dist2_exact(dx, dy, dz);
+              bd = kBandOff * (H2 + ldexpf(eb, -20));
+              j = __float_as_int(l.w);
+            }
+            if (fabsf(r2 - H2) <= bd) {
+              if constexpr (!kRefine) j = __float_as_int(tlos[w][k].w);
+              in = within64(x64[s], x64[j], fmax(hi64, h64[j]));
+            } else {
+              in = r2 < hi2 || r2 < hj2;
+            }
+          }
+        }
+        if (in) {
+          ++np;
+          pair(k, q, qv, dx, dy, dz, r2);
+        }
       }
-      const float r2 = dist2_exact(dx, dy, dz);
-      // r2 < fl(max(h_i, h_j)^2) taken as r2 < fl(h_i^2) or r2 < fl(h_j^2)
-      // (the same decision: rounding is monotone), without a max
-      const float hj2 = sq_exact(qv.w);
-      bool in = r2 < hi2 || r2 < hj2;
-      if constexpr (kF64) {
-        const float H2 = fmaxf(hi2, hj2);
-        if (valid && fabsf(r2 - H2) <= H2 * kBand64)
-          in = within64(p64, tiles64[w][k], fmax(hi64, th64[w][k]));
-      }
-      if (in) {
-        ++np;
-        pair(k, q, qv, dx, dy, dz, r2);
-      }
-    }
+    };
+    if (kF64 && !fine)
+      scan(std::true_type{});
+    else
+      scan(std::false_type{});
     neumaier_add(ax, cax, px);
     neumaier_add(ay, cay, py);
     neumaier_add(az, caz, pz);
@@ -770,7 +915,7 @@ hipError_t launch_density(const Octree &gas, const Groups &gs, int64_t max_group
                      : (sp.streams == 4 ? k_density<false, 4> : k_density<false, 1>);
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
       gas.nodes, gas.xm, gas.x64, gas.perm, gs, sp.n_ngb, sp.h_tol, solve_h, sp.max_iter,
-      sp.walk_leaf, sp.slack, h, rho, drho_dh, omega, nngb, counters);
+      sp.walk_leaf, sp.absmax, h, rho, drho_dh, omega, nngb, counters);
   return hipGetLastError();
 }
 
@@ -800,7 +945,7 @@ hipError_t launch_hydro(const Octree &gas, const Groups &gs, int64_t max_groups,
                      : (ext ? k_hydro<false, true> : k_hydro<false, false>);
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
       gas.nodes, gas.xm, gas.x64, gas.h64, gas.vh, gas.aux, ext, gas.perm, gs, sp.alpha,
-      alpha_u, sp.gamma - 1.0f, sp.walk_leaf, sp.slack, acc, dudt, vsig, npairs);
+      alpha_u, sp.gamma - 1.0f, sp.walk_leaf, sp.absmax, acc, dudt, vsig, npairs);
   return hipGetLastError();
 }
 

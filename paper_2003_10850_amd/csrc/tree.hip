@@ -13,6 +13,7 @@
 // Morton order) the nodes sorted by (first member, level) are numbered by an
 // exclusive scan of the per-member counts. The node after the subtree of a
 // node ending before member e is the first node that starts at e.
+#include <algorithm>
 #include <utility>
 
 #include "g3_device.h"
@@ -324,6 +325,37 @@ __global__ void k_hmax_level(Node *__restrict__ nodes, int64_t nnodes,
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// The largest |coordinate| of the FP64 positions, as float bits (the FP32
+// rounding upwards keeps it an upper bound); *out must start at zero. A
+// grid-stride loop with one atomic per block: a few thousand atomics on the
+// one word instead of one per wave.
+constexpr int kAbsmaxBlocks = 2048;
+__global__ __launch_bounds__(kBlock) void k_absmax(const double4 *__restrict__ x64, int64_t n,
+                                                   unsigned *__restrict__ out) {
+  __shared__ float part[kBlock / kWave];
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double4 v = x64[i];
+    const double a = fmax(fabs(v.x), fmax(fabs(v.y), fabs(v.z)));
+    float f = (float)a;
+    if ((double)f < a) f = nextafterf(f, INFINITY);
+    m = fmaxf(m, f);
+  }
+#pragma unroll
+  for (int k = 1; k < kWave; k <<= 1) m = fmaxf(m, __shfl_xor(m, k));
+  if ((threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) m = fmaxf(m, part[w]);
+    if (m > 0.0f) atomicMax(out, __float_as_uint(m));
+  }
+}
+
+__global__ void k_zero_one(unsigned *p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
 // The gravity walk's 32-byte node copies (after the moments).
 __global__ void k_gnodes(const Node *__restrict__ nodes, int64_t nnodes,
                          GNode *__restrict__ gnodes) {
@@ -517,6 +549,16 @@ int refit_octree(g3_ctx *c, g3_tree *t, Octree &o, const void *pos, const float 
     return G3_EHIP;
   }
   return G3_OK;
+}
+
+hipError_t update_absmax(g3_tree *t, hipStream_t s) {
+  if (!t->f64 || !t->absmax) return hipSuccess;
+  k_zero_one<<<1, 64, 0, s>>>(t->absmax);
+  if (t->all.n > 0) {
+    const unsigned nb = (unsigned)std::min<int64_t>(nblk(t->all.n), kAbsmaxBlocks);
+    k_absmax<<<nb, kBlock, 0, s>>>(t->all.x64, t->all.n, t->absmax);
+  }
+  return hipGetLastError();
 }
 
 hipError_t refit_hmax(Octree &o, hipStream_t s) {

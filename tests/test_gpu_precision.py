@@ -142,3 +142,46 @@ def test_hydro_and_gravity_mixed_precision(ctx, shift):
     dg = np.linalg.norm(host(gr["acc"]) - rg["acc"], axis=1)
     assert (dg / rg["S"]).max() < TOL
     np.testing.assert_allclose(host(gr["pot"]), rg["pot"], rtol=TOL)
+
+
+def test_refit_after_drift_in_a_far_box(ctx):
+    """An FP64 tree of a box at 1000, refit after particles drift by up to
+    3e-3 of the box per axis (some leave the box), keeps exact neighbour
+    and pair counts and the same bars: the offsets are taken from each
+    group's FP64 centre, and the walk's rounding pad follows the largest
+    coordinate found on the device at the refit."""
+    from paper_2003_10850_amd import ops
+    w = inputs.plummer(n=30000, n_spheres=4, seed=26, n_ngb=64.0)
+    c = Case64(ctx, w, shift=1000.0)
+    rng = np.random.default_rng(27)
+    moved = c.pos + rng.uniform(-3e-3, 3e-3, c.pos.shape)
+    c.tree.refit(dev_t(moved), dev_t(c.m32))
+    # the oracle's trees only organise its direct definitions: give them a
+    # box that holds the moved particles
+    lo = moved.min(0) - 1e-3
+    big = np.array([*lo, (moved.max(0) - lo).max() + 1e-3])
+    gt = oracle.Tree(moved, c.M, big, type=w.type, gas_only=True)
+    at = oracle.Tree(moved, c.M, big, type=w.type)
+    h = inputs.model_smoothing(w)
+    d = ops.density(c.tree, h=dev_t(h), solve_h=False)
+    r = oracle.density(gt, c.pr, active=c.gas, h=h, solve_h=False)
+    np.testing.assert_array_equal(host(d["nngb"])[c.gas], r["nngb"][c.gas])
+    err = (np.abs(host(d["rho"])[c.gas] - r["rho"][c.gas]) / r["rho"][c.gas]).max()
+    assert err < TOL, f"rho: max rel {err:.3e}"
+    rho = inputs.model_gas_density(w).astype(np.float32)
+    om = np.ones(w.n, np.float32)
+    v32, u32 = w.vel.astype(np.float32), w.u.astype(np.float32)
+    g = ops.hydro_force(c.tree, dev_t(v32), dev_t(u32), dev_t(h), dev_t(rho), dev_t(om))
+    rh = oracle.hydro(gt, c.pr, v32, u32, h, rho, om, active=c.gas)
+    np.testing.assert_array_equal(host(g["npairs"])[c.gas], rh["npairs"][c.gas])
+    da = np.linalg.norm(host(g["acc"])[c.gas] - rh["acc"][c.gas], axis=1)
+    assert (da / rh["S"][c.gas]).max() < TOL
+    # gravity at theta = 0 (no decision depends on the refit cells)
+    p0 = dataclasses.replace(c.p, theta=0.0)
+    gr = ops.gravity(c.tree, params=p0)
+    rg = oracle.gravity(at, fp64_params(p0))
+    np.testing.assert_array_equal(host(gr["nterms"]), rg["nterms"])
+    dg = np.linalg.norm(host(gr["acc"]) - rg["acc"], axis=1)
+    assert (dg / rg["S"]).max() < TOL
+    print(f"far-box refit: rho {err:.2e}, hydro {(da / rh['S'][c.gas]).max():.2e}, "
+          f"gravity {(dg / rg['S']).max():.2e}", flush=True)
