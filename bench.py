@@ -585,12 +585,19 @@ def run_differentiation(dev, steps: int, warmup: int, n: int = 1 << 20, seed: in
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / steps
     ctx.nonconverged(reset=True)
-    print(f"bench: differentiation {ms:.3f} ms/step (loss {float(L):.6e})", file=sys.stderr,
-          flush=True)
+    # outside the timed region: two more steps give the same gradient bits
+    grads = []
+    for _ in range(2):
+        step()
+        grads.append([t.grad.detach().clone() for t in (pos, mass, h)])
+    same = all(torch.equal(a, b) for a, b in zip(*grads))
+    print(f"bench: differentiation {ms:.3f} ms/step (loss {float(L):.6e}); repeated gradients "
+          f"{'bit-identical' if same else 'differ'}", file=sys.stderr, flush=True)
     return {
         "workload": f"{w.name}: N={n} clustered as the plain workload, FP32; loss = sum_gas "
                     "(log rho)^2 + (1/2) sum m phi at the solved h",
         "ms_per_step": ms,
+        "deterministic": bool(same),
         "step": "forward (density at h, gravity) + backward (density and gravity adjoints, "
                 "walks recomputed) for dL/dpos, dL/dmass, dL/dh",
     }

@@ -585,7 +585,12 @@ int g3_hydro_force_backward(g3_ctx *ctx, g3_tree *tree, int64_t n_act,
                             float *g_omega, void *stream);
 /* Gravity: upstream g_acc [n][3], g_pot [n]. Node monopoles pass their
  * gradients to their members through M = sum m and c = sum m x / M.
- * Outputs dL/dpos, dL/dmass. */
+ * Outputs dL/dpos, dL/dmass. With eps > 0 the result is deterministic (the
+ * same bits on every run): the terms each source collects from many
+ * wavefronts are added as 64-bit fixed-point integers, at a scale bounded
+ * from the largest upstream gradients, the largest mass and eps, and turned
+ * back into floats once. With eps = 0 they are FP32 atomics (order-dependent
+ * in the last bits). */
 int g3_gravity_backward(g3_ctx *ctx, const g3_tree *tree, int64_t n_act,
                         const int32_t *active, const g3_params *p,
                         const float *g_acc, const float *g_pot, float *g_pos,

@@ -12,7 +12,9 @@
 // gradient is written by one lane in a fixed order (deterministic). The
 // gravity adjoint is scattered: a wave sums the source-side terms of a tile
 // entry over its lanes with DPP row operations and adds them with one
-// atomic per entry; node adjoints are then pushed down to the members.
+// atomic per entry, in 64-bit fixed point (integer additions commute, so
+// the result does not depend on the order of the waves: deterministic); node
+// adjoints are then pushed down to the members.
 #include "g3_device.h"
 #include "g3_internal.h"
 
@@ -324,6 +326,92 @@ __device__ __forceinline__ float wave_reduce_scatter16(float (&v)[16], int lane)
   return v[0];
 }
 
+// Deterministic accumulation of the gravity adjoint's scattered sums. Every
+// value v is added as two 64-bit integers, hi = trunc(v 2^F) and
+// lo = rint((v 2^F - hi) 2^kFxLoBits), to a pair of counters: integer
+// addition is exact and commutes, so the totals do not depend on the order
+// in which waves add them. F is one per call, taken from a bound B on every
+// counter's partial sums (|sum hi| <= B 2^F <= 2^62): with S = r^2 + eps^2 >=
+// eps^2, a term's position part is at most G m (4 |g_a| S^-3/2 + |g_phi|
+// S^-1) and its mass part G (|g_a| S^-1 + |g_phi| S^-1/2), |g_a| <= sqrt(3)
+// times the largest upstream component, m at most n times the largest mass
+// (a node), and a counter takes at most n_act such terms from the source
+// side and at most n from its own target side. The overestimate (many
+// orders of magnitude) costs nothing: the low counter resolves 2^-(62 + 36)
+// of B, about 2^-30 of the largest true total even at 2e7 particles, far
+// below the FP32 rounding of the terms; lo stays below 2^63 for up to 2^26
+// additions per counter. Needs eps > 0 (else no such bound: FP32 atomics).
+constexpr int kFxLoBits = 36;
+
+// The scale 2^F from the device maxima (float bits) of the upstream
+// gradient components, the upstream potential gradients and the masses.
+__device__ __forceinline__ double fx_scale(const unsigned *__restrict__ mx, float eps2, float G,
+                                           int64_t n, int64_t n_act) {
+  const double ga = 1.7320508075688772 * (double)__uint_as_float(mx[0]);
+  const double gp = (double)__uint_as_float(mx[1]);
+  const double mm = (double)__uint_as_float(mx[2]);
+  const double e2 = (double)eps2, e1 = sqrt(e2);
+  const double T = 4.0 * ga / (e2 * e1) + gp / e2 + ga / e2 + gp / e1;
+  const double B = 2.0 * fabs((double)G) * T * ((double)n * mm + 1.0) *
+                   ((double)n + (double)n_act + 1.0);
+  // (no finite bound, from non-finite inputs: any scale; the sums are then
+  // as meaningless as the inputs)
+  const int F = (B > 0.0 && B < 1e300) ? 62 - (ilogb(B) + 1) : 0;
+  return ldexp(1.0, F);
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long *dst, float v, double scale) {
+  const double d = (double)v * scale;
+  const double hi = trunc(d);  // d - hi is exact
+  const long long lo = (long long)rint((d - hi) * (double)(1ll << kFxLoBits));
+  atomicAdd(dst, (unsigned long long)(long long)hi);
+  atomicAdd(dst + 1, (unsigned long long)lo);
+}
+
+// The largest |upstream gradient component|, |upstream potential gradient|
+// (over the active rows; ids outside [0, m) are skipped, as by the walk) and
+// mass (over every member), as float bits into mx[0..2] (zero on entry).
+__global__ void k_fx_bound(const int32_t *__restrict__ active, int64_t n_act,
+                           const float *__restrict__ g_acc, const float *__restrict__ g_pot,
+                           const float4 *__restrict__ xm, int64_t m, unsigned *__restrict__ mx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float a = 0.0f, p = 0.0f, w = 0.0f;
+  const int64_t id = i < n_act ? (active ? active[i] : i) : -1;
+  if (id >= 0 && id < m) {
+    if (g_acc)
+      a = fmaxf(fabsf(g_acc[3 * id]), fmaxf(fabsf(g_acc[3 * id + 1]), fabsf(g_acc[3 * id + 2])));
+    if (g_pot) p = fabsf(g_pot[id]);
+  }
+  if (i < m) w = fabsf(xm[i].w);
+#pragma unroll
+  for (int k = 1; k < kWave; k <<= 1) {
+    a = fmaxf(a, __shfl_xor(a, k));
+    p = fmaxf(p, __shfl_xor(p, k));
+    w = fmaxf(w, __shfl_xor(w, k));
+  }
+  if ((threadIdx.x & 63u) == 0u) {
+    atomicMax(&mx[0], __float_as_uint(a));
+    atomicMax(&mx[1], __float_as_uint(p));
+    atomicMax(&mx[2], __float_as_uint(w));
+  }
+}
+
+// Fixed-point counter pairs (hi, lo) x 4 components back to float4.
+__global__ void k_fx_to_f4(const unsigned long long *__restrict__ fx, int64_t m,
+                           const unsigned *__restrict__ mx, float eps2, float G, int64_t n,
+                           int64_t n_act, float4 *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double inv = 1.0 / fx_scale(mx, eps2, G, n, n_act);
+  double v[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long long hi = (long long)fx[8 * i + 2 * c], lo = (long long)fx[8 * i + 2 * c + 1];
+    v[c] = ((double)hi + ldexp((double)lo, -kFxLoBits)) * inv;
+  }
+  out[i] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+
 struct __align__(16) GEntry {
   float4 p;   // source position, mass
   int4 meta;  // sorted source index, or -(node + 1); mask low, mask high; unused
@@ -346,14 +434,21 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
 //   dL/dx_i += dL/dx,  dL/dx_s -= dL/dx,  dL/dm_s = -G ((ga . x) / S^(3/2) + gp / S^(1/2)).
 // The source side of a tile entry is summed over the wave's lanes and added
 // once: to the particle's sorted slot, or to the node's (dL/dc, dL/dM).
+// kFixed: the sums go to fixed-point counter pairs (gsrc_fx [n][4][2],
+// gnode_fx [nnodes][4][2], scale from mx), else to FP32 atomics (gsrc,
+// gnode).
+template <bool kFixed>
 __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
     const Node *__restrict__ nodes, const float4 *__restrict__ xm,
     const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
     float theta2, float eps2, float G, int inside_test, const float *__restrict__ g_acc,
-    const float *__restrict__ g_pot, float4 *__restrict__ gsrc, float4 *__restrict__ gnode) {
+    const float *__restrict__ g_pot, float4 *__restrict__ gsrc, float4 *__restrict__ gnode,
+    unsigned long long *__restrict__ gsrc_fx, unsigned long long *__restrict__ gnode_fx,
+    const unsigned *__restrict__ mx, int64_t n_all, int64_t n_act) {
   __shared__ GEntry tiles[kWpb][kTile];
   const int w = (int)(threadIdx.x >> 6), lane = lane_id();
   GEntry *tile = tiles[w];
+  const double scale = kFixed ? fx_scale(mx, eps2, G, n_all, n_act) : 1.0;
   int range = 0;
   for (int g; (g = next_group(gs, range)) >= 0;) {
     const Group grp = group_at(gs, g);
@@ -418,8 +513,14 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
         const int e = lane >> 4, comp = (lane >> 2) & 3;
         if ((lane & 3) == 0 && k0 + e < nc) {
           const int src = tile[k0 + e].meta.x;
-          float *dst = src >= 0 ? (float *)&gsrc[src] : (float *)&gnode[-src - 1];
-          atomicAdd(dst + comp, tot);
+          if constexpr (kFixed) {
+            unsigned long long *dst = src >= 0 ? gsrc_fx + 8 * (int64_t)src
+                                               : gnode_fx + 8 * (int64_t)(-src - 1);
+            fx_add(dst + 2 * comp, tot, scale);
+          } else {
+            float *dst = src >= 0 ? (float *)&gsrc[src] : (float *)&gnode[-src - 1];
+            atomicAdd(dst + comp, tot);
+          }
         }
       }
       neumaier_add(ox, cox, px);
@@ -493,9 +594,15 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
     }
     if (tc > 0) flush(tc);
     if (valid) {
-      atomicAdd(&gsrc[s].x, ox + cox);
-      atomicAdd(&gsrc[s].y, oy + coy);
-      atomicAdd(&gsrc[s].z, oz + coz);
+      if constexpr (kFixed) {
+        fx_add(gsrc_fx + 8 * (int64_t)s, ox + cox, scale);
+        fx_add(gsrc_fx + 8 * (int64_t)s + 2, oy + coy, scale);
+        fx_add(gsrc_fx + 8 * (int64_t)s + 4, oz + coz, scale);
+      } else {
+        atomicAdd(&gsrc[s].x, ox + cox);
+        atomicAdd(&gsrc[s].y, oy + coy);
+        atomicAdd(&gsrc[s].z, oz + coz);
+      }
     }
   }
 }
@@ -875,17 +982,37 @@ hipError_t launch_hydro_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
 }
 
 hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_groups,
-                              const GravParams &gp, const float *g_acc, const float *g_pot,
-                              float4 *gsrc, float4 *gnode, double4 *pq, double *rr,
-                              float *g_pos, float *g_mass, hipStream_t s) {
+                              const GravParams &gp, int64_t n_act, const int32_t *active,
+                              const float *g_acc, const float *g_pot, float4 *gsrc,
+                              float4 *gnode, unsigned long long *gsrc_fx,
+                              unsigned long long *gnode_fx, unsigned *mx, double4 *pq,
+                              double *rr, float *g_pos, float *g_mass, hipStream_t s) {
   const int64_t m = all.n, nn = all.nnodes;
   if (m == 0 || nn == 0) return hipSuccess;
-  k_zero_f4<<<nblk(m), kBlock, 0, s>>>(gsrc, m);
-  k_zero_f4<<<nblk(nn), kBlock, 0, s>>>(gnode, nn);
-  if (max_groups > 0)
-    k_gravity_bwd<<<persistent_grid((const void *)k_gravity_bwd, kBlock, max_groups), kBlock, 0,
-                    s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
-                         gp.inside_test, g_acc, g_pot, gsrc, gnode);
+  const int64_t na = active ? n_act : m;
+  if (gp.eps2 > 0.0f) {
+    // fixed-point counters (two words per component, four components)
+    k_zero_f4<<<nblk(4 * m), kBlock, 0, s>>>((float4 *)gsrc_fx, 4 * m);
+    k_zero_f4<<<nblk(4 * nn), kBlock, 0, s>>>((float4 *)gnode_fx, 4 * nn);
+    k_zero_f4<<<1, kBlock, 0, s>>>((float4 *)mx, 1);
+    const int64_t nb = na > m ? na : m;
+    k_fx_bound<<<nblk(nb), kBlock, 0, s>>>(active, na, g_acc, g_pot, all.xm, m, mx);
+    if (max_groups > 0)
+      k_gravity_bwd<true>
+          <<<persistent_grid((const void *)k_gravity_bwd<true>, kBlock, max_groups), kBlock, 0,
+             s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
+                  gp.inside_test, g_acc, g_pot, gsrc, gnode, gsrc_fx, gnode_fx, mx, m, na);
+    k_fx_to_f4<<<nblk(m), kBlock, 0, s>>>(gsrc_fx, m, mx, gp.eps2, gp.G, m, na, gsrc);
+    k_fx_to_f4<<<nblk(nn), kBlock, 0, s>>>(gnode_fx, nn, mx, gp.eps2, gp.G, m, na, gnode);
+  } else {
+    k_zero_f4<<<nblk(m), kBlock, 0, s>>>(gsrc, m);
+    k_zero_f4<<<nblk(nn), kBlock, 0, s>>>(gnode, nn);
+    if (max_groups > 0)
+      k_gravity_bwd<false>
+          <<<persistent_grid((const void *)k_gravity_bwd<false>, kBlock, max_groups), kBlock, 0,
+             s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
+                  gp.inside_test, g_acc, g_pot, gsrc, gnode, nullptr, nullptr, nullptr, m, na);
+  }
   k_push_init<<<nblk(nn), kBlock, 0, s>>>(gnode, all.mom, nn, pq, rr);
   for (int l = 0; l < all.max_level; ++l)
     k_push_level<<<nblk(nn), kBlock, 0, s>>>(all.nodes, all.mom, nn, l, pq, rr);

@@ -1671,13 +1671,24 @@ int g3_gravity_backward(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_
   float4 *gnode = (float4 *)scratch(c, kAdjNode, o.nnodes * sizeof(float4));
   double4 *pq = (double4 *)scratch(c, kAdjPQ, o.nnodes * sizeof(double4));
   double *rr = (double *)scratch(c, kAdjR, o.nnodes * sizeof(double));
-  if (!gsrc || !gnode || !pq || !rr)
+  // fixed-point counters (8 words per member / node) and, after the
+  // members', the four words of the scale's maxima
+  const bool fixed = p->eps > 0.0;
+  unsigned long long *gsrc_fx = fixed ? (unsigned long long *)scratch(
+                                            c, kAdjSrcFx, (8 * o.n + 2) * sizeof(uint64_t))
+                                      : nullptr;
+  unsigned long long *gnode_fx =
+      fixed ? (unsigned long long *)scratch(c, kAdjNodeFx, 8 * o.nnodes * sizeof(uint64_t))
+            : nullptr;
+  if (!gsrc || !gnode || !pq || !rr || (fixed && (!gsrc_fx || !gnode_fx)))
     return fail(c, G3_ENOMEM, "g3_gravity_backward: scratch allocation failed");
   Work wk;
   st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s);
   if (st) return st;
-  hipError_t e = launch_gravity_bwd(o, wk.gs, wk.max_groups, grav_params(p, t), g_acc, g_pot,
-                                    gsrc, gnode, pq, rr, g_pos, g_mass, s);
+  hipError_t e = launch_gravity_bwd(o, wk.gs, wk.max_groups, grav_params(p, t), n_act, active,
+                                    g_acc, g_pot, gsrc, gnode, gsrc_fx, gnode_fx,
+                                    fixed ? (unsigned *)(gsrc_fx + 8 * o.n) : nullptr, pq, rr,
+                                    g_pos, g_mass, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity_backward");
   c->err.clear();
   return G3_OK;

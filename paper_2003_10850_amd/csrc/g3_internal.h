@@ -140,7 +140,7 @@ enum Slot {
   kFlags, kTargets, kRows, kIds, kLevel, kWalkCounts, kMisc,
   kSnapKeys, kSnapKeysAlt, kGroups, kAdjSrc, kAdjNode, kAdjPQ, kAdjR,
   kGasFlags, kGasSlot, kGasScan, kIntAccH, kIntVp, kIntUp, kCondCh, kHydroExt,
-  kNumSlots
+  kAdjSrcFx, kAdjNodeFx, kNumSlots
 };
 static_assert(kNumSlots <= (int)(sizeof(g3_ctx::scratch) / sizeof(g3_ctx::Buf)),
               "more scratch slots than the ctx holds");
@@ -328,12 +328,16 @@ hipError_t launch_hydro_bwd(Octree &gas, const int32_t *iperm, int64_t n_caller,
                             const float *omega, const float *g_acc, const float *g_dudt,
                             float4 *up, float *g_pos, float *g_vel, float *g_mass, float *g_h,
                             float *g_u, float *g_rho, float *g_omega, hipStream_t s);
-// Gravity over the active targets `gs`; scratch gsrc [n], gnode [nnodes],
+// Gravity over the active targets `gs` (n_act rows of `active`, nullptr:
+// every member); scratch gsrc [n], gnode [nnodes], the fixed-point counters
+// gsrc_fx [n][8] and gnode_fx [nnodes][8] with mx [4] (used when eps > 0),
 // pq [nnodes], rr [nnodes].
 hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_groups,
-                              const GravParams &gp, const float *g_acc, const float *g_pot,
-                              float4 *gsrc, float4 *gnode, double4 *pq, double *rr,
-                              float *g_pos, float *g_mass, hipStream_t s);
+                              const GravParams &gp, int64_t n_act, const int32_t *active,
+                              const float *g_acc, const float *g_pot, float4 *gsrc,
+                              float4 *gnode, unsigned long long *gsrc_fx,
+                              unsigned long long *gnode_fx, unsigned *mx, double4 *pq,
+                              double *rr, float *g_pos, float *g_mass, hipStream_t s);
 
 // Thermal conduction (conduction.hip): ch [n_gas] scratch of the sorted
 // pair inputs; the gas octree's node hmax must be refit from h first.

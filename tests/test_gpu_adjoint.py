@@ -224,6 +224,30 @@ def test_gravity_backward(ctx, theta, frac):
     check("gravity g_mass", host(mass.grad), ref["mass"], ref["S"]["mass"])
 
 
+def test_gravity_backward_is_deterministic(ctx):
+    """With eps > 0 the scattered source sums are fixed-point integer
+    additions: repeated calls give the same bits, on a workload large enough
+    that many wavefronts add to the same node and particle counters."""
+    from paper_2003_10850_amd import ops
+    w = inputs.plummer(n=300000, n_spheres=8, seed=84)
+    pos32, _, m32, _ = w.as_f32()
+    tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(w.type), tuple(w.box), w.params)
+    rng = np.random.default_rng(7)
+    gA = dev_t(rng.normal(size=(w.n, 3)).astype(np.float32))
+    gP = dev_t(rng.normal(size=w.n).astype(np.float32))
+    runs = []
+    for _ in range(3):
+        pos = dev_t(pos32).requires_grad_(True)
+        mass = dev_t(m32).requires_grad_(True)
+        acc, pot = ops.gravity_ad(tree, pos, mass)
+        ((acc * gA).sum() + (pot * gP).sum()).backward()
+        runs.append((host(pos.grad).copy(), host(mass.grad).copy()))
+    for k in (1, 2):
+        np.testing.assert_array_equal(runs[k][0], runs[0][0])
+        np.testing.assert_array_equal(runs[k][1], runs[0][1])
+    assert np.all(np.isfinite(runs[0][0])) and np.abs(runs[0][0]).max() > 0
+
+
 def loss_terms(tree, pos, mass, h):
     """The differentiation workload's loss: sum over gas of (log rho)^2 plus
     the total potential energy (1/2) sum m phi, at a given h."""
