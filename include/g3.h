@@ -211,14 +211,17 @@ int g3_tree_export(g3_ctx *ctx, const g3_tree *tree, int32_t which,
  *                as -(k + 1).
  * Neighbour test (exact, FP32): dx = fl(x_j - x_i) per axis,
  * r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)), neighbour iff r2 < fl(H * H).
- *   h        [n] float smoothing lengths (GATHER, SYMMETRIC; ignored for
- *            GRAVITY)
+ * On trees built from FP64 positions every decision is the FP64 one, the
+ * one the mixed-precision g3_density, g3_hydro_force and g3_gravity take:
+ * ((dx dx + dy dy) + dz dz) < H H on the FP64 positions and h, and the
+ * opening test on the FP64 node centres with the exact cube side.
+ *   h        [n] smoothing lengths in the tree's dtype (GATHER, SYMMETRIC;
+ *            ignored for GRAVITY)
  *   offsets  [n_act + 1] int64 output
  *   list     [capacity] output; entries of a row in walk order
  *   total    (host) output: offsets[n_act]
  * SYNCS. Returns G3_EOVERFLOW, with *total and offsets valid and list
- * untouched, when *total > capacity. Trees built from FP64 positions are
- * rejected (G3_EINVAL): lists are built for the plain path only. */
+ * untouched, when *total > capacity. */
 int g3_walk(g3_ctx *ctx, const g3_tree *tree, int32_t kind, int64_t n_act,
             const int32_t *active, const void *h, const g3_params *p,
             int64_t capacity, int64_t *offsets, int32_t *list, int64_t *total,

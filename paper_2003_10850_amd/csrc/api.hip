@@ -830,8 +830,6 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, tc, n_act, active, "g3_walk");
   if (st) return st;
-  if (tc->f64)
-    return fail(c, G3_EINVAL, "g3_walk: explicit lists are built for FP32 trees only");
   if (kind != G3_GATHER && kind != G3_SYMMETRIC && kind != G3_GRAVITY)
     return fail(c, G3_EINVAL, "g3_walk: unknown kind");
   if (!params_ok(p) || !offsets || !total || capacity < 0 || (capacity > 0 && !list))
@@ -849,19 +847,24 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   int32_t *counts = (int32_t *)scratch(c, kWalkCounts, (n_act + 1) * sizeof(int32_t));
   int64_t *stmp = (int64_t *)scratch(c, kMisc, scan_tmp_elems(n_act) * sizeof(int64_t) + 64);
   if (!counts || !stmp) return fail(c, G3_ENOMEM, "g3_walk: allocation failed");
+  if (kind != G3_GRAVITY) {
+    st = ensure_h64(c, t, o);
+    if (st) return st;
+  }
   Work wk;
   st = prepare_work(c, t, o, iperm, n_act, active, &wk, s);
   if (st) return st;
   hipError_t e;
   if (kind != G3_GRAVITY && o.n > 0) {
-    e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, 0, s);
+    e = launch_hydro_prep(o, nullptr, nullptr, h, nullptr, nullptr, 1.0f, t->f64, s);
     if (e == hipSuccess && kind == G3_SYMMETRIC) e = refit_hmax(o, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk prep");
   }
   e = fill_i32(counts, 0, n_act, s);
   GravParams gp = grav_params(p, t);
   if (e == hipSuccess)
-    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, counts, nullptr, nullptr, s);
+    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, t->absmax, counts, nullptr,
+                    nullptr, s);
   if (e == hipSuccess) e = scan_i32_to_i64(counts, offsets, n_act, stmp, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&c->pinned[3], offsets + n_act, sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -872,7 +875,8 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
   if (*total > 0) {
     // the fill pass takes the groups from a fresh queue
     k_zero_u32<<<1, 64, 0, s>>>(wk.gs.queue, 8);
-    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, counts, offsets, list, s);
+    e = launch_walk(o, kind, wk.gs, wk.rows, wk.max_groups, gp, t->absmax, counts, offsets,
+                    list, s);
     if (e != hipSuccess) return hip_fail(c, e, "g3_walk fill pass");
   }
   c->err.clear();

@@ -174,4 +174,28 @@ __device__ __forceinline__ void two_float_offset(double4 x, double4 c, float3 &o
   l = make_float3((float)(dx - (double)o.x), (float)(dy - (double)o.y), (float)(dz - (double)o.z));
 }
 
+// FP64 neighbour test on the stored FP64 positions, the same expression as
+// the mixed-precision definition: ((dx dx + dy dy) + dz dz) < H H.
+__device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
+#pragma clang fp contract(off)
+  const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+  return (dx * dx + dy * dy) + dz * dz < H * H;
+}
+
+// The opening test in FP64 on the stored FP64 positions and node centres:
+// l l < (theta theta) ((dx dx + dy dy) + dz dz), no contraction.
+__device__ __forceinline__ bool open_accept64(double l, double theta, double4 c, double4 x) {
+#pragma clang fp contract(off)
+  const double dx = c.x - x.x, dy = c.y - x.y, dz = c.z - x.z;
+  return l * l < theta * theta * ((dx * dx + dy * dy) + dz * dz);
+}
+
+// FP64 positions: a walk radius for pruning on the FP32 copies (node boxes,
+// group boxes, FP32 h). It covers the FP32 rounding of h (and of its
+// square) with the factor 1 + 2^-22, and that of the coordinates with
+// slack = 2^-20 max|x|, the pad the kernels take from the tree.
+__device__ __forceinline__ float walk_radius64(float h, float slack) {
+  return h * 1.0000002384185791f + slack;  // 1 + 2^-22
+}
+
 }  // namespace g3

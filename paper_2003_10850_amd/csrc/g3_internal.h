@@ -366,8 +366,9 @@ hipError_t launch_update(int64_t n, int f64, const IntegUpdate &up, const uint8_
 hipError_t launch_store_count(const uint32_t *count, int64_t *out, hipStream_t s);
 
 // Walk lists: counts pass (list == nullptr) or fill pass.
+// absmax: the tree's largest coordinate (FP64 trees, SPH kinds).
 hipError_t launch_walk(const Octree &o, int kind, const Groups &gs, const int32_t *rows,
-                       int64_t max_groups, const GravParams &gp, int32_t *counts,
-                       const int64_t *offsets, int32_t *list, hipStream_t s);
+                       int64_t max_groups, const GravParams &gp, const unsigned *absmax,
+                       int32_t *counts, const int64_t *offsets, int32_t *list, hipStream_t s);
 
 }  // namespace g3

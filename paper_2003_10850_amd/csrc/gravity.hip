@@ -41,13 +41,6 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
   return lhs < rhs;
 }
 
-// The opening test in FP64 on the stored FP64 positions and node centres:
-// l l < (theta theta) ((dx dx + dy dy) + dz dz), no contraction.
-__device__ __forceinline__ bool open_accept64(double l, double theta, double4 c, double4 x) {
-#pragma clang fp contract(off)
-  const double dx = c.x - x.x, dy = c.y - x.y, dz = c.z - x.z;
-  return l * l < theta * theta * ((dx * dx + dy * dy) + dz * dz);
-}
 
 // Mixed precision (kF64): positions are stored in FP64 and the node centres
 // of mass come from FP64 moments. Each term works on the FP32 difference of

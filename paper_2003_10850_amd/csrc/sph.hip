@@ -68,13 +68,6 @@ __device__ float node_density_guess(const Node *__restrict__ nodes, int root, in
   return nd.com_m.w / (l * l * l);
 }
 
-// FP64 neighbour test on the stored FP64 positions, the same expression as
-// the mixed-precision definition: ((dx dx + dy dy) + dz dz) < H H.
-__device__ __forceinline__ bool within64(double4 a, double4 b, double H) {
-#pragma clang fp contract(off)
-  const double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-  return (dx * dx + dy * dy) + dz * dz < H * H;
-}
 
 // The mixed precision of the density and hydro kernels works on FP32 offsets
 // from one FP64 centre per group (the position of its first target), each
@@ -188,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const float h2 = !live ? -1.0f : (kF64 ? (float)((double)hcur * (double)hcur) : sq_exact(hf));
     // walk pruning radius: exact for FP32 positions, padded by the rounding
     // of FP32 absolute coordinates when the positions are FP64
-    const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(hf + slack) : h2);
+    const float hw2 = !live ? -1.0f : (kF64 ? sq_exact(walk_radius64(hf, slack)) : h2);
 
     const float hinv = 1.0f / hf;
     // sums of m w, m wh and m wss: plain per tile, compensated across tiles
@@ -686,7 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   float4 thi = make_float4(valid ? xi.x : -INFINITY, valid ? xi.y : -INFINITY,
                            valid ? xi.z : -INFINITY, 0.f);
   // (with FP64 positions: the FP32 copies and radii padded as in the walk)
-  float hmax2 = kF64 ? (valid ? sq_exact(hi + slack) : -1.0f) : hi2;
+  float hmax2 = kF64 ? (valid ? sq_exact(walk_radius64(hi, slack)) : -1.0f) : hi2;
   {
 #pragma unroll
     for (int m = 1; m < kWave; m <<= 1) {
@@ -727,7 +720,8 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
         }
       }
       const float d2 = box_dist2(make_float3(vx.x, vx.y, vx.z), tlo, thi);
-      const bool keep = lane < nc && (d2 < hmax2 || d2 < sq_exact(kF64 ? vv.w + slack : vv.w));
+      const bool keep =
+          lane < nc && (d2 < hmax2 || d2 < sq_exact(kF64 ? walk_radius64(vv.w, slack) : vv.w));
       const uint64_t km = __ballot(keep);
       const int slot = (int)__builtin_amdgcn_mbcnt_hi(
           (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
@@ -857,7 +851,7 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   int cur = grp.root;
   while (cur < grp.end) {
     const Node nd = nodes[cur];
-    const float hm = fmaxf(hi, nd.lo_h.w) + slack;
+    const float hm = kF64 ? walk_radius64(fmaxf(hi, nd.lo_h.w), slack) : fmaxf(hi, nd.lo_h.w);
     const bool want = hi > 0.0f && box_dist2(xi, nd.lo_h, nd.hi_l) < sq_exact(hm);
     if (__ballot(want) == 0ull) {
       cur = nd.meta.x;

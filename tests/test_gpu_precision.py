@@ -185,3 +185,31 @@ def test_refit_after_drift_in_a_far_box(ctx):
     assert (dg / rg["S"]).max() < TOL
     print(f"far-box refit: rho {err:.2e}, hydro {(da / rh['S'][c.gas]).max():.2e}, "
           f"gravity {(dg / rg['S']).max():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("shift", [0.0, 1000.0])
+def test_walk_lists_on_fp64_trees(ctx, shift):
+    """g3_walk on a tree of FP64 positions: every list is the FP64-decision
+    list of the oracle, as exact sets (gather, symmetric, gravity; all
+    targets and a sparse active subset)."""
+    from paper_2003_10850_amd import ops, g3
+    w = inputs.plummer(n=8000, n_spheres=3, seed=28, n_ngb=64.0)
+    c = Case64(ctx, w, shift=shift)
+    h = inputs.model_smoothing(w, 64.0)
+    sub = inputs.active_subset(w.n, 0.1, seed=2)
+    for kind, act in ((g3.G3_GATHER, None), (g3.G3_SYMMETRIC, None), (g3.G3_GRAVITY, None),
+                      (g3.G3_SYMMETRIC, sub)):
+        a_t = None if act is None else dev_t(act.astype(np.int32))
+        off, lst, st = ops.walk(c.tree, kind, h=None if kind == g3.G3_GRAVITY else dev_t(h),
+                                active=a_t)
+        assert st == g3.G3_OK
+        off, lst = host(off), host(lst)
+        tgt = np.arange(w.n) if act is None else act
+        t = c.at if kind == g3.G3_GRAVITY else c.gt
+        roff, rl = oracle.lists(t, c.pr, kind, active=tgt,
+                                h=None if kind == g3.G3_GRAVITY else h)
+        np.testing.assert_array_equal(np.diff(off), np.diff(roff))
+        for a in range(len(tgt)):
+            assert np.array_equal(np.sort(lst[off[a]:off[a + 1]]), rl[roff[a]:roff[a + 1]]), \
+                (kind, a)
+        print(f"fp64 walk kind {kind} shift {shift}: {off[-1]} entries exact", flush=True)
