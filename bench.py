@@ -281,10 +281,11 @@ def copy_calibration(dev) -> None:
 
 
 def is_plain_kernel(full_name: str, k: str) -> bool:
-    """Whether a profiler kernel name is the FP32 (plain) instance of g3 kernel k:
-    k(...), k<false>(...) or k<false, streams>(...)."""
+    """Whether a profiler kernel name is the FP32 (plain) instance of g3 kernel k
+    without the switches' extension: k(...), k<false>(...), k<false, streams>(...)
+    or k<false, false>(...)."""
     import re
-    return re.search(rf"::{k}(<false(, \d+)?>)?\(", full_name) is not None
+    return re.search(rf"::{k}(<false(, (\d+|false))?>)?\(", full_name) is not None
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, out_json: str) -> dict:

@@ -371,28 +371,44 @@ __device__ __forceinline__ void fx_add(unsigned long long *dst, float v, double 
 // The largest |upstream gradient component|, |upstream potential gradient|
 // (over the active rows; ids outside [0, m) are skipped, as by the walk) and
 // mass (over every member), as float bits into mx[0..2] (zero on entry).
-__global__ void k_fx_bound(const int32_t *__restrict__ active, int64_t n_act,
-                           const float *__restrict__ g_acc, const float *__restrict__ g_pot,
-                           const float4 *__restrict__ xm, int64_t m, unsigned *__restrict__ mx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kFxBoundBlocks = 1024;
+__global__ __launch_bounds__(kBlock) void k_fx_bound(
+    const int32_t *__restrict__ active, int64_t n_act, const float *__restrict__ g_acc,
+    const float *__restrict__ g_pot, const float4 *__restrict__ xm, int64_t m,
+    unsigned *__restrict__ mx) {
+  // a grid-stride pass, then one atomic per block and value (one per wave
+  // on three words had serialised)
+  __shared__ float part[3][kBlock / kWave];
   float a = 0.0f, p = 0.0f, w = 0.0f;
-  const int64_t id = i < n_act ? (active ? active[i] : i) : -1;
-  if (id >= 0 && id < m) {
-    if (g_acc)
-      a = fmaxf(fabsf(g_acc[3 * id]), fmaxf(fabsf(g_acc[3 * id + 1]), fabsf(g_acc[3 * id + 2])));
-    if (g_pot) p = fabsf(g_pot[id]);
+  const int64_t n = n_act > m ? n_act : m;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = i < n_act ? (active ? active[i] : i) : -1;
+    if (id >= 0 && id < m) {
+      if (g_acc)
+        a = fmaxf(a, fmaxf(fabsf(g_acc[3 * id]),
+                           fmaxf(fabsf(g_acc[3 * id + 1]), fabsf(g_acc[3 * id + 2]))));
+      if (g_pot) p = fmaxf(p, fabsf(g_pot[id]));
+    }
+    if (i < m) w = fmaxf(w, fabsf(xm[i].w));
   }
-  if (i < m) w = fabsf(xm[i].w);
 #pragma unroll
   for (int k = 1; k < kWave; k <<= 1) {
     a = fmaxf(a, __shfl_xor(a, k));
     p = fmaxf(p, __shfl_xor(p, k));
     w = fmaxf(w, __shfl_xor(w, k));
   }
+  const int wv = (int)(threadIdx.x >> 6);
   if ((threadIdx.x & 63u) == 0u) {
-    atomicMax(&mx[0], __float_as_uint(a));
-    atomicMax(&mx[1], __float_as_uint(p));
-    atomicMax(&mx[2], __float_as_uint(w));
+    part[0][wv] = a;
+    part[1][wv] = p;
+    part[2][wv] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3u) {
+    float v = part[threadIdx.x][0];
+    for (int k = 1; k < kBlock / kWave; ++k) v = fmaxf(v, part[threadIdx.x][k]);
+    atomicMax(&mx[threadIdx.x], __float_as_uint(v));
   }
 }
 
@@ -996,7 +1012,8 @@ hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_g
     k_zero_f4<<<nblk(4 * nn), kBlock, 0, s>>>((float4 *)gnode_fx, 4 * nn);
     k_zero_f4<<<1, kBlock, 0, s>>>((float4 *)mx, 1);
     const int64_t nb = na > m ? na : m;
-    k_fx_bound<<<nblk(nb), kBlock, 0, s>>>(active, na, g_acc, g_pot, all.xm, m, mx);
+    const unsigned gb = nblk(nb) < (unsigned)kFxBoundBlocks ? nblk(nb) : (unsigned)kFxBoundBlocks;
+    k_fx_bound<<<gb, kBlock, 0, s>>>(active, na, g_acc, g_pot, all.xm, m, mx);
     if (max_groups > 0)
       k_gravity_bwd<true>
           <<<persistent_grid((const void *)k_gravity_bwd<true>, kBlock, max_groups), kBlock, 0,

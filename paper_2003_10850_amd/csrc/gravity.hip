@@ -195,11 +195,14 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       const int take = min(c, kTile - tc);
       if (lane < take) {
         Entry e;
-        e.p = xm[st + lane];  // FP32 mass (and FP32 position on the plain path)
         if constexpr (kF64) {
+          // the FP32 offset from the group centre; the fourth slot holds the
+          // (FP32) mass exactly
           const double4 q = x64[st + lane];
           e.p = make_float4((float)(q.x - c64.x), (float)(q.y - c64.y), (float)(q.z - c64.z),
-                            e.p.w);
+                            (float)q.w);
+        } else {
+          e.p = xm[st + lane];
         }
         e.meta = make_int4(st + lane, (int)(uint32_t)omask, (int)(uint32_t)(omask >> 32), 0);
         tile[tc + lane] = e;

@@ -805,30 +805,25 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
           // the density's bands with E bounded by gext + H near the
           // threshold, E H <= 3 H^2 + gext^2: a narrow group decides on the
           // high parts outside 2^-19 (3 H^2 + gext^2) of it; a wide one
-          // takes the low parts within that band or closer and decides on
-          // them outside 2^-19 (H^2 + 2^-20 (3 H^2 + gext^2)); inside the
-          // band the FP64 test decides
+          // adds the low parts to every entry and decides on them outside
+          // 2^-19 (H^2 + 2^-20 (3 H^2 + gext^2)); inside the band the FP64
+          // test decides (rare: a wave-uniform branch)
           const float H2 = fmaxf(hi2, hj2);
           const float eb = 3.0f * H2 + ext2;
-          in = false;
-          if (valid && r2 < H2 + kBandOff * eb) {
-            float bd = kBandOff * eb;
-            int j = 0;
-            if constexpr (kRefine) {
-              const float4 l = tlos[w][k];
-              dx += sub_exact(l.x, xl.x);
-              dy += sub_exact(l.y, xl.y);
-              dz += sub_exact(l.z, xl.z);
-              r2 = dist2_exact(dx, dy, dz);
-              bd = kBandOff * (H2 + ldexpf(eb, -20));
-              j = __float_as_int(l.w);
-            }
-            if (fabsf(r2 - H2) <= bd) {
-              if constexpr (!kRefine) j = __float_as_int(tlos[w][k].w);
-              in = within64(x64[s], x64[j], fmax(hi64, h64[j]));
-            } else {
-              in = r2 < hi2 || r2 < hj2;
-            }
+          float bd = kBandOff * eb;
+          if constexpr (kRefine) {
+            const float4 l = tlos[w][k];
+            dx += sub_exact(l.x, xl.x);
+            dy += sub_exact(l.y, xl.y);
+            dz += sub_exact(l.z, xl.z);
+            r2 = dist2_exact(dx, dy, dz);
+            bd = kBandOff * (H2 + ldexpf(eb, -20));
+          }
+          in = r2 < H2;
+          const bool near = valid && fabsf(r2 - H2) <= bd;
+          if (__ballot(near) != 0ull && near) {
+            const int j = __float_as_int(tlos[w][k].w);
+            in = within64(x64[s], x64[j], fmax(hi64, h64[j]));
           }
         }
         if (in) {
