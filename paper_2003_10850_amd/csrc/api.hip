@@ -11,10 +11,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "g3_device.h"
 #include "g3_internal.h"
 
 namespace g3 {
+
+// A roctx range around each interaction and build call, named after the
+// entry point: a timeline under rocprofv3 --marker-trace shows every C-ABI
+// call with the kernels it launched (a no-op when no profiler listens).
+struct RocTxRange {
+  explicit RocTxRange(const char *name) { roctxRangePush(name); }
+  ~RocTxRange() { roctxRangePop(); }
+  RocTxRange(const RocTxRange &) = delete;
+  RocTxRange &operator=(const RocTxRange &) = delete;
+};
+#define G3_RANGE(name) const ::g3::RocTxRange g3_range_(name)
 
 int select_members(g3_ctx *c, g3_tree *t, const uint8_t *type, int64_t *m_out, hipStream_t s);
 
@@ -534,6 +547,7 @@ static int build_forest_body(g3_ctx *c, g3_tree *t, int32_t n_snap, const int64_
 int g3_build_forest(g3_ctx *c, int32_t n_snap, const int64_t *snap_off, int32_t pos_t,
                     const void *pos, const float *mass, const uint8_t *type, const double *box,
                     const g3_params *p, g3_tree **tree, void *stream) {
+  G3_RANGE("g3_build_forest");
   if (!c) return G3_EINVAL;
   if (n_snap < 1 || n_snap > G3_MAX_SNAPSHOTS || !snap_off || !box)
     return fail(c, G3_EINVAL, "g3_build_forest: need 1..G3_MAX_SNAPSHOTS snapshots, offsets and boxes");
@@ -665,6 +679,7 @@ int g3_build_tree(g3_ctx *c, int64_t n, int32_t pos_t, const void *pos, const fl
 }
 
 int g3_refit_tree(g3_ctx *c, g3_tree *t, const void *pos, const float *mass, void *stream) {
+  G3_RANGE("g3_refit_tree");
   if (!c) return G3_EINVAL;
   if (!t) return fail(c, G3_EINVAL, "g3_refit_tree: null tree");
   if (t->owner != c) return fail(c, G3_ESTATE, "g3_refit_tree: tree of another ctx");
@@ -708,6 +723,7 @@ int g3_tree_info(const g3_tree *t, int32_t which, int64_t *n_members, int64_t *n
 int g3_tree_export(g3_ctx *c, const g3_tree *t, int32_t which, int32_t *order, uint64_t *keys,
                    int32_t *node_start, int32_t *node_count, int32_t *node_level,
                    int32_t *node_skip, double *node_mass, double *node_com, void *stream) {
+  G3_RANGE("g3_tree_export");
   if (!c) return G3_EINVAL;
   if (!t || (which != 0 && which != 1)) return fail(c, G3_EINVAL, "g3_tree_export: bad tree");
   if (t->owner != c) return fail(c, G3_ESTATE, "g3_tree_export: tree of another ctx");
@@ -827,6 +843,7 @@ static int active_args_ok(g3_ctx *c, const g3_tree *t, int64_t n_act, const int3
 int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int32_t *active,
             const void *h, const g3_params *p, int64_t capacity, int64_t *offsets,
             int32_t *list, int64_t *total, void *stream) {
+  G3_RANGE("g3_walk");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, tc, n_act, active, "g3_walk");
   if (st) return st;
@@ -886,6 +903,7 @@ int g3_walk(g3_ctx *c, const g3_tree *tc, int32_t kind, int64_t n_act, const int
 int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
                const g3_params *p, int32_t solve_h, void *h, float *rho, float *drho_dh,
                float *omega, int32_t *nngb, void *stream) {
+  G3_RANGE("g3_density");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_density");
   if (st) return st;
@@ -914,6 +932,7 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
                    const g3_params *p, const float *vel, const float *u, const void *h,
                    const float *rho, const float *omega, float *acc, float *dudt, float *vsig,
                    int32_t *npairs, void *stream) {
+  G3_RANGE("g3_hydro_force");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_hydro_force");
   if (st) return st;
@@ -944,6 +963,7 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
 
 int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
                const g3_params *p, float *acc, float *pot, int32_t *nterms, void *stream) {
+  G3_RANGE("g3_gravity");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_gravity");
   if (st) return st;
@@ -968,6 +988,7 @@ int g3_conduction(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
                   const g3_params *p, double kappa0, double kappa_exp, const float *u,
                   const void *h, const float *rho, float *dudt, int32_t *npairs,
                   void *stream) {
+  G3_RANGE("g3_conduction");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_conduction");
   if (st) return st;
@@ -1016,6 +1037,7 @@ static bool switch_params_ok(const g3_switch_params *sp) {
 int g3_velocity_gradients(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
                           const g3_params *p, const float *vel, const void *h, const float *rho,
                           const float *omega, float *div_v, float *curl_v, void *stream) {
+  G3_RANGE("g3_velocity_gradients");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_velocity_gradients");
   if (st) return st;
@@ -1050,6 +1072,7 @@ int g3_viscosity_switch(g3_ctx *c, int64_t n, int32_t h_type, int64_t n_act,
                         const int32_t *active, const g3_params *p, const g3_switch_params *sw,
                         double dt, const float *u, const void *h, const float *div_v,
                         const float *curl_v, float *alpha, float *balsara, void *stream) {
+  G3_RANGE("g3_viscosity_switch");
   if (!c) return G3_EINVAL;
   if (n < 0 || n_act < 0 || (!active && n_act != n) || (h_type != G3_F32 && h_type != G3_F64))
     return fail(c, G3_EINVAL, "g3_viscosity_switch: bad sizes");
@@ -1082,6 +1105,7 @@ int g3_hydro_force_switches(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
                             const float *omega, const float *alpha, const float *balsara,
                             float *acc, float *dudt, float *vsig, int32_t *npairs,
                             void *stream) {
+  G3_RANGE("g3_hydro_force_switches");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_hydro_force_switches");
   if (st) return st;
@@ -1256,6 +1280,7 @@ static int integ_build(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, cons
 int g3_integrate_start(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3_state *st,
                        const double *box, const g3_params *p, const g3_integ_params *ip,
                        void *stream) {
+  G3_RANGE("g3_integrate_start");
   if (!c) return G3_EINVAL;
   if (!tree) return fail(c, G3_EINVAL, "g3_integrate_start: null tree handle");
   if (!integ_args_ok(c, n, pos_t, st, box, p, ip, "g3_integrate_start")) return G3_EINVAL;
@@ -1283,6 +1308,7 @@ int g3_integrate_start(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, cons
 int g3_system_step(g3_ctx *c, g3_tree **tree, int64_t n, int32_t pos_t, const g3_state *st,
                    const double *box, const g3_params *p, const g3_integ_params *ip,
                    int64_t *tick_active, void *stream) {
+  G3_RANGE("g3_system_step");
   if (!c) return G3_EINVAL;
   if (!tree) return fail(c, G3_EINVAL, "g3_system_step: null tree handle");
   if (!integ_args_ok(c, n, pos_t, st, box, p, ip, "g3_system_step")) return G3_EINVAL;
@@ -1428,6 +1454,7 @@ static int time_candidate(g3_ctx *c, hipStream_t s, hipEvent_t e0, hipEvent_t e1
 int g3_autotune(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active, const g3_params *p,
                 const void *h, const float *vel, const float *u, const float *rho,
                 const float *omega, void *stream) {
+  G3_RANGE("g3_autotune");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_autotune");
   if (st) return st;
@@ -1561,6 +1588,7 @@ int g3_density_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *act
                         const float *drho_dh, const float *g_rho, const float *g_drho_dh,
                         const float *g_omega, float *g_pos, float *g_mass, float *g_h,
                         void *stream) {
+  G3_RANGE("g3_density_backward");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_density_backward");
   if (st) return st;
@@ -1592,6 +1620,7 @@ int g3_density_solve_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_
                               const g3_params *p, const float *h, const float *rho,
                               const float *drho_dh, const float *g_h, float *g_pos,
                               float *g_mass, void *stream) {
+  G3_RANGE("g3_density_solve_backward");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_density_solve_backward");
   if (st) return st;
@@ -1625,6 +1654,7 @@ int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
                             const float *g_acc, const float *g_dudt, float *g_pos, float *g_vel,
                             float *g_mass, float *g_h, float *g_u, float *g_rho,
                             float *g_omega, void *stream) {
+  G3_RANGE("g3_hydro_force_backward");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_hydro_force_backward");
   if (st) return st;
@@ -1659,6 +1689,7 @@ int g3_hydro_force_backward(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t 
 int g3_gravity_backward(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active,
                         const g3_params *p, const float *g_acc, const float *g_pot,
                         float *g_pos, float *g_mass, void *stream) {
+  G3_RANGE("g3_gravity_backward");
   if (!c) return G3_EINVAL;
   int st = active_args_ok(c, t, n_act, active, "g3_gravity_backward");
   if (st) return st;
