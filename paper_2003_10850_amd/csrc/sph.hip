@@ -166,6 +166,10 @@ __global__ __launch_bounds__(kBlock) void k_density(
     }
   }
   HT lo = HT(0), hi = HT(INFINITY);
+  // the previous evaluation of the solve: its h, f and f' (have_prev: set)
+  HT h_prev = HT(0);
+  float f_prev = 0.0f, g_prev = 0.0f;
+  bool have_prev = false;
   bool done = !valid;
   // results of the accepted evaluation
   HT res_h = hcur;
@@ -484,37 +488,70 @@ __global__ __launch_bounds__(kBlock) void k_density(
         const float slope = 3.0f + swh / sw;
         // Halley step on f(s) = ln(N_eff / N_ngb) (cubic convergence: about
         // one walk pass fewer than Newton from the node-density first
-        // guess), in the precision of h; the log of the ratio (not a
-        // difference of logs) keeps the step accurate to a few 1e-8 near the
-        // root, well inside the convergence test below. Far from the root,
-        // where the curvature factor leaves [1/2, 2], it is a Newton step.
-        HT hn;
-        if (N == n_ngb) hn = hcur;
-        else if (slope > 0.05f) {
-          if constexpr (kF64) {
-            // FP64 h: the step in FP32 transcendentals, accurate to about
-            // 1e-7 of itself (N is an FP32 sum; N - N_ngb is exact near the
-            // root), applied to h in FP64 as h + h expm1(d); FP64 log and
-            // exp here would set the kernel's register count
-            const float f = log1pf((N - n_ngb) / n_ngb);
-            const float curv = sss / sw - slope * slope;
-            const float den = 1.0f - f * (curv / (2.0f * slope * slope));
-            float d = -f / slope;
-            if (den > 0.5f && den < 2.0f) d /= den;
-            hn = hcur + hcur * (HT)expm1f(d);
-          } else {
-            const HT f = (HT)log((HT)N / (HT)n_ngb);
-            const float curv = sss / sw - slope * slope;
-            const HT den = HT(1) - f * (HT)(curv / (2.0f * slope * slope));
-            HT d = -f / (HT)slope;
-            if (den > HT(0.5) && den < HT(2)) d /= den;
-            hn = hcur * (HT)exp(d);
+        // guess), in FP32; the log of the ratio (not a difference of logs;
+        // log1p of the relative difference with FP64 h) keeps the step
+        // accurate to a few 1e-8 near the root, well inside the convergence
+        // test below. Far from the root, where the curvature factor leaves
+        // [1/2, 2], it is a Newton step.
+        HT hn, hstep;  // the Halley (or Newton) step, which decides convergence; the next h
+        if (N == n_ngb) {
+          hn = hstep = hcur;
+          have_prev = false;
+        } else if (slope > 0.05f) {
+          const float f = kF64 ? log1pf((N - n_ngb) / n_ngb) : logf(N / n_ngb);
+          const float curv = sss / sw - slope * slope;
+          const float den = 1.0f - f * (curv / (2.0f * slope * slope));
+          const bool halley = den > 0.5f && den < 2.0f;
+          float d = -f / slope;
+          if (halley) d /= den;
+          // With the previous evaluation at distance D = ln(h_prev / h), the
+          // quartic in t = ln h - ln h_now that matches f, f', f'' here and
+          // f, f' there has a root that is more accurate than Halley's step by
+          // about the factor D^2 / 20 (Hermite interpolation error): from a
+          // far first guess it saves the solve's last walk. Newton on the
+          // quartic from Halley's step; kept only if it stays close to it.
+          float dq = d;
+          if (halley && have_prev) {
+            const float D = logf((float)(h_prev / hcur));
+            if (fabsf(D) > 1e-4f && fabsf(D) < 1.5f) {
+              const float R0 = f_prev - f - D * (slope + 0.5f * curv * D);
+              const float R1 = g_prev - slope - curv * D;
+              const float D2 = D * D, D3 = D2 * D;
+              const float b4 = (R1 - 3.0f * R0 / D) / D3;
+              const float a3 = (R0 - b4 * D3 * D) / D3;
+              float t = d;
+#pragma unroll
+              for (int it = 0; it < 3; ++it) {
+                const float pv = f + t * (slope + t * (0.5f * curv + t * (a3 + t * b4)));
+                const float dp = slope + t * (curv + t * (3.0f * a3 + 4.0f * b4 * t));
+                t -= pv / dp;
+              }
+              if (isfinite(t) && fabsf(t - d) <= 0.5f * fabsf(d)) dq = t;
+            }
           }
-        } else hn = below ? HT(2) * hcur : HT(0.5) * hcur;
+          h_prev = hcur;
+          f_prev = f;
+          g_prev = slope;
+          have_prev = true;
+          if constexpr (kF64) {
+            // FP64 h: steps in FP32 transcendentals, accurate to about 1e-7
+            // of themselves (N is an FP32 sum; N - N_ngb is exact near the
+            // root), applied in FP64 as h + h expm1(d); FP64 log and exp here
+            // would set the kernel's register count
+            hstep = hcur + hcur * (HT)expm1f(d);
+            hn = hcur + hcur * (HT)expm1f(dq);
+          } else {
+            hstep = hcur * expf(d);
+            hn = hcur * expf(dq);
+          }
+        } else {
+          hn = hstep = below ? HT(2) * hcur : HT(0.5) * hcur;
+          have_prev = false;
+        }
         // converged when the Newton correction itself is below half the
         // tolerance (h then lies within it of the root), or the bracket has
         // closed; tested before any safeguard replaces the step
-        const bool conv = fabs(hn - hcur) <= HT(0.5) * (HT)tol * hcur ||
+        const bool conv = fabs(hstep - hcur) <= HT(0.5) * (HT)tol * hcur ||
                           (hi < HT(INFINITY) && hi - lo <= (HT)tol * hi);
         hn = hn < HT(0.25) * hcur ? HT(0.25) * hcur : (hn > HT(4) * hcur ? HT(4) * hcur : hn);
         if (!(hn > lo && hn < hi)) {
