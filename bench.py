@@ -90,25 +90,31 @@ def _oracle_ops(gt, at, p, vel, u, fields, sd, sh, sg):
     return (t_d, t_h, t_g), inter, (d, hy, g)
 
 
-def _errors(gt, p, gpu, sd, sh, sg, ref) -> dict:
-    """Errors of one GPU step against the oracle on the sampled rows: h
-    against the oracle's own solve; rho and the neighbour counts at the
-    GPU's h; hydro and gravity accelerations relative to the sum S of the
+def _errors(gt, p, gpu, fields, sd, sh, sg, ref) -> dict:
+    """Errors of one GPU step against the oracle on the sampled rows, the
+    oracle reading only its own or synthetic inputs: the solved h against
+    the oracle's own solve (h_rel), and the density there against the
+    oracle's at its h (rho_solved_rel, which carries the difference of the
+    two h); rho and the neighbour counts of the GPU's check call at the
+    synthetic h (rho_rel); the hydro acceleration of its check call at the
+    synthetic fields and the step's gravity, relative to the sum S of the
     magnitudes of their terms; counts must be exact."""
     import oracle
     d, hy, g = ref
-    h = gpu["h"].astype(np.float64)
-    at_h = oracle.density(gt, p, active=sd, h=h, solve_h=False)
+    hm = fields[0]
+    at_m = oracle.density(gt, p, active=sd, h=hm, solve_h=False)
     rel = lambda a, b: np.abs(a - b) / np.abs(b)
+    h = gpu["h"].astype(np.float64)
     e = {
         "h_rel": float(rel(h[sd], d["h"][sd]).max()),
-        "rho_rel": float(rel(gpu["rho"][sd], at_h["rho"][sd]).max()),
-        "hydro_acc_rel_S": float((np.linalg.norm(gpu["acc"][sh] - hy["acc"][sh], axis=1) /
+        "rho_solved_rel": float(rel(gpu["rho"][sd], d["rho"][sd]).max()),
+        "rho_rel": float(rel(gpu["rho_m"][sd], at_m["rho"][sd]).max()),
+        "hydro_acc_rel_S": float((np.linalg.norm(gpu["acc_m"][sh] - hy["acc"][sh], axis=1) /
                                   hy["S"][sh]).max()),
         "grav_acc_rel_S": float((np.linalg.norm(gpu["gacc"][sg] - g["acc"][sg], axis=1) /
                                  g["S"][sg]).max()),
-        "counts_exact": bool(np.array_equal(gpu["nngb"][sd], at_h["nngb"][sd]) and
-                             np.array_equal(gpu["npairs"][sh], hy["npairs"][sh]) and
+        "counts_exact": bool(np.array_equal(gpu["nngb_m"][sd], at_m["nngb"][sd]) and
+                             np.array_equal(gpu["npairs_m"][sh], hy["npairs"][sh]) and
                              np.array_equal(gpu["nterms"][sg], g["nterms"][sg])),
         "samples": {"density": int(sd.size), "hydro": int(sh.size), "gravity": int(sg.size)},
     }
@@ -122,7 +128,8 @@ def cpu_baseline(w, samples: int, gpu=None, seed: int = 0) -> dict:
     fraction. On every host core: the median of three passes (each over a
     third of the sample); on one thread: one pass over a sixteenth. With the
     plain GPU step's outputs (gpu), also that step's errors on the first
-    pass's samples, the hydro evaluated at the GPU's h, rho and Omega."""
+    pass's samples (see _errors). The hydro is evaluated at the generating
+    model's smooth fields (h, gas density, Omega = 1)."""
     import oracle
 
     pos32, vel32, m32, u32 = w.as_f32()
@@ -134,14 +141,10 @@ def cpu_baseline(w, samples: int, gpu=None, seed: int = 0) -> dict:
     gt = oracle.Tree(P, M, w.box, type=w.type, gas_only=True)
     at = oracle.Tree(P, M, w.box, type=w.type)
     t_build = time.perf_counter() - t0
-    if gpu is not None:
-        fields = (gpu["h"].astype(np.float64), gpu["rho"].astype(np.float64),
-                  gpu["omega"].astype(np.float64))
-    else:  # the generating model's smooth fields
-        from paper_2003_10850_amd import inputs
-        fields = (inputs.model_smoothing(w).astype(np.float32).astype(np.float64),
-                  inputs.model_gas_density(w).astype(np.float32).astype(np.float64),
-                  np.ones(w.n))
+    from paper_2003_10850_amd import inputs
+    fields = (inputs.model_smoothing(w).astype(np.float32).astype(np.float64),
+              inputs.model_gas_density(w).astype(np.float32).astype(np.float64),
+              np.ones(w.n))
 
     def draw(k):
         return (np.sort(rng.choice(gas, min(k, gas.size), replace=False)),
@@ -190,7 +193,7 @@ def cpu_baseline(w, samples: int, gpu=None, seed: int = 0) -> dict:
     }
     if gpu is not None:
         samp, ref = first
-        out["gpu_errors"] = _errors(gt, p, gpu, *samp, ref)
+        out["gpu_errors"] = _errors(gt, p, gpu, fields, *samp, ref)
     return out
 
 
@@ -199,8 +202,8 @@ def batched_errors(check, n_pick: int = 4, per: int = 300, seed: int = 5) -> dic
     n_pick snapshots drawn at random (those with active gas), up to `per`
     active gas particles (density, hydro) and active particles (gravity)
     each; the FP32 forest with FP32 decisions, the mixed-precision forest
-    (FP64 positions) with FP64 decisions. The hydro is evaluated at the
-    step's own h, rho and Omega."""
+    (FP64 positions) with FP64 decisions. Density and hydro are compared at
+    the generating model's fields (see _errors)."""
     import dataclasses
     import oracle
     b = check["batch"]
@@ -226,11 +229,11 @@ def batched_errors(check, n_pick: int = 4, per: int = 300, seed: int = 5) -> dic
             sd = np.sort(rng.choice(ag, min(per, ag.size), replace=False))
             sg = np.sort(rng.choice(a, min(per, a.size), replace=False))
             g = {f: v[r0:r1] for f, v in gpu.items()}
-            fields = (g["h"].astype(np.float64), g["rho"].astype(np.float64),
-                      g["omega"].astype(np.float64))
+            fields = (check["hm"][r0:r1].astype(np.float64), check["rm"][r0:r1].astype(np.float64),
+                      np.ones(r1 - r0))
             _, _, ref = _oracle_ops(gt, at, p, b.vel[r0:r1].astype(np.float32),
                                     b.u[r0:r1].astype(np.float32), fields, sd, sd, sg)
-            e = _errors(gt, p, g, sd, sd, sg, ref)
+            e = _errors(gt, p, g, fields, sd, sd, sg, ref)
             for f, v in e.items():
                 if f == "counts_exact":
                     worst[f] = worst.get(f, True) and v
@@ -259,11 +262,10 @@ def precision_errors(check, k: int = 10_000, seed: int = 11) -> dict:
     M = w.mass.astype(np.float32).astype(np.float64)
     gt = oracle.Tree(w.pos, M, w.box, type=w.type, gas_only=True)
     at = oracle.Tree(w.pos, M, w.box, type=w.type)
-    fields = (gpu["h"].astype(np.float64), gpu["rho"].astype(np.float64),
-              gpu["omega"].astype(np.float64))
+    fields = (check["hm"], check["rm"].astype(np.float64), np.ones(w.n))
     _, _, ref = _oracle_ops(gt, at, p, w.vel.astype(np.float32), w.u.astype(np.float32),
                             fields, sd, sd, sg)
-    return _errors(gt, p, gpu, sd, sd, sg, ref)
+    return _errors(gt, p, gpu, fields, sd, sd, sg, ref)
 
 
 COPY_BYTES = 256 << 20  # the calibration copy: 256 MiB read + 256 MiB written
@@ -335,6 +337,20 @@ def step_roofline(counts, ms: float) -> dict:
     achieved = flop / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS}
+
+
+def _check_calls(tree, vel, u, hm, rm, active=None) -> dict:
+    """Outside every timed region: the density and the hydro force of the
+    same tree at synthetic inputs (the generating model's h and gas density,
+    Omega = 1), which the oracle then reads too, so that the error figures
+    never feed a GPU output to the oracle. hm in the tree's dtype."""
+    import torch
+    from paper_2003_10850_amd import ops
+    dm = ops.density(tree, h=hm, active=active, solve_h=False)
+    hy = ops.hydro_force(tree, vel, u, hm, rm, torch.ones_like(rm), active=active)
+    torch.cuda.synchronize()
+    return {"rho_m": dm["rho"].cpu().numpy(), "nngb_m": dm["nngb"].cpu().numpy(),
+            "acc_m": hy["acc"].cpu().numpy(), "npairs_m": hy["npairs"].cpu().numpy()}
 
 
 def _host_outputs(o) -> dict:
@@ -440,6 +456,12 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
     inter = i_d + i_h + i_g
     nonconv = ctx.nonconverged(reset=True)
     check = {"batch": b, "fp32": _host_outputs(B)}
+    # synthetic fields for the error figures: the generating models' h and
+    # gas density per snapshot (boxes at their own places)
+    hm = np.concatenate([inputs.model_smoothing(x) for x in b.snaps])
+    rm = np.concatenate([inputs.model_gas_density(x) for x in b.snaps]).astype(np.float32)
+    check["hm"], check["rm"] = hm.astype(np.float32), rm
+    check["fp32"].update(_check_calls(tree, vel, u, T(check["hm"]), T(rm), active=act))
     print(f"bench: batched graph {graph_ms:.3f} ms/step, eager {eager_ms:.3f} ms/step, "
           f"build {build_ms:.2f} ms; interactions {inter}", file=sys.stderr, flush=True)
 
@@ -475,6 +497,8 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
            int(B["nterms"][act.long()].sum()))
     i64 = sum(k64)
     check["mixed"] = _host_outputs(dict(B, h=H64))
+    check["mixed"].update(_check_calls(tree64, vel, u, T(check["hm"].astype(np.float64)), T(rm),
+                                       active=act))
     tree64.close()
     ctx.nonconverged(reset=True)
     print(f"bench: batched mixed precision {mixed_ms:.3f} ms/step", file=sys.stderr, flush=True)
@@ -650,8 +674,17 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
     nonconv = ctx.nonconverged(reset=True)
     print(f"bench: precision {ms:.3f} ms/step, {inter} interactions", file=sys.stderr,
           flush=True)
-    check = {"w": w, "gpu": _host_outputs(dict(od, acc=oh["acc"], npairs=oh["npairs"],
-                                               gacc=og["acc"], nterms=og["nterms"]))}
+    # synthetic fields for the error figures (a gas mass histogram at this
+    # size: the model's sum over 256 spheres for 2e7 particles is slow)
+    rm64 = inputs.grid_gas_density(w, cells=128)
+    hm = (3.0 * w.params.n_ngb * w.mass / (4.0 * np.pi * rm64)) ** (1.0 / 3.0)
+    rm = rm64.astype(np.float32)
+    del rm64
+    cc = _check_calls(tree, vel, u, T(hm), T(rm))
+    check = {"w": w, "hm": hm, "rm": rm,
+             "gpu": _host_outputs(dict(od, acc=oh["acc"], npairs=oh["npairs"], gacc=og["acc"],
+                                       nterms=og["nterms"]))}
+    check["gpu"].update(cc)
     tree.close()
     return check, {
         "workload": f"{w.name}: N={n} in 256 Plummer spheres + 20% background (half gas), "
@@ -847,6 +880,8 @@ def main() -> int:
     times = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
     plain_out = _host_outputs(dict(outd, h=d["h"], acc=outh["acc"], npairs=outh["npairs"],
                                    gacc=outg["acc"], nterms=outg["nterms"]))
+    plain_out.update(_check_calls(tree, vel, u, T(inputs.model_smoothing(w).astype(np.float32)),
+                                  T(inputs.model_gas_density(w).astype(np.float32))))
     ms_interactions = times["density"] + times["hydro"] + times["gravity"]
     print(f"bench: {args.steps} steps, {ms:.3f} ms/step; per op ms {times}; "
           f"interactions dens {i_d} hydro {i_h} grav {i_g}; nonconv {nonconv}",

@@ -1,8 +1,9 @@
 """The differentiation workload at full size: N = 2^20 clustered particles
-(FP32), loss = sum over gas of (log rho)^2 + (1/2) sum m phi at the solved
-h, gradients with respect to positions, masses and h through the autograd
-functions (walks recomputed in the backward), checked against the oracle's
-adjoints on a random subset of 4096 particles.
+(FP32), loss = sum over gas of (log rho)^2 + (1/2) sum m phi at a given h
+(the generating model's: an input both sides read, where the benchmark
+takes the GPU's solved h), gradients with respect to positions, masses and
+h through the autograd functions (walks recomputed in the backward),
+checked against the oracle's adjoints on a random subset of 4096 particles.
 
 The bar is the adjoint bar (1e-5 of the oracle's L1 sum of the
 contributions to each entry, floored at 1e-7 of the array's median).
@@ -41,8 +42,7 @@ def test_loss_gradient_full_size_subset():
     pos32, _, m32, _ = w.as_f32()
     ctx = ops.Context(torch.device("cuda", 0))
     tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(w.type), tuple(w.box), w.params)
-    h = ops.density(tree)["h"].detach()
-    assert ctx.nonconverged(reset=True) == 0
+    h = dev_t(inputs.model_smoothing(w).astype(np.float32))
     pos = dev_t(pos32).requires_grad_(True)
     mass = dev_t(m32).requires_grad_(True)
     h.requires_grad_(True)

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_util import check_solved_density
 from paper_2003_10850_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -138,8 +139,12 @@ def test_forest_density_solve(ctx):
     fo = Forest(ctx, F)
     act = forest_active(F, 5)
     d = ops.density(fo.tree, active=dev_t(act))
-    h = host(d["h"]).astype(np.float64)
+    h, rho = host(d["h"]).astype(np.float64), host(d["rho"])
     nonconv = 0
+    # the oracle's solved h (FP32-rounded) is then given to both sides for
+    # exact counts and sums at one h
+    hg = np.ones(len(F["type"]), np.float32)
+    checked = []
     for k, w in enumerate(F["snaps"]):
         r = fo.snap_rows(k)
         a = np.intersect1d(act, r[F["type"][r] == 0]) - F["off"][k]
@@ -151,13 +156,18 @@ def test_forest_density_solve(ctx):
             nonconv += a.size  # too few gas particles for any root
             continue
         ref = oracle.density(gt, F["params"], active=a)
-        rel = np.abs(h[a + F["off"][k]] - ref["h"][a]) / ref["h"][a]
-        assert rel.max() < TOL, f"snapshot {k}: h max rel {rel.max():.3e}"
-        at = oracle.density(gt, F["params"], active=a, h=h[r], solve_h=False)
-        np.testing.assert_array_equal(host(d["nngb"])[a + F["off"][k]], at["nngb"][a])
-        err = np.abs(host(d["rho"])[a + F["off"][k]] - at["rho"][a]) / at["rho"][a]
-        assert err.max() < TOL, f"snapshot {k}: rho {err.max():.3e}"
+        check_solved_density(h[r], rho[r], ref, a, TOL, TOL, f"snapshot {k}")
+        hg[a + F["off"][k]] = ref["h"][a].astype(np.float32)
+        checked.append((k, a, gt))
     assert fo.tree.ctx.nonconverged(reset=True) == nonconv
+    dg = ops.density(fo.tree, h=dev_t(hg), active=dev_t(act), solve_h=False)
+    fo.tree.ctx.nonconverged(reset=True)
+    for k, a, gt in checked:
+        r = fo.snap_rows(k)
+        at = oracle.density(gt, F["params"], active=a, h=hg[r].astype(np.float64), solve_h=False)
+        np.testing.assert_array_equal(host(dg["nngb"])[a + F["off"][k]], at["nngb"][a])
+        err = np.abs(host(dg["rho"])[a + F["off"][k]] - at["rho"][a]) / at["rho"][a]
+        assert err.max() < TOL, f"snapshot {k}: rho {err.max():.3e}"
 
 
 def test_forest_hydro_and_gravity(ctx):
@@ -282,8 +292,10 @@ def test_forest_mixed_precision_density(ctx):
     fo = Forest(ctx, F)
     d = ops.density(fo.tree)
     assert d["h"].dtype == torch.float64
-    h = host(d["h"])
+    h, rho = host(d["h"]), host(d["rho"])
     pr = dataclasses.replace(F["params"], flags=oracle.FLAG_FP64_DECISIONS)
+    hg = np.ones(len(F["type"]))  # the oracle's solved h, given to both sides
+    checked = []
     for k, w in enumerate(F["snaps"]):
         r = fo.snap_rows(k)
         ng = int((F["type"][r] == 0).sum())
@@ -292,11 +304,18 @@ def test_forest_mixed_precision_density(ctx):
         a = np.nonzero(F["type"][r] == 0)[0]
         gt = fo.otree(k, True)
         ref = oracle.density(gt, pr, active=a)
-        rel = np.abs(h[r][a] - ref["h"][a]) / ref["h"][a]
-        assert rel.max() < 2e-6, f"snapshot {k}: h {rel.max():.3e}"
-        at = oracle.density(gt, pr, active=a, h=h[r], solve_h=False)
-        np.testing.assert_array_equal(host(d["nngb"])[r][a], at["nngb"][a])
+        check_solved_density(h[r], rho[r], ref, a, 2e-6, 1e-5, f"snapshot {k}")
+        hg[a + F["off"][k]] = ref["h"][a]
+        checked.append((k, a, gt))
     fo.tree.ctx.nonconverged(reset=True)
+    dg = ops.density(fo.tree, h=dev_t(hg), solve_h=False)
+    fo.tree.ctx.nonconverged(reset=True)
+    for k, a, gt in checked:
+        r = fo.snap_rows(k)
+        at = oracle.density(gt, pr, active=a, h=hg[r], solve_h=False)
+        np.testing.assert_array_equal(host(dg["nngb"])[r][a], at["nngb"][a])
+        err = np.abs(host(dg["rho"])[r][a] - at["rho"][a]) / at["rho"][a]
+        assert err.max() < 1e-5, f"snapshot {k}: rho {err.max():.3e}"
 
 
 def test_forest_argument_checks(ctx):

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_util import check_solved_density
 from paper_2003_10850_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -116,16 +117,14 @@ def density_check(c, active=None, solve=True):
     act_gas = c.gas if active is None else np.intersect1d(active, c.gas)
     a_t = None if active is None else dev_t(active.astype(np.int32))
     if solve:
-        d = ops.density(c.tree, active=a_t)
+        ds = ops.density(c.tree, active=a_t)
         ref = oracle.density(c.gt, c.p, active=act_gas)
-        h_gpu = host(d["h"]).astype(np.float64)
-        rel = np.abs(h_gpu[act_gas] - ref["h"][act_gas]) / ref["h"][act_gas]
-        assert rel.max() < TOL, f"h: max rel {rel.max():.3e}"
+        check_solved_density(host(ds["h"]), host(ds["rho"]), ref, act_gas, TOL, TOL)
         assert c.tree.ctx.nonconverged(reset=True) == 0
-    else:
-        h_gpu = inputs.model_smoothing(c.w).astype(np.float32).astype(np.float64)
-        d = ops.density(c.tree, h=dev_t(h_gpu.astype(np.float32)), active=a_t, solve_h=False)
-    # the oracle at the same (FP32) h: counts exact, sums within tolerance
+    # the sums at a given (synthetic, FP32) h on both sides: counts exact,
+    # sums within tolerance
+    h_gpu = inputs.model_smoothing(c.w).astype(np.float32).astype(np.float64)
+    d = ops.density(c.tree, h=dev_t(h_gpu.astype(np.float32)), active=a_t, solve_h=False)
     at = oracle.density(c.gt, c.p, active=act_gas, h=h_gpu, solve_h=False)
     np.testing.assert_array_equal(host(d["nngb"])[act_gas], at["nngb"][act_gas])
     r = host(d["rho"])[act_gas]

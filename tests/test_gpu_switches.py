@@ -10,7 +10,9 @@ acceleration, S_du for du/dt); pair counts exact; the per-particle switch
 within 2e-6 relative (FP32 expf and sqrtf of the same FP32 inputs the
 oracle reads). With one strength, unit factors and no conduction the
 switches' hydro force is g3_hydro_force (the same pair arithmetic, to
-1e-6 of S). Active subsets write only their rows.
+1e-6 of S). Active subsets write only their rows. Both sides read the same
+inputs: h, rho and Omega from the oracle's density solve (rounded to FP32),
+and for the switch step the oracle's velocity divergence and curl.
 """
 import numpy as np
 import pytest
@@ -45,11 +47,13 @@ def case():
     rng = np.random.default_rng(3)
     u32 = rng.uniform(0.5, 2.0, w.n).astype(np.float32)
     tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(w.type), tuple(w.box), w.params)
-    d = ops.density(tree)
-    torch.cuda.synchronize()
     gas = np.nonzero(w.type == 0)[0]
     gt = oracle.Tree(pos32.astype(np.float64), m32.astype(np.float64), w.box, type=w.type,
                      gas_only=True)
+    od = oracle.density(gt, w.params, active=gas)
+    g = w.type == 0
+    f32 = {k: np.where(g, od[k], 1.0).astype(np.float32) for k in ("h", "rho", "omega")}
+    d = {k: dev_t(v) for k, v in f32.items()}
     return dict(ctx=ctx, w=w, tree=tree, d=d, vel=vel32, u=u32, gas=gas, gt=gt)
 
 
@@ -84,18 +88,21 @@ def test_viscosity_switch_matches_the_oracle(case):
     from paper_2003_10850_amd import ops
     c = case
     sw = inputs.SwitchParams()
-    g = ops.velocity_gradients(c["tree"], dev_t(c["vel"]), c["d"]["h"], c["d"]["rho"],
-                               c["d"]["omega"])
     n = c["w"].n
     alpha0 = np.random.default_rng(6).uniform(sw.alpha_min, sw.alpha_max, n).astype(np.float32)
     alpha = dev_t(alpha0)
     gas = c["gas"]
     act = dev_t(gas.astype(np.int32))
     dt = 2e-3
+    # the switch step of both sides from the oracle's divergence and curl
+    vg = oracle.velgrad(c["gt"], c["w"].params, c["vel"], host(c["d"]["h"]),
+                        host(c["d"]["rho"]), host(c["d"]["omega"]), active=gas)
+    div = vg["div"].astype(np.float32)
+    curl = vg["curl"].astype(np.float32)
     bf = ops.viscosity_switch(c["ctx"], sw, c["w"].params, dt, dev_t(c["u"]), c["d"]["h"],
-                              g["div"], g["curl"], alpha=alpha, active=act)
+                              dev_t(div), dev_t(curl), alpha=alpha, active=act)
     torch.cuda.synchronize()
-    div, curl, h = host(g["div"]), host(g["curl"]), host(c["d"]["h"])
+    h = host(c["d"]["h"])
     fr = oracle.balsara(div, curl, c["u"], h, c["w"].params.gamma, sw.balsara_eps)
     ar = oracle.alpha_step(alpha0, dt, div, fr, c["u"], h, c["w"].params.gamma, sw.alpha_min,
                            sw.alpha_max, sw.decay)
