@@ -2,7 +2,9 @@
 
 One step = the whole hot path over one synthetic snapshot: octree build (all
 particles and gas), SPH density with the smoothing-length solve from a cold
-start, SPH hydro force, Barnes-Hut gravity, every particle active. The
+start, SPH hydro force, Barnes-Hut gravity, every particle active. Gravity
+runs on a second stream, queued after the density and beside it and the
+hydro (--serial: after them on one stream). The
 workload is the paper-like clustered set: N = 2^21 particles (half gas, half
 collisionless) in 32 Plummer spheres on a 20 % uniform background, FP32,
 Wendland C6 with 295 target neighbours, theta = 0.5, eps = 1e-3.
@@ -406,14 +408,34 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
     B["omega"].copy_(om0)
     rho_in, om_in = rho0.clone(), om0.clone()
 
+    # gravity runs on a second stream beside density and hydro, queued after
+    # the density (in the graph: a fork at the step's start, a join at its
+    # end)
+    side = torch.cuda.Stream(dev)  # default priority
+
+    def fork():
+        e = torch.cuda.Event()
+        e.record(torch.cuda.current_stream(dev))
+        return e
+
+    def beside(e, fn):
+        side.wait_event(e)
+        with torch.cuda.stream(side):
+            fn()
+
+    def join():
+        torch.cuda.current_stream(dev).wait_stream(side)
+
     def step():
+        e = fork()
         B["h"].copy_(h0)  # last step's h is the first guess of the solve
         ops.density(tree, active=act, out={k: B[k] for k in
                                            ("h", "rho", "drho_dh", "omega", "nngb")})
+        beside(e, lambda: ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
+                                                             "nterms": B["nterms"]}))
         ops.hydro_force(tree, vel, u, B["h"], B["rho"], B["omega"], active=act,
                         out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
-        ops.gravity(tree, active=act, out={"acc": B["gacc"], "pot": B["pot"],
-                                           "nterms": B["nterms"]})
+        join()
 
     # the autotuner picks candidate tile depth and group split per kernel
     tt = time.perf_counter()
@@ -477,13 +499,16 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
     del base64
 
     def step64():
+        e = fork()
         H64.copy_(h64)
         ops.density(tree64, active=act, out={"h": H64, **{k: B[k] for k in
                                                          ("rho", "drho_dh", "omega", "nngb")}})
+        beside(e, lambda: ops.gravity(tree64, active=act, out={"acc": B["gacc"],
+                                                               "pot": B["pot"],
+                                                               "nterms": B["nterms"]}))
         ops.hydro_force(tree64, vel, u, H64, B["rho"], B["omega"], active=act,
                         out={k: B[k] for k in ("acc", "dudt", "vsig", "npairs")})
-        ops.gravity(tree64, active=act, out={"acc": B["gacc"], "pot": B["pot"],
-                                             "nterms": B["nterms"]})
+        join()
 
     for _ in range(max(warmup, 1)):
         step64()
@@ -568,7 +593,8 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
         "interactions_per_step": {"density": i_d, "hydro": i_h, "gravity": i_g},
         "h_nonconverged": nonconv,
         "step": "h solve + density, hydro force, gravity over every snapshot's active set: "
-                "one persistent launch per kernel, the step captured in a HIP graph",
+                "one persistent launch per kernel, gravity on a second stream beside the "
+                "other two, the step captured in a HIP graph",
     }
 
 
@@ -652,6 +678,10 @@ def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int =
               npairs=torch.zeros(n, dtype=torch.int32, device=dev))
     og = dict(acc=torch.zeros(n, 3, **f32), pot=torch.zeros(n, **f32),
               nterms=torch.zeros(n, dtype=torch.int32, device=dev))
+
+    # one stream: at this size gravity beside density and hydro lengthens
+    # the step (each kernel runs long enough that the other's cache and
+    # memory traffic costs more than the filled tails gain)
 
     def step():
         tree.build(pos, mass, typ)
@@ -763,6 +793,8 @@ def main() -> int:
                     help="skip the batched (forest of snapshots) measurement")
     ap.add_argument("--no-differentiation", action="store_true",
                     help="skip the loss forward + backward measurement")
+    ap.add_argument("--serial", action="store_true",
+                    help="plain step: gravity after hydro on the same stream")
     ap.add_argument("--autotune", action="store_true",
                     help="plain leg: run the autotuner first (its candidate runs then appear "
                          "in kernel traces of this command); default launch choices otherwise")
@@ -832,28 +864,55 @@ def main() -> int:
     outg = dict(acc=torch.zeros(n, 3, device=dev), pot=torch.zeros(n, device=dev),
                 nterms=torch.zeros(n, dtype=torch.int32, device=dev))
     stream = torch.cuda.current_stream(dev)
-    ev = {k: [] for k in ("build", "density", "hydro", "gravity")}
+    # gravity reads only the all-particle octree and has its own scratch, so
+    # it runs on a second stream beside density and hydro (--serial: after
+    # them on one stream, for the kernels' stand-alone durations)
+    side = stream if args.serial else torch.cuda.Stream(dev)  # default priority
+    ev = {k: [] for k in ("build", "density", "hydro", "gravity", "interactions")}
 
     def step(record: bool):
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        mk = lambda: torch.cuda.Event(enable_timing=True)
+        marks = [mk() for _ in range(5)] if record else None  # on `stream`
+        gm = [mk(), mk()] if record else None  # gravity's, on `side`
         if record:
             marks[0].record(stream)
         tree.build(pos, mass, typ)
         if record:
             marks[1].record(stream)
+
+        def gravity():
+            with torch.cuda.stream(side):
+                if record:
+                    gm[0].record(side)
+                ops.gravity(tree, out=outg)
+                if record:
+                    gm[1].record(side)
+
+        built = torch.cuda.Event()
+        built.record(stream)
         h.zero_()  # cold start of the h solve every step
         d = ops.density(tree, h=h, out=outd)
-        hh = d["h"]
+        if not args.serial:
+            # queued after the density, so that its waves fill the GPU
+            # first and gravity's fill in as the density's tail drains
+            side.wait_event(built)
+            gravity()
         if record:
             marks[2].record(stream)
-        ops.hydro_force(tree, vel, u, hh, outd["rho"], outd["omega"], out=outh)
+        ops.hydro_force(tree, vel, u, d["h"], outd["rho"], outd["omega"], out=outh)
         if record:
             marks[3].record(stream)
-        ops.gravity(tree, out=outg)
+        if args.serial:
+            gravity()
+        else:
+            stream.wait_stream(side)
         if record:
             marks[4].record(stream)
-            for k, (a, b) in zip(ev, zip(marks[:-1], marks[1:])):
-                ev[k].append((a, b))
+            ev["build"].append((marks[0], marks[1]))
+            ev["density"].append((marks[1], marks[2]))
+            ev["hydro"].append((marks[2], marks[3]))
+            ev["gravity"].append((gm[0], gm[1]))
+            ev["interactions"].append((marks[1], marks[4]))
         return d
 
     print(f"bench: {w.name} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
@@ -882,7 +941,9 @@ def main() -> int:
                                    gacc=outg["acc"], nterms=outg["nterms"]))
     plain_out.update(_check_calls(tree, vel, u, T(inputs.model_smoothing(w).astype(np.float32)),
                                   T(inputs.model_gas_density(w).astype(np.float32))))
-    ms_interactions = times["density"] + times["hydro"] + times["gravity"]
+    # the three interaction calls' wall time (with gravity beside the SPH
+    # calls, less than the sum of their durations)
+    ms_interactions = times["interactions"]
     print(f"bench: {args.steps} steps, {ms:.3f} ms/step; per op ms {times}; "
           f"interactions dens {i_d} hydro {i_h} grav {i_g}; nonconv {nonconv}",
           file=sys.stderr, flush=True)
@@ -899,7 +960,10 @@ def main() -> int:
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "per_op": {k: {"ms": times[k], "tflops": flops[k] / (times[k] * 1e-3) / 1e12
-                               if k in flops else None} for k in times}}
+                               if k in flops else None} for k in times},
+                # with gravity beside density and hydro the kernels share the
+                # CUs: each duration spans the time it shared
+                "concurrent": not args.serial}
     line = {
         "metric": "particle interactions/sec (density+hydro+gravity), batched-FP32 vs plain at stated err",
         "value": inter / (ms * 1e-3),
@@ -920,6 +984,9 @@ def main() -> int:
                                                      "gravity": i_g},
                    "h_nonconverged": nonconv,
                    "h_passes_per_wave": passes / max(waves, 1), "path": "plain",
+                   "schedule": ("build; density, hydro, gravity on one stream" if args.serial
+                                else "build; density then hydro on one stream, gravity "
+                                     "queued after the density on a second"),
                    "launch_choices": tuned, "autotune_s": tune_s},
         # the same interactions over the three interaction calls alone (the
         # octree builds excluded: HIP-event times of the timed steps)

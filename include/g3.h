@@ -33,6 +33,13 @@
  *    before returning, and a tree whose build failed is unusable (G3_ESTATE)
  *    until a later build of it succeeds. Outputs are then untouched.
  *  - One g3_ctx per host thread. A g3_tree belongs to the ctx that built it.
+ *  - Streams: g3_gravity and g3_gravity_backward take their work tables from
+ *    scratch of their own, so one of them may run on one stream while the
+ *    SPH calls (density, hydro, conduction, switches and their backward
+ *    twins) of the same ctx and tree run on another (gravity reads only the
+ *    all-particle octree, the SPH calls only the gas one). Two calls of the
+ *    same group must not overlap; a build or refit of the tree must not
+ *    overlap any call that reads it.
  *  - Graph capture: g3_density, g3_hydro_force, g3_gravity and the
  *    _backward calls neither wait on the host nor use memset nodes; they
  *    allocate ctx scratch only when a call needs more than an earlier one.
@@ -103,8 +110,9 @@ const char *g3_last_error(const g3_ctx *ctx);
  * density are those of the last pass), walk passes summed over wavefronts,
  * wavefronts, 0. This is where g3_density, which never waits on the host,
  * reports non-convergence: the call returns G3_ENOCONV (stats still filled)
- * when the first counter is above zero, else G3_OK. SYNCS the ctx's last
- * stream. */
+ * when the first counter is above zero, else G3_OK. SYNCS the stream of
+ * the ctx's last call other than g3_gravity / g3_gravity_backward (those
+ * two count nothing here). */
 int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
 /* Fault injection, for tests of the error paths:
  *   G3_INJECT_ALLOC     value >= 0: the next `value` device allocations the

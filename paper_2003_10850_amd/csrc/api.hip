@@ -41,7 +41,7 @@ hipError_t dev_malloc(g3_ctx *c, void **p, size_t bytes) {
 }
 
 void *scratch(g3_ctx *c, int slot, size_t bytes) {
-  g3_ctx::Buf &b = c->scratch[slot];
+  g3_ctx::Buf &b = c->scratch[slot + c->bank * g3_ctx::kBankSlots];
   if (b.p && bytes <= b.bytes) return b.p;
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
@@ -972,7 +972,8 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   st = check_pending(c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  c->last_stream = s;
+  // last_stream stays with the SPH calls: only they count into c->counters
+  const BankGuard bank(c, 1);
   const Octree &o = t->all;
   const Tuning tu = tuning_for(c, kTuneGravity, active ? std::min<int64_t>(n_act, o.n) : o.n);
   Work wk;
@@ -1699,7 +1700,8 @@ int g3_gravity_backward(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_
   st = check_pending(c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  c->last_stream = s;
+  // last_stream stays with the SPH calls: only they count into c->counters
+  const BankGuard bank(c, 1);
   const Octree &o = t->all;
   if (o.n == 0) return G3_OK;
   float4 *gsrc = (float4 *)scratch(c, kAdjSrc, o.n * sizeof(float4));

@@ -120,7 +120,12 @@ struct g3_ctx {
     void *p = nullptr;
     size_t bytes = 0;
   };
-  Buf scratch[32];
+  // two banks of scratch slots: bank 1 serves the gravity calls, bank 0
+  // every other call, so that a gravity call may run on one stream while
+  // the SPH calls of the same ctx run on another
+  static constexpr int kBankSlots = 32;
+  Buf scratch[2 * kBankSlots];
+  int bank = 0;  // the bank of the call in progress (host side)
   // autotuned launch choices: (kind, floor(log2(targets))) -> choice
   std::map<std::pair<int, int>, g3::Tuning> tuning;
   unsigned long long *counters = nullptr;  // device [8]: [0] non-converged h
@@ -142,8 +147,17 @@ enum Slot {
   kGasFlags, kGasSlot, kGasScan, kIntAccH, kIntVp, kIntUp, kCondCh, kHydroExt,
   kAdjSrcFx, kAdjNodeFx, kNumSlots
 };
-static_assert(kNumSlots <= (int)(sizeof(g3_ctx::scratch) / sizeof(g3_ctx::Buf)),
-              "more scratch slots than the ctx holds");
+static_assert(kNumSlots <= g3_ctx::kBankSlots, "more scratch slots than a bank holds");
+
+// Selects the gravity calls' scratch bank for the lifetime of the guard.
+struct BankGuard {
+  g3_ctx *c;
+  int prev;
+  BankGuard(g3_ctx *ctx, int bank) : c(ctx), prev(ctx->bank) { c->bank = bank; }
+  ~BankGuard() { c->bank = prev; }
+  BankGuard(const BankGuard &) = delete;
+  BankGuard &operator=(const BankGuard &) = delete;
+};
 
 void *scratch(g3_ctx *c, int slot, size_t bytes);  // nullptr on failure
 

@@ -1,0 +1,94 @@
+"""Gravity on a second stream beside the SPH calls of the same ctx and tree.
+
+g3_gravity and g3_gravity_backward take their work tables from a scratch
+bank of their own and read only the all-particle octree, so they may run on
+one stream while density and hydro run on another. Every output must then
+carry the same bits as when the calls run one after another: each target's
+sums are formed by one wavefront in a fixed order, and the gravity adjoint's
+scattered sums are fixed-point integer additions.
+"""
+import numpy as np
+import pytest
+
+from paper_2003_10850_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2003_10850_amd import ops
+    return ops.Context(torch.device("cuda", 0))
+
+
+def dev_t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().numpy().copy()
+
+
+def one_step(tree, vel, u, pos, mass, typ, active, beside, side, density_first=False):
+    """Build, density + hydro of every gas particle on the current stream,
+    gravity of `active` (forward and adjoint) either after them on the same
+    stream or on `side` beside them, queued before or after the density."""
+    from paper_2003_10850_amd import ops
+    main = torch.cuda.current_stream()
+    tree.build(pos, mass, typ)
+    rng = np.random.default_rng(5)
+    gA = dev_t(rng.normal(size=(tree.n, 3)).astype(np.float32))
+
+    def gravity_part():
+        g = ops.gravity(tree, active=active)
+        p = pos.detach().clone().requires_grad_(True)
+        m = mass.detach().clone().requires_grad_(True)
+        acc, pot = ops.gravity_ad(tree, p, m, active=active)
+        ((acc * gA).sum() + pot.sum()).backward()
+        return {"gacc": g["acc"], "pot": g["pot"], "nterms": g["nterms"], "gpos": p.grad,
+                "gmass": m.grad}
+
+    out = {}
+    built = torch.cuda.Event()
+    built.record(main)
+
+    def on_side():
+        side.wait_event(built)
+        with torch.cuda.stream(side):
+            out.update(gravity_part())
+
+    if beside and not density_first:
+        on_side()
+    d = ops.density(tree)
+    if beside and density_first:
+        on_side()
+    hy = ops.hydro_force(tree, vel, u, d["h"], d["rho"], d["omega"])
+    if not beside:
+        out.update(gravity_part())
+    main.wait_stream(side)
+    torch.cuda.synchronize()
+    out.update(h=d["h"], rho=d["rho"], omega=d["omega"], nngb=d["nngb"], acc=hy["acc"],
+               dudt=hy["dudt"], npairs=hy["npairs"])
+    return {k: host(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("frac", [None, 0.3])
+def test_gravity_beside_sph_gives_the_same_bits(ctx, frac):
+    from paper_2003_10850_amd import ops
+    w = inputs.plummer(n=200000, n_spheres=8, seed=91)
+    pos32, vel32, m32, u32 = w.as_f32()
+    print(f"concurrency case plummer n={w.n} active fraction {frac}", flush=True)
+    pos, vel, mass, u, typ = dev_t(pos32), dev_t(vel32), dev_t(m32), dev_t(u32), dev_t(w.type)
+    tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
+    active = None if frac is None else dev_t(inputs.active_subset(w.n, frac, seed=3))
+    side = torch.cuda.Stream()  # default priority
+    ref = one_step(tree, vel, u, pos, mass, typ, active, beside=False, side=side)
+    for rep in range(4):
+        got = one_step(tree, vel, u, pos, mass, typ, active, beside=True, side=side,
+                       density_first=rep % 2 == 1)
+        for k, v in ref.items():
+            np.testing.assert_array_equal(got[k], v, err_msg=f"{k}, repeat {rep}")
+    assert np.abs(ref["gacc"]).max() > 0 and np.abs(ref["acc"]).max() > 0
+    assert ref["npairs"].sum() > 0 and ref["nterms"].sum() > 0

@@ -21,12 +21,16 @@ def dev_t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def test_captured_step_replays_match_eager():
+@pytest.mark.parametrize("fork", [False, True])
+def test_captured_step_replays_match_eager(fork):
+    """fork: gravity on a second stream, queued after the density and
+    joined at the step's end (in the graph: a fork and a join)."""
     from paper_2003_10850_amd import ops
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     ctx = ops.Context(torch.device("cuda", 0))
     b = inputs.batch(n_snap=6, n_min=1e3, n_max=2e4, seed=5, n_ngb=64.0)
-    print(f"graph step: forest n={b.n} snapshots={b.n_snap} active={b.active.size}", flush=True)
+    print(f"graph step: forest n={b.n} snapshots={b.n_snap} active={b.active.size} "
+          f"fork={fork}", flush=True)
     tree = ops.Tree(ctx, dev_t(b.pos.astype(np.float32)), dev_t(b.mass.astype(np.float32)),
                     dev_t(b.type), [tuple(x) for x in b.boxes], b.params, snap_off=b.snap_off)
     act = dev_t(b.active)
@@ -47,18 +51,33 @@ def test_captured_step_replays_match_eager():
     om_all = base["omega"].clone()
     h_all = base["h"].clone()
 
+    side = torch.cuda.Stream()  # default priority
+
+    def gravity():
+        ops.gravity(tree, active=act, out={"acc": bufs["gacc"], "pot": bufs["pot"],
+                                           "nterms": bufs["nterms"]})
+
     def step():
+        main = torch.cuda.current_stream()
         for k in bufs:
             bufs[k].zero_()
+        start = torch.cuda.Event()
+        start.record(main)
         bufs["h"].copy_(h_all)
         ops.density(tree, active=act, out={k: bufs[k] for k in
                                            ("h", "rho", "drho_dh", "omega", "nngb")})
+        if fork:
+            side.wait_event(start)
+            with torch.cuda.stream(side):
+                gravity()
         rho = torch.where(bufs["rho"] > 0, bufs["rho"], rho_all)
         om = torch.where(bufs["omega"] > 0, bufs["omega"], om_all)
         ops.hydro_force(tree, vel, u, bufs["h"], rho, om, active=act,
                         out={k: bufs[k] for k in ("acc", "dudt", "vsig", "npairs")})
-        ops.gravity(tree, active=act, out={"acc": bufs["gacc"], "pot": bufs["pot"],
-                                           "nterms": bufs["nterms"]})
+        if fork:
+            main.wait_stream(side)
+        else:
+            gravity()
 
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
