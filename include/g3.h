@@ -114,6 +114,23 @@ const char *g3_last_error(const g3_ctx *ctx);
  * the ctx's last call other than g3_gravity / g3_gravity_backward (those
  * two count nothing here). */
 int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
+/* Kernel timing, for benchmarks and profilers. With capacity > 0, the next
+ * `capacity` calls of `kind` (G3_TUNE_DENSITY: g3_density, G3_TUNE_HYDRO:
+ * g3_hydro_force, G3_TUNE_GRAVITY: g3_gravity) after this call, or after
+ * the last g3_ctx_kernel_times of that kind, each record a pair of HIP
+ * events on their stream just before and just after their interaction
+ * kernel (k_density, k_hydro, k_gravity: not the group-table and prep
+ * kernels before it), so that the pair spans that kernel alone also when
+ * other streams keep the device busy. Later calls and calls made under
+ * stream capture record nothing. capacity 0 turns timing off; at most
+ * G3_TIMING_MAX. Creates the events (host call, no device wait). */
+enum { G3_TIMING_MAX = 4096 };
+int g3_ctx_kernel_timing(g3_ctx *ctx, int32_t kind, int32_t capacity);
+/* The durations (ms, host [capacity]) of the kernels recorded since timing
+ * of `kind` was enabled or last read, in call order; *count receives their
+ * number (0..capacity). Waits for each stop event (SYNCS on them), then
+ * starts a new round of up to `capacity` recordings. */
+int g3_ctx_kernel_times(g3_ctx *ctx, int32_t kind, float *ms, int32_t *count);
 /* Fault injection, for tests of the error paths:
  *   G3_INJECT_ALLOC     value >= 0: the next `value` device allocations the
  *                       ctx makes (trees and scratch) succeed and every
@@ -551,8 +568,9 @@ int g3_tuning_load(g3_ctx *ctx, const char *path);
  * particles receive what the active particles' sums owe them. FP32 trees
  * only (G3_EINVAL otherwise). Density and hydro adjoints are gathered per
  * particle in a fixed order (run-to-run identical); the gravity adjoint adds
- * the source side of each term with atomics, so its last bits may vary
- * between runs.
+ * the source side of each term across wavefronts, as fixed-point integers
+ * when eps > 0 (run-to-run identical) and as float atomics when eps = 0
+ * (last bits may vary between runs): see g3_gravity_backward.
  *
  * Density: L's upstream gradients g_rho, g_drho_dh, g_omega; rho and
  * drho_dh are the forward outputs at the active rows (they enter through

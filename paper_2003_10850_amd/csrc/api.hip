@@ -91,6 +91,36 @@ int check_pending(g3_ctx *c) {
   return G3_OK;
 }
 
+// Records the start event of a timed interaction kernel on construction
+// and its stop event at stop(); does nothing unless timing is on for the
+// kind, the ring has room and the stream is not being captured.
+struct KernelTimer {
+  g3_ctx::Timing *tm = nullptr;
+  hipStream_t s = nullptr;
+  int slot = -1;
+  KernelTimer(g3_ctx *c, int kind, hipStream_t stream) : s(stream) {
+    g3_ctx::Timing &t = c->timing[kind];
+    if (t.capacity == 0 || t.count >= t.capacity) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      (void)hipGetLastError();
+      return;
+    }
+    if (hipEventRecord(t.ev[2 * t.count], s) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    tm = &t;
+    slot = t.count;
+  }
+  void stop() {
+    if (!tm) return;
+    if (hipEventRecord(tm->ev[2 * slot + 1], s) == hipSuccess) tm->count = slot + 1;
+    else (void)hipGetLastError();
+    tm = nullptr;
+  }
+};
+
 bool params_ok(const g3_params *p) {
   return p && p->leaf_size >= 1 && p->leaf_size <= 64 && p->flags == 0 &&
          std::isfinite(p->theta) && p->theta >= 0.0 && std::isfinite(p->eps) &&
@@ -500,6 +530,8 @@ void g3_ctx_destroy(g3_ctx *c) {
     if (b.p) (void)hipFree(b.p);
   if (c->counters) (void)hipFree(c->counters);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto &tm : c->timing)
+    for (hipEvent_t e : tm.ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -522,6 +554,44 @@ int g3_ctx_stats(g3_ctx *c, int64_t *stats, int32_t reset) {
   if (stats[0] > 0)
     return fail(c, G3_ENOCONV, std::to_string(stats[0]) +
                                    " particles' h solves did not converge since the last reset");
+  return G3_OK;
+}
+
+int g3_ctx_kernel_timing(g3_ctx *c, int32_t kind, int32_t capacity) {
+  if (!c) return G3_EINVAL;
+  if (kind < 0 || kind >= kTuneKinds || capacity < 0 || capacity > G3_TIMING_MAX)
+    return fail(c, G3_EINVAL, "g3_ctx_kernel_timing: bad kind or capacity");
+  DeviceGuard g(c->device);
+  g3_ctx::Timing &t = c->timing[kind];
+  t.count = 0;
+  t.capacity = 0;
+  while ((int)t.ev.size() < 2 * capacity) {
+    hipEvent_t e = nullptr;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(c, r, "g3_ctx_kernel_timing");
+    t.ev.push_back(e);
+  }
+  t.capacity = capacity;
+  c->err.clear();
+  return G3_OK;
+}
+
+int g3_ctx_kernel_times(g3_ctx *c, int32_t kind, float *ms, int32_t *count) {
+  if (!c) return G3_EINVAL;
+  if (kind < 0 || kind >= kTuneKinds || !count)
+    return fail(c, G3_EINVAL, "g3_ctx_kernel_times: bad kind or null count");
+  DeviceGuard g(c->device);
+  g3_ctx::Timing &t = c->timing[kind];
+  const int n = t.count;
+  if (n > 0 && !ms) return fail(c, G3_EINVAL, "g3_ctx_kernel_times: null ms");
+  for (int k = 0; k < n; ++k) {
+    hipError_t r = hipEventSynchronize(t.ev[2 * k + 1]);
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms[k], t.ev[2 * k], t.ev[2 * k + 1]);
+    if (r != hipSuccess) return hip_fail(c, r, "g3_ctx_kernel_times");
+  }
+  *count = n;
+  t.count = 0;
+  c->err.clear();
   return G3_OK;
 }
 
@@ -921,8 +991,10 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   Work wk;
   st = prepare_work(c, t, o, t->iperm_gas, n_act, active, &wk, s, tu.split);
   if (st) return st;
+  KernelTimer timer(c, kTuneDensity, s);
   hipError_t e = launch_density(o, wk.gs, wk.max_groups, sp, solve_h ? 1 : 0, h, rho, drho_dh,
                                 omega, nngb, c->counters, s);
+  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
   c->err.clear();
   return G3_OK;
@@ -955,7 +1027,9 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   hipError_t e = launch_hydro_prep(o, vel, u, h, rho, omega, sp.gamma, t->f64, s);
   if (e == hipSuccess) e = refit_hmax(o, s);
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
+  KernelTimer timer(c, kTuneHydro, s);
   e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s);
+  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force");
   c->err.clear();
   return G3_OK;
@@ -979,7 +1053,9 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   Work wk;
   st = prepare_work(c, t, o, t->iperm_all, n_act, active, &wk, s, tu.split);
   if (st) return st;
+  KernelTimer timer(c, kTuneGravity, s);
   hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
+  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
   c->err.clear();
   return G3_OK;

@@ -135,6 +135,16 @@ struct g3_ctx {
   // later one fails (-1: off), and the h solve's pass limit
   int64_t alloc_budget = -1;
   int max_iter = 64;
+  // opt-in kernel timing (g3_ctx_kernel_timing), per kind (density, hydro,
+  // gravity): event pairs recorded on the call's stream around its
+  // interaction kernel, for the first `capacity` calls after enabling or
+  // after the last read
+  struct Timing {
+    std::vector<hipEvent_t> ev;  // start, stop of pair k at 2k, 2k + 1
+    int capacity = 0;
+    int count = 0;
+  };
+  Timing timing[3];  // indexed by g3::TuneKind
 };
 
 namespace g3 {

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "G3_OK", -1: "G3_EINVAL", -2: "G3_ENOMEM", -3: "G3_EHIP",
                 -4: "G3_EOVERFLOW", -5: "G3_ENOCONV", -6: "G3_ESTATE"}
 
 # every symbol include/g3.h declares
-EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats", "g3_ctx_inject",
+EXPORTS = ("g3_ctx_create", "g3_ctx_destroy", "g3_last_error", "g3_ctx_stats",
+           "g3_ctx_kernel_timing", "g3_ctx_kernel_times", "g3_ctx_inject",
            "g3_build_tree", "g3_build_forest", "g3_refit_tree", "g3_tree_destroy", "g3_tree_info",
            "g3_tree_export",
            "g3_walk", "g3_density", "g3_hydro_force", "g3_gravity", "g3_gravity_noalloc",
@@ -90,6 +91,8 @@ def lib():
             "g3_ctx_destroy": ([P], None),
             "g3_last_error": ([P], ctypes.c_char_p),
             "g3_ctx_stats": ([P, P, i32], ctypes.c_int),
+            "g3_ctx_kernel_timing": ([P, i32, i32], ctypes.c_int),
+            "g3_ctx_kernel_times": ([P, i32, P, P], ctypes.c_int),
             "g3_ctx_inject": ([P, i32, i64], ctypes.c_int),
             "g3_build_tree": ([P, i64, i32, P, P, P, P, P, P, P], ctypes.c_int),
             "g3_build_forest": ([P, i32, P, i32, P, P, P, P, P, P, P], ctypes.c_int),
@@ -345,6 +348,24 @@ def g3_system_step(ctx, tree_ref, n, pos_t, state, box, params, iparams, tick_ac
 
 G3_TUNE_DENSITY, G3_TUNE_HYDRO, G3_TUNE_GRAVITY = 0, 1, 2
 G3_SPLIT_AUTO = -2
+G3_TIMING_MAX = 4096
+_timing_cap = {}
+
+
+def g3_ctx_kernel_timing(ctx, kind, capacity):
+    st = lib().g3_ctx_kernel_timing(ctx, int(kind), int(capacity))
+    _check(ctx, st, "g3_ctx_kernel_timing")
+    _timing_cap[(ctx, int(kind))] = int(capacity)
+
+
+def g3_ctx_kernel_times(ctx, kind):
+    """Kernel durations (ms) recorded since timing was enabled or last read."""
+    cap = max(_timing_cap.get((ctx, int(kind)), 0), 1)
+    ms = (ctypes.c_float * cap)()
+    n = ctypes.c_int32(0)
+    st = lib().g3_ctx_kernel_times(ctx, int(kind), ms, ctypes.byref(n))
+    _check(ctx, st, "g3_ctx_kernel_times")
+    return [float(ms[k]) for k in range(n.value)]
 
 
 def g3_autotune(ctx, tree, n_act, active, params, h, vel, u, rho, omega, stream):

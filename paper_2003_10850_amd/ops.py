@@ -47,6 +47,16 @@ class Context:
     def nonconverged(self, reset: bool = False) -> int:
         return self.stats(reset)[0]
 
+    def kernel_timing(self, kind: int, capacity: int) -> None:
+        """Record the next `capacity` interaction kernels of `kind` (a
+        G3_TUNE_* value) with HIP events on their streams; 0 turns it off."""
+        g3.g3_ctx_kernel_timing(self.handle, kind, capacity)
+
+    def kernel_times(self, kind: int) -> list:
+        """Durations (ms) of the kernels recorded since enabling or the last
+        read, in call order (waits for them)."""
+        return g3.g3_ctx_kernel_times(self.handle, kind)
+
     def tuning(self, kind: int, n_targets: int):
         """(walk_leaf, split, streams) the calls of `kind` over n_targets use."""
         return g3.g3_tuning_get(self.handle, kind, n_targets)

@@ -92,3 +92,63 @@ def test_gravity_beside_sph_gives_the_same_bits(ctx, frac):
             np.testing.assert_array_equal(got[k], v, err_msg=f"{k}, repeat {rep}")
     assert np.abs(ref["gacc"]).max() > 0 and np.abs(ref["acc"]).max() > 0
     assert ref["npairs"].sum() > 0 and ref["nterms"].sum() > 0
+
+
+def test_kernel_timing_records_each_interaction_kernel(ctx):
+    """g3_ctx_kernel_timing: one event pair per call of the enabled kind, up
+    to its capacity; a read starts a new round; nothing under capture; each
+    pair spans the kernel alone, within the span of its whole call."""
+    from paper_2003_10850_amd import g3, ops
+    w = inputs.plummer(n=60000, n_spheres=4, seed=12)
+    pos32, _, m32, _ = w.as_f32()
+    tree = ops.Tree(ctx, dev_t(pos32), dev_t(m32), dev_t(w.type), tuple(w.box), w.params)
+    D, H, G = g3.G3_TUNE_DENSITY, g3.G3_TUNE_HYDRO, g3.G3_TUNE_GRAVITY
+    ops.density(tree)
+    ops.gravity(tree)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(D, 2)
+    ctx.kernel_timing(G, 3)
+    main = torch.cuda.current_stream()
+    spans = []
+    for _ in range(3):
+        ops.density(tree)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(main)
+        ops.gravity(tree)
+        b.record(main)
+        spans.append((a, b))
+    dt, gt = ctx.kernel_times(D), ctx.kernel_times(G)
+    assert len(dt) == 2 and len(gt) == 3
+    assert all(t > 0 for t in dt + gt)
+    for t, (a, b) in zip(gt, spans):
+        assert t <= a.elapsed_time(b) + 0.05
+    assert ctx.kernel_times(H) == []  # never enabled
+    ops.density(tree)
+    assert len(ctx.kernel_times(D)) == 1  # a new round after the read
+    # under capture nothing is recorded
+    n = tree.n
+    out = dict(h=torch.zeros(n, device="cuda:0"), rho=torch.zeros(n, device="cuda:0"),
+               drho_dh=torch.zeros(n, device="cuda:0"), omega=torch.zeros(n, device="cuda:0"),
+               nngb=torch.zeros(n, dtype=torch.int32, device="cuda:0"))
+    s = torch.cuda.Stream()
+    s.wait_stream(main)
+    with torch.cuda.stream(s):
+        ops.density(tree, out=out)
+    main.wait_stream(s)
+    torch.cuda.synchronize()
+    assert len(ctx.kernel_times(D)) == 1
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ops.density(tree, out=out)
+    graph.replay()
+    torch.cuda.synchronize()
+    assert ctx.kernel_times(D) == []
+    with pytest.raises(Exception):
+        ctx.kernel_timing(3, 1)
+    with pytest.raises(Exception):
+        ctx.kernel_timing(D, g3.G3_TIMING_MAX + 1)
+    ctx.kernel_timing(D, 0)
+    ctx.kernel_timing(G, 0)
+    ops.density(tree)
+    assert ctx.kernel_times(D) == []  # off
+    ctx.nonconverged(reset=True)
