@@ -34,12 +34,13 @@
  *    until a later build of it succeeds. Outputs are then untouched.
  *  - One g3_ctx per host thread. A g3_tree belongs to the ctx that built it.
  *  - Streams: g3_gravity and g3_gravity_backward take their work tables from
- *    scratch of their own, so one of them may run on one stream while the
- *    SPH calls (density, hydro, conduction, switches and their backward
- *    twins) of the same ctx and tree run on another (gravity reads only the
- *    all-particle octree, the SPH calls only the gas one). Two calls of the
- *    same group must not overlap; a build or refit of the tree must not
- *    overlap any call that reads it.
+ *    scratch of their own (g3_gravity_noalloc from its per-device region),
+ *    so one of them may run on one stream while the SPH calls (density,
+ *    hydro, conduction, switches and their backward twins) of the same ctx
+ *    and tree run on another (gravity reads only the all-particle octree,
+ *    the SPH calls only the gas one). Two calls of the same group must not
+ *    overlap; a build or refit of the tree must not overlap any call that
+ *    reads it.
  *  - Graph capture: g3_density, g3_hydro_force, g3_gravity and the
  *    _backward calls neither wait on the host nor use memset nodes; they
  *    allocate ctx scratch only when a call needs more than an earlier one.

@@ -1232,7 +1232,7 @@ int g3_gravity_noalloc(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t
   arena.cap = kNoAllocBytes;
   if (!arena.base) return fail(c, G3_ESTATE, "g3_gravity_noalloc: no region on this device");
   hipStream_t s = (hipStream_t)stream;
-  c->last_stream = s;
+  // last_stream stays with the SPH calls: only they count into c->counters
   const Octree &o = t->all;
   const Tuning tu = tuning_for(c, kTuneGravity, active ? std::min<int64_t>(n_act, o.n) : o.n);
   Work wk;

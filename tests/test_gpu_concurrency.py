@@ -1,8 +1,9 @@
 """Gravity on a second stream beside the SPH calls of the same ctx and tree.
 
 g3_gravity and g3_gravity_backward take their work tables from a scratch
-bank of their own and read only the all-particle octree, so they may run on
-one stream while density and hydro run on another. Every output must then
+bank of their own (g3_gravity_noalloc from its per-device region) and read
+only the all-particle octree, so they may run on one stream while density
+and hydro run on another. Every output must then
 carry the same bits as when the calls run one after another: each target's
 sums are formed by one wavefront in a fixed order, and the gravity adjoint's
 scattered sums are fixed-point integer additions.
@@ -31,10 +32,25 @@ def host(t):
     return t.detach().cpu().numpy().copy()
 
 
+def noalloc_gravity(tree, active):
+    """g3_gravity_noalloc through the C ABI on the current stream."""
+    from paper_2003_10850_amd import g3
+    n = tree.n
+    acc = torch.zeros(n, 3, device="cuda:0")
+    pot = torch.zeros(n, device="cuda:0")
+    nt = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    na, ap = (n, None) if active is None else (int(active.shape[0]), active.data_ptr())
+    g3.g3_gravity_noalloc(tree.ctx.handle, tree.handle, na, ap, g3.g3_params.of(tree.params),
+                          acc.data_ptr(), pot.data_ptr(), nt.data_ptr(),
+                          torch.cuda.current_stream().cuda_stream)
+    return acc, pot, nt
+
+
 def one_step(tree, vel, u, pos, mass, typ, active, beside, side, density_first=False):
     """Build, density + hydro of every gas particle on the current stream,
-    gravity of `active` (forward and adjoint) either after them on the same
-    stream or on `side` beside them, queued before or after the density."""
+    gravity of `active` (forward, the allocation-free forward and, on FP32
+    trees, the adjoint) either after them on the same stream or on `side`
+    beside them, queued before or after the density."""
     from paper_2003_10850_amd import ops
     main = torch.cuda.current_stream()
     tree.build(pos, mass, typ)
@@ -43,12 +59,16 @@ def one_step(tree, vel, u, pos, mass, typ, active, beside, side, density_first=F
 
     def gravity_part():
         g = ops.gravity(tree, active=active)
-        p = pos.detach().clone().requires_grad_(True)
-        m = mass.detach().clone().requires_grad_(True)
-        acc, pot = ops.gravity_ad(tree, p, m, active=active)
-        ((acc * gA).sum() + pot.sum()).backward()
-        return {"gacc": g["acc"], "pot": g["pot"], "nterms": g["nterms"], "gpos": p.grad,
-                "gmass": m.grad}
+        na_acc, na_pot, na_nt = noalloc_gravity(tree, active)
+        out = {"gacc": g["acc"], "pot": g["pot"], "nterms": g["nterms"], "na_acc": na_acc,
+               "na_pot": na_pot, "na_nterms": na_nt}
+        if pos.dtype == torch.float32:
+            p = pos.detach().clone().requires_grad_(True)
+            m = mass.detach().clone().requires_grad_(True)
+            acc, pot = ops.gravity_ad(tree, p, m, active=active)
+            ((acc * gA).sum() + pot.sum()).backward()
+            out.update(gpos=p.grad, gmass=m.grad)
+        return out
 
     out = {}
     built = torch.cuda.Event()
@@ -74,13 +94,15 @@ def one_step(tree, vel, u, pos, mass, typ, active, beside, side, density_first=F
     return {k: host(v) for k, v in out.items()}
 
 
-@pytest.mark.parametrize("frac", [None, 0.3])
-def test_gravity_beside_sph_gives_the_same_bits(ctx, frac):
+@pytest.mark.parametrize("frac,f64", [(None, False), (0.3, False), (0.3, True)])
+def test_gravity_beside_sph_gives_the_same_bits(ctx, frac, f64):
     from paper_2003_10850_amd import ops
     w = inputs.plummer(n=200000, n_spheres=8, seed=91)
     pos32, vel32, m32, u32 = w.as_f32()
-    print(f"concurrency case plummer n={w.n} active fraction {frac}", flush=True)
-    pos, vel, mass, u, typ = dev_t(pos32), dev_t(vel32), dev_t(m32), dev_t(u32), dev_t(w.type)
+    print(f"concurrency case plummer n={w.n} active fraction {frac} fp64 positions {f64}",
+          flush=True)
+    pos = dev_t(w.pos) if f64 else dev_t(pos32)
+    vel, mass, u, typ = dev_t(vel32), dev_t(m32), dev_t(u32), dev_t(w.type)
     tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
     active = None if frac is None else dev_t(inputs.active_subset(w.n, frac, seed=3))
     side = torch.cuda.Stream()  # default priority
@@ -92,6 +114,9 @@ def test_gravity_beside_sph_gives_the_same_bits(ctx, frac):
             np.testing.assert_array_equal(got[k], v, err_msg=f"{k}, repeat {rep}")
     assert np.abs(ref["gacc"]).max() > 0 and np.abs(ref["acc"]).max() > 0
     assert ref["npairs"].sum() > 0 and ref["nterms"].sum() > 0
+    # the allocation-free call gives the ordinary call's bits
+    for k, kk in (("gacc", "na_acc"), ("pot", "na_pot"), ("nterms", "na_nterms")):
+        np.testing.assert_array_equal(ref[kk], ref[k], err_msg=kk)
 
 
 def test_kernel_timing_records_each_interaction_kernel(ctx):
