@@ -48,7 +48,7 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
 // the opening test on the FP32 rounding of the node's FP64 offset from the
 // target, and near the threshold, where that test could disagree with the
 // FP64 one, the FP64 test decides.
-template <bool kF64>
+template <bool kF64, bool kInside>
 __global__ __launch_bounds__(kBlock) void k_gravity(
     const GNode *__restrict__ nodes, const double4 *__restrict__ c64n,
     const float4 *__restrict__ xm, const double4 *__restrict__ x64,
@@ -130,9 +130,13 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
     wave_sync();
   };
 
-  int resume = valid ? grp.root : INT32_MAX;  // lanes idle while cur < resume
-  int cur = grp.root;
-  while (cur < grp.end) {
+  // the group's node range, wave-uniform (in scalar registers for the
+  // FP32 walk; the mixed-precision walk measured faster without)
+  const int groot = kF64 ? grp.root : __builtin_amdgcn_readfirstlane(grp.root);
+  const int gend = kF64 ? grp.end : __builtin_amdgcn_readfirstlane(grp.end);
+  int resume = valid ? groot : INT32_MAX;  // lanes idle while cur < resume
+  int cur = groot;
+  while (cur < gend) {
     const GNode nd = nodes[cur];
     const float l = __int_as_float(nd.meta.w);
     const bool act = cur >= resume;
@@ -145,22 +149,37 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       r2 = dist2_exact(sub_exact(nd.com_m.x, xi.x), sub_exact(nd.com_m.y, xi.y),
                        sub_exact(nd.com_m.z, xi.z));
     }
-    bool accept = act && open_accept(l, theta2, r2);
-    if constexpr (kF64) {
-      // the FP32 r2 of exact-to-2^-24 offsets is within about 2^-22 of the
-      // FP64 value (relative); inside 2^-19 of the threshold FP64 decides
-      const float lhs = l * l, rhs = theta2 * r2;
-      if (act && fabsf(lhs - rhs) <= rhs * 1.9073486e-6f)
-        accept = open_accept64(ldexp(side, -(root_exp - ilogbf(l))), theta64, cn, p64);
-    }
-    if (inside_test) {
-      const int level = root_exp - ilogbf(l);
-      const uint64_t nk = keys[nd.meta.y];
-      const bool inside = ((ki ^ nk) >> (3 * (kMaxLevel - level))) == 0ull;
-      accept = accept && !inside;
+    bool accept, open;
+    if constexpr (!kF64 && !kInside) {
+      // one compare per decision: an idle lane compares with NaN, for which
+      // both are false; otherwise the exact test fl(l l) < fl(theta2 r2)
+      float t;
+      {
+#pragma clang fp contract(off)
+        t = act ? theta2 * r2 : __builtin_nanf("");
+      }
+      const float lhs = sq_exact(l);
+      accept = lhs < t;
+      open = lhs >= t;
+    } else {
+      accept = act && open_accept(l, theta2, r2);
+      if constexpr (kF64) {
+        // the FP32 r2 of exact-to-2^-24 offsets is within about 2^-22 of the
+        // FP64 value (relative); inside 2^-19 of the threshold FP64 decides
+        const float lhs = l * l, rhs = theta2 * r2;
+        if (act && fabsf(lhs - rhs) <= rhs * 1.9073486e-6f)
+          accept = open_accept64(ldexp(side, -(root_exp - ilogbf(l))), theta64, cn, p64);
+      }
+      if (kInside || (kF64 && inside_test)) {
+        const int level = root_exp - ilogbf(l);
+        const uint64_t nk = keys[nd.meta.y];
+        const bool inside = ((ki ^ nk) >> (3 * (kMaxLevel - level))) == 0ull;
+        accept = accept && !inside;
+      }
+      open = act && !accept;
     }
     const uint64_t amask = __ballot(accept);
-    const uint64_t omask = __ballot(act && !accept);
+    const uint64_t omask = __ballot(open);
     if (accept) resume = nd.meta.x;
     if (amask) {
       if (tc == kTile) {
@@ -211,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity(
       // an opening lane whose own target is among these members clears its
       // bit in that member's entry (one lane per entry)
       const int rel = s - st;
-      if (act && !accept && rel >= 0 && rel < take) {
+      if (open && rel >= 0 && rel < take) {
         uint32_t *wd = (uint32_t *)&tile[tc + rel] + kMaskWord + (hiword ? 1 : 0);
         *wd &= ~(1u << bitpos);
       }
@@ -245,7 +264,9 @@ hipError_t launch_gravity(const Octree &all, const Groups &gs, int64_t max_group
                           const GravParams &gp, float *acc, float *pot, int32_t *nterms,
                           hipStream_t s) {
   if (max_groups <= 0 || all.nnodes == 0) return hipSuccess;
-  auto kern = gp.f64 ? k_gravity<true> : k_gravity<false>;
+  // FP32: the containment test is compiled in or out; FP64: a runtime flag
+  auto kern = gp.f64 ? k_gravity<true, false>
+                     : (gp.inside_test ? k_gravity<false, true> : k_gravity<false, false>);
   if (!all.gnodes) return hipErrorInvalidValue;
   kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
       all.gnodes, all.c64, all.xm, all.x64, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
