@@ -40,6 +40,14 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 # a short spin (GPU clock cycles, about 0.1 ms) on the gravity stream before
 # its call, so that the density beside it is dispatched first
 SIDE_SPIN_CYCLES = 200_000
+
+
+def side_spin(torch) -> None:
+    """The short spin on the current stream (torch's one-wave sleep kernel;
+    skipped where this torch build has none: the order is then a race)."""
+    sleep = getattr(torch.cuda, "_sleep", None)
+    if sleep is not None:
+        sleep(SIDE_SPIN_CYCLES)
 HBM_TBS = 8.0
 
 
@@ -424,7 +432,7 @@ def run_batched(dev, steps: int, warmup: int, n_snap: int = 64, seed: int = 2):
     def beside(e, fn):
         side.wait_event(e)
         with torch.cuda.stream(side):
-            torch.cuda._sleep(SIDE_SPIN_CYCLES)  # the density takes the CUs first
+            side_spin(torch)  # the density takes the CUs first
             fn()
 
     def join():
@@ -903,7 +911,7 @@ def main() -> int:
             # build's end, so the second one spins briefly first
             side.wait_event(built)
             with torch.cuda.stream(side):
-                torch.cuda._sleep(SIDE_SPIN_CYCLES)
+                side_spin(torch)
             gravity()
         if record:
             marks[2].record(stream)
