@@ -453,11 +453,11 @@ __device__ __forceinline__ bool open_accept(float l, float theta2, float r2) {
 // kFixed: the sums go to fixed-point counter pairs (gsrc_fx [n][4][2],
 // gnode_fx [nnodes][4][2], scale from mx), else to FP32 atomics (gsrc,
 // gnode).
-template <bool kFixed>
+template <bool kFixed, bool kInside>
 __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
-    const Node *__restrict__ nodes, const float4 *__restrict__ xm,
+    const GNode *__restrict__ nodes, const float4 *__restrict__ xm,
     const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm, const Groups gs,
-    float theta2, float eps2, float G, int inside_test, const float *__restrict__ g_acc,
+    float theta2, float eps2, float G, const float *__restrict__ g_acc,
     const float *__restrict__ g_pot, float4 *__restrict__ gsrc, float4 *__restrict__ gnode,
     unsigned long long *__restrict__ gsrc_fx, unsigned long long *__restrict__ gnode_fx,
     const unsigned *__restrict__ mx, int64_t n_all, int64_t n_act) {
@@ -544,21 +544,39 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
       neumaier_add(oz, coz, pz);
       wave_sync();
     };
-    int resume = valid ? grp.root : INT32_MAX;
-    int cur = grp.root;
-    while (cur < grp.end) {
-      const Node nd = nodes[cur];
+    // the walk of the forward kernel over the 32-byte node copies: the same
+    // decisions, one compare each without the containment test (an idle
+    // lane compares with NaN, for which both are false)
+    const int root_exp = ilogbf((float)gs.sbox[grp.snap].w);
+    const int groot = __builtin_amdgcn_readfirstlane(grp.root);
+    const int gend = __builtin_amdgcn_readfirstlane(grp.end);
+    int resume = valid ? groot : INT32_MAX;
+    int cur = groot;
+    while (cur < gend) {
+      const GNode nd = nodes[cur];
+      const float l = __int_as_float(nd.meta.w);
       const bool act = cur >= resume;
       const float r2 = dist2_exact(sub_exact(nd.com_m.x, me.x), sub_exact(nd.com_m.y, me.y),
                                    sub_exact(nd.com_m.z, me.z));
-      bool accept = act && open_accept(nd.hi_l.w, theta2, r2);
-      if (inside_test) {
-        const int level = nd.meta.w & 255;
+      bool accept, open;
+      if constexpr (!kInside) {
+        float t;
+        {
+#pragma clang fp contract(off)
+          t = act ? theta2 * r2 : __builtin_nanf("");
+        }
+        const float lhs = sq_exact(l);
+        accept = lhs < t;
+        open = lhs >= t;
+      } else {
+        accept = act && open_accept(l, theta2, r2);
+        const int level = root_exp - ilogbf(l);
         const uint64_t nk = keys[nd.meta.y];
         accept = accept && (((ki ^ nk) >> (3 * (kMaxLevel - level))) != 0ull);
+        open = act && !accept;
       }
       const uint64_t amask = __ballot(accept);
-      const uint64_t omask = __ballot(act && !accept);
+      const uint64_t omask = __ballot(open);
       if (accept) resume = nd.meta.x;
       if (amask) {
         if (tc == kTile) {
@@ -577,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
         cur = nd.meta.x;
         continue;
       }
-      if (!(nd.meta.w & kLeafBit)) {
+      if (nd.meta.z < 0) {  // internal
         ++cur;
         continue;
       }
@@ -598,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_gravity_bwd(
         // an opening lane whose own target is among these members clears
         // its bit in that member's entry (one lane per entry)
         const int rel = s - st;
-        if (act && !accept && rel >= 0 && rel < take) {
+        if (open && rel >= 0 && rel < take) {
           uint32_t *wd = (uint32_t *)&tile[tc + rel] + kGMaskWord + (hiword ? 1 : 0);
           *wd &= ~(1u << bitpos);
         }
@@ -1005,6 +1023,7 @@ hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_g
                               double *rr, float *g_pos, float *g_mass, hipStream_t s) {
   const int64_t m = all.n, nn = all.nnodes;
   if (m == 0 || nn == 0) return hipSuccess;
+  if (!all.gnodes) return hipErrorInvalidValue;
   const int64_t na = active ? n_act : m;
   if (gp.eps2 > 0.0f) {
     // fixed-point counters (two words per component, four components)
@@ -1014,21 +1033,23 @@ hipError_t launch_gravity_bwd(const Octree &all, const Groups &gs, int64_t max_g
     const int64_t nb = na > m ? na : m;
     const unsigned gb = nblk(nb) < (unsigned)kFxBoundBlocks ? nblk(nb) : (unsigned)kFxBoundBlocks;
     k_fx_bound<<<gb, kBlock, 0, s>>>(active, na, g_acc, g_pot, all.xm, m, mx);
-    if (max_groups > 0)
-      k_gravity_bwd<true>
-          <<<persistent_grid((const void *)k_gravity_bwd<true>, kBlock, max_groups), kBlock, 0,
-             s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
-                  gp.inside_test, g_acc, g_pot, gsrc, gnode, gsrc_fx, gnode_fx, mx, m, na);
+    if (max_groups > 0) {
+      auto kern = gp.inside_test ? k_gravity_bwd<true, true> : k_gravity_bwd<true, false>;
+      kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
+          all.gnodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G, g_acc, g_pot,
+          gsrc, gnode, gsrc_fx, gnode_fx, mx, m, na);
+    }
     k_fx_to_f4<<<nblk(m), kBlock, 0, s>>>(gsrc_fx, m, mx, gp.eps2, gp.G, m, na, gsrc);
     k_fx_to_f4<<<nblk(nn), kBlock, 0, s>>>(gnode_fx, nn, mx, gp.eps2, gp.G, m, na, gnode);
   } else {
     k_zero_f4<<<nblk(m), kBlock, 0, s>>>(gsrc, m);
     k_zero_f4<<<nblk(nn), kBlock, 0, s>>>(gnode, nn);
-    if (max_groups > 0)
-      k_gravity_bwd<false>
-          <<<persistent_grid((const void *)k_gravity_bwd<false>, kBlock, max_groups), kBlock, 0,
-             s>>>(all.nodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G,
-                  gp.inside_test, g_acc, g_pot, gsrc, gnode, nullptr, nullptr, nullptr, m, na);
+    if (max_groups > 0) {
+      auto kern = gp.inside_test ? k_gravity_bwd<false, true> : k_gravity_bwd<false, false>;
+      kern<<<persistent_grid((const void *)kern, kBlock, max_groups), kBlock, 0, s>>>(
+          all.gnodes, all.xm, all.keys, all.perm, gs, gp.theta2, gp.eps2, gp.G, g_acc, g_pot,
+          gsrc, gnode, nullptr, nullptr, nullptr, m, na);
+    }
   }
   k_push_init<<<nblk(nn), kBlock, 0, s>>>(gnode, all.mom, nn, pq, rr);
   for (int l = 0; l < all.max_level; ++l)

@@ -201,7 +201,7 @@ def test_hydro_backward(ctx, frac):
         check(f"hydro g_{k}", host(T[k].grad), ref[k], ref["S"][k])
 
 
-@pytest.mark.parametrize("theta,frac", [(0.5, 1.0), (0.5, 0.1), (0.0, 1.0)])
+@pytest.mark.parametrize("theta,frac", [(0.5, 1.0), (0.5, 0.1), (0.0, 1.0), (0.8, 0.3)])
 def test_gravity_backward(ctx, theta, frac):
     from paper_2003_10850_amd import ops
     import dataclasses
