@@ -122,9 +122,10 @@ int g3_ctx_stats(g3_ctx *ctx, int64_t *stats /* host [4] */, int32_t reset);
  * events on their stream just before and just after their interaction
  * kernel (k_density, k_hydro, k_gravity: not the group-table and prep
  * kernels before it), so that the pair spans that kernel alone also when
- * other streams keep the device busy. Later calls and calls made under
- * stream capture record nothing. capacity 0 turns timing off; at most
- * G3_TIMING_MAX. Creates the events (host call, no device wait). */
+ * other streams keep the device busy. Later calls, calls made under
+ * stream capture and calls that fail record nothing. capacity 0 turns
+ * timing off; at most G3_TIMING_MAX. Creates the events (host call, no
+ * device wait). */
 enum { G3_TIMING_MAX = 4096 };
 int g3_ctx_kernel_timing(g3_ctx *ctx, int32_t kind, int32_t capacity);
 /* The durations (ms, host [capacity]) of the kernels recorded since timing

@@ -93,7 +93,9 @@ int check_pending(g3_ctx *c) {
 
 // Records the start event of a timed interaction kernel on construction
 // and its stop event at stop(); does nothing unless timing is on for the
-// kind, the ring has room and the stream is not being captured.
+// kind, the ring has room and the stream is not being captured. A pair
+// counts only once stopped (a call whose launch failed leaves its start
+// event to be recorded again by the next call).
 struct KernelTimer {
   g3_ctx::Timing *tm = nullptr;
   hipStream_t s = nullptr;
@@ -994,8 +996,8 @@ int g3_density(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   KernelTimer timer(c, kTuneDensity, s);
   hipError_t e = launch_density(o, wk.gs, wk.max_groups, sp, solve_h ? 1 : 0, h, rho, drho_dh,
                                 omega, nngb, c->counters, s);
-  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_density");
+  timer.stop();
   c->err.clear();
   return G3_OK;
 }
@@ -1029,8 +1031,8 @@ int g3_hydro_force(g3_ctx *c, g3_tree *t, int64_t n_act, const int32_t *active,
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force prep");
   KernelTimer timer(c, kTuneHydro, s);
   e = launch_hydro(o, wk.gs, wk.max_groups, sp, acc, dudt, vsig, npairs, s);
-  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_hydro_force");
+  timer.stop();
   c->err.clear();
   return G3_OK;
 }
@@ -1055,8 +1057,8 @@ int g3_gravity(g3_ctx *c, const g3_tree *t, int64_t n_act, const int32_t *active
   if (st) return st;
   KernelTimer timer(c, kTuneGravity, s);
   hipError_t e = launch_gravity(o, wk.gs, wk.max_groups, grav_params(p, t), acc, pot, nterms, s);
-  timer.stop();
   if (e != hipSuccess) return hip_fail(c, e, "g3_gravity");
+  timer.stop();
   c->err.clear();
   return G3_OK;
 }

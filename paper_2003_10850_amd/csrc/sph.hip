@@ -884,7 +884,10 @@ __global__ __launch_bounds__(kBlock) void k_hydro(
   while (cur < grp.end) {
     const Node nd = nodes[cur];
     const float hm = kF64 ? walk_radius64(fmaxf(hi, nd.lo_h.w), slack) : fmaxf(hi, nd.lo_h.w);
-    const bool want = hi > 0.0f && box_dist2(xi, nd.lo_h, nd.hi_l) < sq_exact(hm);
+    // one compare: a lane without a target (hi = 0) tests against -1, which
+    // no squared distance is below
+    const float lim = hi > 0.0f ? sq_exact(hm) : -1.0f;
+    const bool want = box_dist2(xi, nd.lo_h, nd.hi_l) < lim;
     if (__ballot(want) == 0ull) {
       cur = nd.meta.x;
       continue;
