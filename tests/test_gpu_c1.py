@@ -2,8 +2,9 @@
 N = 2^21 particles (half gas) in 32 Plummer spheres + 20 % background,
 FP32, 295 neighbours, theta = 0.5, eps = 1e-3, every particle active, the
 library's default launch choices. One step as the benchmark runs it (build,
-cold-start h solve and density, hydro, gravity), checked against the FP64
-oracle on random samples of 4000 gas and 4000 particles of all species.
+cold-start h solve and density, hydro, and gravity on a second stream
+queued after the density and beside it and the hydro), checked against the
+FP64 oracle on random samples of 4000 gas and 4000 particles of all species.
 
 No oracle input comes from the GPU. The solved h and the density there are
 compared with the oracle's own solve (the density within 1e-5 plus its
@@ -44,16 +45,29 @@ def test_plain_workload_full_size_samples():
     ctx = ops.Context(torch.device("cuda", 0))
     pos, mass, typ = dev_t(pos32), dev_t(m32), dev_t(w.type)
     tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
-    tree.build(pos, mass, typ)  # the benchmark rebuilds in place every step
-    d = ops.density(tree, h=torch.zeros(w.n, device="cuda:0"))
-    assert ctx.nonconverged(reset=True) == 0
     hm = inputs.model_smoothing(w).astype(np.float32)
-    dm = ops.density(tree, h=dev_t(hm), solve_h=False)
     rm = inputs.model_gas_density(w).astype(np.float32)
     om = np.ones(w.n, np.float32)
-    hy = ops.hydro_force(tree, dev_t(vel32), dev_t(u32), dev_t(hm), dev_t(rm), dev_t(om))
-    g = ops.gravity(tree)
+    hm_d, rm_d, om_d, vel_d, u_d = dev_t(hm), dev_t(rm), dev_t(om), dev_t(vel32), dev_t(u32)
+    h0 = torch.zeros(w.n, device="cuda:0")
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()  # default priority
+    tree.build(pos, mass, typ)  # the benchmark rebuilds in place every step
+    built = torch.cuda.Event()
+    built.record(main)
+    d = ops.density(tree, h=h0)
+    # gravity as the benchmark schedules it: on a second stream, queued
+    # after the density (behind a short spin) and beside it and the hydro
+    side.wait_event(built)
+    with torch.cuda.stream(side):
+        if hasattr(torch.cuda, "_sleep"):
+            torch.cuda._sleep(200_000)
+        g = ops.gravity(tree)
+    dm = ops.density(tree, h=hm_d, solve_h=False)
+    hy = ops.hydro_force(tree, vel_d, u_d, hm_d, rm_d, om_d)
+    main.wait_stream(side)
     torch.cuda.synchronize()
+    assert ctx.nonconverged(reset=True) == 0
     h, rho = host(d["h"]), host(d["rho"])
     rho_m, nngb_m = host(dm["rho"]), host(dm["nngb"])
     acc, npairs = host(hy["acc"]), host(hy["npairs"])
