@@ -829,8 +829,8 @@ def main() -> int:
         print(json.dumps(summarize_pmc(*args.summarize_pmc), indent=1))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the interaction phase is not sharded across GPUs here)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
+                          "(the interaction phase is not sharded across GPUs)"}))
         return 2
 
     import torch
