@@ -36,6 +36,14 @@ sys.path.insert(0, ROOT)
 FLOP_DENSITY = 36   # rho and drho/dh of one pair in the support
 FLOP_HYDRO = 90     # pressure + viscosity acceleration, du/dt, signal speed
 FLOP_GRAVITY = 20   # softened monopole or particle term, acc + potential
+# the modules around the path (same convention)
+FLOP_CONDUCTION = 30        # symmetric test, F(r, h_i) and F(r, h_j), the pair's rate
+FLOP_VELGRAD = 45           # distance, F(q), the pair's gradient, divergence and curl terms
+FLOP_HYDRO_SWITCHES = 104   # the hydro pair, the pair's viscosity strength, artificial conduction
+# the integration leg's largest step: a particle at the sphere's typical
+# speed (about 5) moves about half the central smoothing length in it, so
+# the refitted octree stays tight through a system step
+DT_INT = 2.5e-4
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 # a short spin (GPU clock cycles, about 0.1 ms) on the gravity stream before
 # its call, so that the density beside it is dispatched first
@@ -666,6 +674,113 @@ def run_differentiation(dev, steps: int, warmup: int, n: int = 1 << 20, seed: in
     }
 
 
+def run_extras(dev, steps: int, warmup: int, n: int = 1 << 21, n_int: int = 1 << 20) -> dict:
+    """The modules around the path. Thermal conduction (kappa = 1e-3 u^(5/2))
+    and the improved-SPH switches (velocity gradients, the viscosity-strength
+    step, the hydro force with per-particle strengths and artificial
+    conduction) on the plain workload, at the fields of its own density
+    solve; and the time integration of a 2^20-body Plummer sphere in
+    equilibrium (half gas, four time bins). Each call is timed with HIP
+    events around it on its stream (its prep and group-table kernels
+    included); interactions are the kernels' own pair counts."""
+    import torch
+    from paper_2003_10850_amd import inputs, ops
+
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    w = inputs.plummer(n=n, n_spheres=32, seed=1)
+    pos32, vel32, m32, u32 = w.as_f32()
+    pos, vel, mass, u, typ = T(pos32), T(vel32), T(m32), T(u32), T(w.type)
+    ctx = ops.Context(dev)
+    tree = ops.Tree(ctx, pos, mass, typ, tuple(w.box), w.params)
+    d = ops.density(tree)
+    h, rho, om = d["h"].clone(), d["rho"].clone(), d["omega"].clone()
+    gas = T(w.type == 0)
+    f32 = dict(dtype=torch.float32, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+
+    def timed(f):
+        for _ in range(max(warmup, 1)):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def entry(ms, pairs, flop):
+        achieved = flop * pairs / (ms * 1e-3) / 1e12
+        return {"ms_per_call": ms, "interactions": pairs, "value": pairs / (ms * 1e-3),
+                "unit": "interactions/s",
+                "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                             "flop_per_interaction": flop}}
+
+    oc = dict(dudt=torch.zeros(n, **f32), npairs=torch.zeros(n, **i32))
+    ms_c = timed(lambda: ops.conduction(tree, u, h, rho, 1e-3, 2.5, out=oc))
+    cond = entry(ms_c, int(oc["npairs"][gas].sum()), FLOP_CONDUCTION)
+    sw = inputs.SwitchParams()
+    og = dict(div=torch.zeros(n, **f32), curl=torch.zeros(n, 3, **f32))
+    ms_v = timed(lambda: ops.velocity_gradients(tree, vel, h, rho, om, out=og))
+    # the same gather as the density at the same h: its neighbour count
+    velgrad = entry(ms_v, int(d["nngb"][gas].sum()), FLOP_VELGRAD)
+    alpha = torch.full((n,), 0.1, **f32)
+    bal = torch.zeros(n, **f32)
+    ms_a = timed(lambda: ops.viscosity_switch(ctx, sw, w.params, 1e-4, u, h, og["div"],
+                                              og["curl"], alpha=alpha, balsara=bal))
+    oh = dict(acc=torch.zeros(n, 3, **f32), dudt=torch.zeros(n, **f32),
+              vsig=torch.zeros(n, **f32), npairs=torch.zeros(n, **i32))
+    ms_h = timed(lambda: ops.hydro_force_switches(tree, vel, u, h, rho, om, sw, alpha=alpha,
+                                                  balsara=bal, out=oh))
+    hydro_sw = entry(ms_h, int(oh["npairs"][gas].sum()), FLOP_HYDRO_SWITCHES)
+    print(f"bench: extras conduction {ms_c:.3f} ms, velocity gradients {ms_v:.3f} ms, "
+          f"switch step {ms_a:.3f} ms, hydro with switches {ms_h:.3f} ms", file=sys.stderr,
+          flush=True)
+    tree.close()
+    del oc, og, oh
+
+    wi = inputs.plummer_equilibrium(n=n_int, gas_fraction=0.5, seed=5)
+    gi = ops.Integrator(ctx, T(wi.pos.astype(np.float32)), T(wi.vel.astype(np.float32)),
+                        T(wi.mass.astype(np.float32)), T(wi.u.astype(np.float32)), T(wi.type),
+                        tuple(wi.box), wi.params, dt_max=DT_INT, bin_depth=3)
+    gi.start()
+    ticks = torch.zeros(8, dtype=torch.int64, device=dev)
+    for _ in range(max(warmup, 1)):
+        gi.system_step(ticks)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tot = torch.zeros(8, dtype=torch.int64, device=dev)
+    e0.record()
+    for _ in range(steps):
+        gi.system_step(ticks)
+        tot += ticks
+    e1.record()
+    torch.cuda.synchronize()
+    ms_i = e0.elapsed_time(e1) / steps
+    per_tick = (tot // steps).cpu().tolist()
+    bins = np.bincount(gi.bin.cpu().numpy(), minlength=4).tolist()
+    print(f"bench: extras system step {ms_i:.3f} ms, active per tick {per_tick}", file=sys.stderr,
+          flush=True)
+    return {
+        "workload": f"{w.name}: the plain workload at its own density solve (conduction "
+                    f"kappa = 1e-3 u^(5/2); switches with alpha = 0.1, dt = 1e-4); and "
+                    f"{wi.name}: a Plummer sphere in equilibrium, N={n_int}, half gas, "
+                    f"KDK leapfrog with 4 time bins (dt_max = {DT_INT:g})",
+        "conduction": cond,
+        "velocity_gradients": velgrad,
+        "viscosity_switch_ms": ms_a,
+        "hydro_force_switches": hydro_sw,
+        "integration": {"ms_per_system_step": ms_i, "ticks": 8,
+                        "active_per_tick": per_tick, "bins": bins,
+                        "value": sum(per_tick) / (ms_i * 1e-3),
+                        "unit": "active particle updates/s",
+                        "step": "build; per tick: drift, refit of both octrees, density (h solve), "
+                                "hydro and gravity of the tick's active set, kicks"},
+    }
+
+
 def run_precision(dev, steps: int, warmup: int, n: int = 20_000_000, seed: int = 3):
     """The precision workload: N = 2e7 particles clustered as the plain
     workload but in 256 Plummer spheres, FP64 stored positions, on the
@@ -812,7 +927,9 @@ def main() -> int:
                          "in kernel traces of this command); default launch choices otherwise")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 2e7-particle mixed-precision measurement")
-    ap.add_argument("--only", choices=("batched", "differentiation", "precision"),
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the conduction, switches and integration leg")
+    ap.add_argument("--only", choices=("batched", "differentiation", "precision", "extras"),
                     help="run just this leg and print its object (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
@@ -840,7 +957,7 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     if args.only:
         leg = {"batched": run_batched, "differentiation": run_differentiation,
-               "precision": run_precision}[args.only]
+               "precision": run_precision, "extras": run_extras}[args.only]
         res = leg(dev, args.steps, args.warmup)
         if isinstance(res, tuple):
             res = res[1]
@@ -1042,6 +1159,8 @@ def main() -> int:
     if not args.no_precision:
         checks["precision"], line["precision"] = run_precision(dev, args.steps, args.warmup)
         line["precision"]["max_err"] = None
+    if not args.no_extras:
+        line["extras"] = run_extras(dev, args.steps, args.warmup)
     if args.copy_calibration:
         copy_calibration(dev)
     if not args.no_cpu_baseline:
